@@ -1,0 +1,244 @@
+"""CPU oracle of the two-material finite-volume step (TEST INFRASTRUCTURE).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It is the plain FP64 reference the GPU library is
+checked against and shares no code with it.
+
+Contents
+--------
+* ``m2c_oracle.c`` -- the scheme in plain C (built into ``liboracle.so``),
+  wrapped here with ctypes: :class:`OracleSim` and point functions.
+* ``exact_riemann.py`` -- an independent derivative-free (bisection) solver of
+  the two-material stiffened-gas Riemann problem in high precision, plus the
+  self-similar exact solution used to pin the scheme.
+* ``mlp_ref.py`` -- FP64 forward/backward of the star-pressure MLP.
+
+Parity status: the phase-update rule is a reading of an under-specified step
+and is "parity unpinned" beyond the translation and self-consistency tests;
+every other part is pinned by the tests under ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "m2c_oracle.c")
+
+OK, ERR_ARG, ERR_NONPHYSICAL, ERR_RIEMANN, ERR_NOMEM = 0, -1, -2, -3, -7
+
+
+def build(force: bool = True, extra_flags=()):
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA)."""
+    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(_SRC):
+        return _SO
+    tmp = _SO + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+           *extra_flags, "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def build_variant(path: str, defines=()):
+    """Build a separate copy of the oracle (e.g. with a planted mistake for a
+    test that shows the pins catch it)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+           *[f"-D{d}" for d in defines], "-o", path, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
+
+
+class Cfg(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("gamma", C.c_double * 2), ("pc", C.c_double * 2),
+                ("bc", C.c_int32 * 6), ("alpha", C.c_double), ("rk_order", C.c_int32),
+                ("cfl", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double),
+                ("maxit", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt_last", C.c_double),
+                ("iface_faces_last", C.c_int64), ("newton_iters", C.c_int64),
+                ("riemann_solves", C.c_int64), ("bisection_fallbacks", C.c_int64),
+                ("flips", C.c_int64), ("orphans", C.c_int64), ("err_cell", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = np.ctypeslib.ndpointer
+_D = _P(dtype=np.float64, flags="C_CONTIGUOUS")
+_U8 = _P(dtype=np.uint8, flags="C_CONTIGUOUS")
+_I32 = _P(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def load(path: str | None = None):
+    path = path or _SO
+    if path == _SO and not os.path.exists(_SO):
+        build()
+    lib = C.CDLL(path)
+    lib.ora_create.restype = C.c_void_p
+    lib.ora_create.argtypes = [C.POINTER(Cfg)]
+    lib.ora_destroy.argtypes = [C.c_void_p]
+    lib.ora_set_prim.argtypes = [C.c_void_p, _D]
+    lib.ora_get_prim.argtypes = [C.c_void_p, _D, C.c_void_p]
+    lib.ora_set_cons.argtypes = [C.c_void_p, _D]
+    lib.ora_get_cons.argtypes = [C.c_void_p, _D]
+    lib.ora_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.ora_step_dt.argtypes = [C.c_void_p, C.c_int32, C.c_double]
+    lib.ora_dt.restype = C.c_double
+    lib.ora_dt.argtypes = [C.c_void_p]
+    lib.ora_get_stats.argtypes = [C.c_void_p, C.POINTER(Stats)]
+    lib.ora_interface_faces.restype = C.c_int64
+    lib.ora_interface_faces.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+    lib.ora_prim_to_cons.argtypes = [_D, C.c_double, C.c_double, _D]
+    lib.ora_cons_to_prim.argtypes = [_D, C.c_double, C.c_double, _D]
+    lib.ora_sound_speed.restype = C.c_double
+    lib.ora_sound_speed.argtypes = [C.c_double] * 4
+    lib.ora_mc_slope.restype = C.c_double
+    lib.ora_mc_slope.argtypes = [C.c_double, C.c_double, C.c_double]
+    lib.ora_hllc.argtypes = [_D, _D, C.c_double, C.c_double, _D]
+    lib.ora_riemann.restype = C.c_int
+    lib.ora_riemann.argtypes = [_D, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32)]
+    lib.ora_ls_derivative.restype = C.c_double
+    lib.ora_ls_derivative.argtypes = [_D, C.c_double, C.c_double]
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50):
+    c = Cfg()
+    c.nx, c.ny, c.nz = problem.n
+    for d in range(3):
+        c.lo[d] = problem.lo[d]
+        c.hi[d] = problem.hi[d]
+    for m in range(2):
+        c.gamma[m] = problem.gamma[m]
+        c.pc[m] = problem.pc[m]
+    for f in range(6):
+        c.bc[f] = problem.bc[f]
+    c.alpha = alpha
+    c.rk_order = rk_order
+    c.cfl = problem.cfl
+    c.dt_fixed = problem.dt_fixed
+    c.rtol = rtol
+    c.maxit = maxit
+    return c
+
+
+class OracleSim:
+    """The oracle on one grid."""
+
+    def __init__(self, problem, lib_handle=None, **kw):
+        self.lib = lib_handle or lib()
+        self.problem = problem
+        self.cfg = make_cfg(problem, **kw)
+        self.h = self.lib.ora_create(C.byref(self.cfg))
+        if not self.h:
+            raise MemoryError("ora_create failed")
+        self.N = problem.ncells
+        if problem.prim is not None:
+            rc = self.set_prim(problem.prim)
+            if rc != OK:
+                raise ValueError(f"ora_set_prim rc={rc}")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.ora_destroy(self.h)
+            self.h = None
+
+    def set_prim(self, prim):
+        return self.lib.ora_set_prim(self.h, np.ascontiguousarray(prim, dtype=np.float64).reshape(-1))
+
+    def set_cons(self, w6):
+        return self.lib.ora_set_cons(self.h, np.ascontiguousarray(w6, dtype=np.float64).reshape(-1))
+
+    def prim(self):
+        out = np.empty(6 * self.N)
+        chi = np.empty(self.N, dtype=np.uint8)
+        self.lib.ora_get_prim(self.h, out, chi.ctypes.data)
+        nx, ny, nz = self.problem.n
+        return out.reshape(6, nz, ny, nx), chi.reshape(nz, ny, nx)
+
+    def cons(self):
+        out = np.empty(6 * self.N)
+        self.lib.ora_get_cons(self.h, out)
+        nx, ny, nz = self.problem.n
+        return out.reshape(6, nz, ny, nx)
+
+    def step(self, n=1):
+        return self.lib.ora_step(self.h, n)
+
+    def step_dt(self, n, dt):
+        return self.lib.ora_step_dt(self.h, n, dt)
+
+    def dt(self):
+        return self.lib.ora_dt(self.h)
+
+    def stats(self):
+        s = Stats()
+        self.lib.ora_get_stats(self.h, C.byref(s))
+        return s.as_dict()
+
+    def interface_faces(self):
+        n = self.lib.ora_interface_faces(self.h, None, 0)
+        out = np.empty(max(n, 1), dtype=np.int32)
+        self.lib.ora_interface_faces(self.h, out.ctypes.data, n)
+        return out[:n]
+
+
+# ---- point-function conveniences ------------------------------------------
+
+def hllc(qL, qR, gamma, pc):
+    F = np.empty(5)
+    lib().ora_hllc(np.asarray(qL, dtype=np.float64), np.asarray(qR, dtype=np.float64),
+                   gamma, pc, F)
+    return F
+
+
+def riemann(inp, eos, rtol=1e-12, maxit=50):
+    """Returns (rc, (p*, u*, rho*_L, rho*_R), iterations)."""
+    out = np.empty(4)
+    it = C.c_int32(0)
+    rc = lib().ora_riemann(np.asarray(inp, dtype=np.float64), np.asarray(eos, dtype=np.float64),
+                           rtol, maxit, out, C.byref(it))
+    return rc, out, it.value
+
+
+def sound_speed(rho, p, gamma, pc):
+    return lib().ora_sound_speed(rho, p, gamma, pc)
+
+
+def mc_slope(dm, dp, alpha=1.2):
+    return lib().ora_mc_slope(dm, dp, alpha)
+
+
+def prim_to_cons(q, gamma, pc):
+    w = np.empty(5)
+    lib().ora_prim_to_cons(np.asarray(q, dtype=np.float64), gamma, pc, w)
+    return w
+
+
+def cons_to_prim(w, gamma, pc):
+    q = np.empty(5)
+    lib().ora_cons_to_prim(np.asarray(w, dtype=np.float64), gamma, pc, q)
+    return q
+
+
+def ls_derivative(f5, v, h):
+    return lib().ora_ls_derivative(np.asarray(f5, dtype=np.float64), v, h)

@@ -1,0 +1,104 @@
+/*
+ * m2c_oracle.h -- plain FP64 CPU oracle of the two-material finite-volume
+ * time step (TEST INFRASTRUCTURE ONLY).
+ *
+ * This is the slow, obviously-correct reference that the GPU library is
+ * checked against.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load it; the product path never does.  It shares no
+ * code, header, table or constant with the GPU library.
+ *
+ * What it computes (one time step, paper sections "Spatial discretization of
+ * governing equations", "Time integration", "Level set method" and the step
+ * outline in "Code structure"):
+ *   cell-centred finite volumes on a uniform Cartesian grid (eq.
+ *   NS_discretized, inviscid, no source); primitive-variable MUSCL with the MC
+ *   limiter (appendix "Slope limiters", eqs. theta/AB); HLLC at faces inside
+ *   one material (appendix "HLLC flux"); FIVER at faces whose two cells hold
+ *   different materials: an exact two-material Riemann problem (eq.
+ *   1DRiemannProblem) whose star states feed one one-sided HLLC flux per side;
+ *   level-set advection (eq. levelset) with third-order upwind differences;
+ *   TVD Runge-Kutta in time with a CFL-based dt; and the phase update for
+ *   cells whose level-set sign flipped.  Stiffened gas per material:
+ *   p = (gamma-1) rho e - gamma p_c (eq. NASG_EOS with b = e_c = 0).
+ *
+ * Arrays are structure-of-arrays, x fastest: cell (i,j,k) is at
+ * i + nx*(j + ny*k).  Material 1 occupies phi < 0.
+ */
+#ifndef M2C_ORACLE_H
+#define M2C_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORA_OK = 0, ORA_ERR_ARG = -1, ORA_ERR_NONPHYSICAL = -2, ORA_ERR_RIEMANN = -3,
+       ORA_ERR_NOMEM = -7 };
+enum { ORA_BC_TRANSMISSIVE = 0, ORA_BC_WALL = 1, ORA_BC_PERIODIC = 2 };
+
+typedef struct {
+    int32_t nx, ny, nz;
+    double lo[3], hi[3];
+    double gamma[2], pc[2];   /* material 0 (phi >= 0), material 1 (phi < 0) */
+    int32_t bc[6];            /* -x,+x,-y,+y,-z,+z */
+    double alpha;             /* MC limiter parameter (paper default 1.2)       */
+    int32_t rk_order;         /* 1 forward Euler, 2 TVD-RK2, 3 TVD-RK3            */
+    double cfl, dt_fixed;     /* dt_fixed > 0 overrides the CFL rule             */
+    double rtol;              /* Newton stopping tolerance on p*                 */
+    int32_t maxit;            /* Newton iterations before bisection              */
+} ora_cfg;
+
+typedef struct {
+    int64_t steps;
+    double t, dt_last;
+    int64_t iface_faces_last;   /* interface faces in the last step            */
+    int64_t newton_iters;       /* summed over all solves                      */
+    int64_t riemann_solves;
+    int64_t bisection_fallbacks;
+    int64_t flips, orphans;     /* phase update counters (all steps)           */
+    int64_t err_cell;           /* first failing cell (or -1)                  */
+} ora_stats;
+
+typedef struct ora_sim ora_sim;
+
+ora_sim* ora_create(const ora_cfg* cfg);
+void     ora_destroy(ora_sim* s);
+/* prim6 = [rho,u,v,w,p,phi][N]; material ids follow from phi. */
+int      ora_set_prim(ora_sim* s, const double* prim6);
+int      ora_get_prim(const ora_sim* s, double* prim6, uint8_t* chi /* nullable */);
+/* w6 = [rho, rho u, rho v, rho w, rho E, phi][N] (exact checkpoint). */
+int      ora_set_cons(ora_sim* s, const double* w6);
+int      ora_get_cons(const ora_sim* s, double* w6);
+int      ora_step(ora_sim* s, int32_t nsteps);
+/* Same as ora_step but with dt imposed for every step (for sampled checks). */
+int      ora_step_dt(ora_sim* s, int32_t nsteps, double dt);
+double   ora_dt(const ora_sim* s);
+void     ora_get_stats(const ora_sim* s, ora_stats* st);
+/* Interface faces of the current material field, ascending face ids
+ * f = 3*c + d (face between cell c and its +d neighbour).  Returns count;
+ * writes at most cap ids. */
+int64_t  ora_interface_faces(const ora_sim* s, int32_t* out, int64_t cap);
+
+/* ---- point functions ---------------------------------------------------- */
+/* Stiffened-gas primitive -> conservative and back (one cell). */
+void ora_prim_to_cons(const double* q5, double gamma, double pc, double* w5);
+void ora_cons_to_prim(const double* w5, double gamma, double pc, double* q5);
+/* Speed of sound of a stiffened-gas state. */
+double ora_sound_speed(double rho, double p, double gamma, double pc);
+/* MC-limited slope from the backward and forward differences. */
+double ora_mc_slope(double dminus, double dplus, double alpha);
+/* HLLC flux along +x in the face frame: q = (rho, u_n, v_t1, v_t2, p). */
+void ora_hllc(const double* qL, const double* qR, double gamma, double pc, double* F5);
+/* Exact two-material stiffened-gas Riemann problem.
+ * in = (rho_L, u_L, p_L, rho_R, u_R, p_R), eos = (gamma_L, pc_L, gamma_R, pc_R)
+ * out = (p*, u*, rho*_L, rho*_R); returns ORA_OK or ORA_ERR_RIEMANN (vacuum). */
+int  ora_riemann(const double* in, const double* eos, double rtol, int32_t maxit,
+                 double* out, int32_t* iters);
+/* Third-order upwind-biased derivative of phi at the centre of a 5-point
+ * stencil f[0..4] = phi_{i-2..i+2} for advection speed v. */
+double ora_ls_derivative(const double* f, double v, double h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
