@@ -1,0 +1,125 @@
+"""Throughput of the two-material finite-volume step on one MI355X.
+
+One benchmark step is one full time step of the hot path (CFL time step,
+interface compaction, two TVD-RK2 stages each with FIVER interface fluxes
+and the fused bulk stage kernel, phase update) on the 128^3 shock-bubble
+workload: unit box, air bubble of radius 0.15 at a seed-jittered centre in
+water at 1e5 Pa, planar water shock of 1e8 Pa at x = 0.1, transmissive
+boundaries, CFL 0.4.  The state is resident in HBM before the timed region.
+
+Prints one JSON line; see ``--help``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Compulsory HBM bytes per cell of the fused stage kernel (FP64 SoA state of
+# 5 conserved fields + phi, uint8 material id): stage 1 reads W^n, phi, chi
+# (49 B) and writes W(1), phi (48 B); stage 2 also reads W^n, phi (48 B).
+BYTES_STAGE1, BYTES_STAGE2 = 97, 145
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=128, help="grid edge (default 128)")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4,
+                    help="oracle steps timed for the CPU baseline (bounded sample)")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem, steps):
+    import oracle
+
+    oracle.build(force=False)
+    s = oracle.OracleSim(problem)
+    t0 = time.perf_counter()
+    rc = s.step(steps)
+    t = time.perf_counter() - t0
+    assert rc == 0
+    N = problem.ncells
+    return {"value": N * steps * 2 / t, "unit": "cell-updates/s per RK stage", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the same {problem.n[0]}x{problem.n[1]}x{problem.n[2]} "
+                      f"shock-bubble run, single-threaded C oracle ({t:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2508_16387_amd as m2c
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    p = W.shock_bubble(args.seed, n=args.n)
+    prec = m2c.M2C_PREC_MIXED if args.precision == "mixed" else m2c.M2C_PREC_FP64
+    sim = m2c.Sim(m2c.config_for(p, precision=prec))
+    stream = torch.cuda.current_stream()
+    sim.set_stream(stream)
+    sim.set_state(p.prim)
+    if args.warmup:
+        sim.step(args.warmup)
+        sim.set_state(p.prim)          # time steps 1..K of the workload
+    sim.reset_stats()
+    sim.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    st = sim.stats()
+    N = p.ncells
+    value = N * args.steps * 2 / T
+
+    stage_ms = st["ms_stage"] / max(st["stage_launches"], 1)
+    bytes_per_launch = N * (BYTES_STAGE1 + BYTES_STAGE2) / 2
+    achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
+    out = {
+        "metric": "cell-updates/s per RK stage",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == m2c.M2C_PREC_FP64 else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"shock_bubble_{args.n}^3", "grid": [args.n] * 3, "steps": args.steps,
+                   "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl, "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "fiver": {"solves": st["riemann_solves"], "ms": st["ms_fiver"],
+                  "solves_per_s": st["riemann_solves"] / max(st["ms_fiver"] * 1e-3, 1e-12),
+                  "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1)},
+        "time_split_ms": {"stage": st["ms_stage"], "fiver": st["ms_fiver"], "other": st["ms_other"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

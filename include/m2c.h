@@ -1,0 +1,195 @@
+/*
+ * m2c.h -- C ABI of the MI355X (gfx950) two-material finite-volume library.
+ *
+ * The library advances the 3D compressible Euler equations for two
+ * stiffened-gas materials separated by one level set on a uniform Cartesian
+ * grid, following the method of M2C (arXiv 2508.16387):
+ *   - cell-centred finite volumes (eq. NS_discretized, inviscid, no source);
+ *   - MUSCL reconstruction of the primitive variables with the MC limiter
+ *     (appendix "Slope limiters", eqs. theta and AB);
+ *   - HLLC fluxes at faces inside one material (appendix "HLLC flux");
+ *   - FIVER at faces between materials: the exact two-material Riemann
+ *     problem along the face normal (eq. 1DRiemannProblem) gives star
+ *     states that feed one one-sided flux per side (section "Spatial
+ *     discretization of governing equations");
+ *   - level-set advection (eq. levelset) by third-order upwind differences
+ *     (section "Level set method");
+ *   - TVD Runge-Kutta time integration with a CFL-based time step
+ *     (section "Time integration");
+ *   - the phase update of the time-step outline (step 6, section "Code
+ *     structure") for cells whose level-set sign changed.
+ *
+ * Conventions shared by every call
+ *   - Arrays are structure-of-arrays, x fastest: cell (i,j,k) has index
+ *     c = i + nx*(j + ny*k); a field of N = nx*ny*nz cells is N contiguous
+ *     values, and "[m][N]" means m such fields back to back.  No ghost cells
+ *     cross the ABI.
+ *   - Material 1 occupies phi < 0, material 0 phi >= 0.  Material ids are
+ *     always derived from phi, never passed in.
+ *   - Stiffened gas per material m: p = (gamma_m - 1) rho e - gamma_m pc_m
+ *     (eq. NASG_EOS with b = e_c = 0).
+ *   - Ownership: the caller owns every pointer it passes; the library copies
+ *     what it needs during the call and keeps no caller pointer.  Calls that
+ *     take device pointers work on the context's stream (m2c_set_stream) and
+ *     the memory must stay valid until that stream has finished the call.
+ *   - Errors: every call returns an m2c_status; nothing throws across the
+ *     ABI.  m2c_last_error() gives a message for the last failure of a
+ *     context.  A context is not thread-safe; distinct contexts are
+ *     independent.
+ */
+#ifndef M2C_H
+#define M2C_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum m2c_status {
+    M2C_OK = 0,
+    M2C_ERR_ARG = -1,           /* invalid argument or configuration           */
+    M2C_ERR_NONPHYSICAL = -2,   /* rho <= 0, p + p_c <= 0 or non-finite value  */
+    M2C_ERR_RIEMANN = -3,       /* interface Riemann problem with no admissible
+                                   star pressure (a vacuum would open)          */
+    M2C_ERR_DEVICE = -4,        /* HIP runtime failure                          */
+    M2C_ERR_STATE = -5,         /* call out of order (e.g. step before set)     */
+    M2C_ERR_UNIMPLEMENTED = -6,
+    M2C_ERR_NOMEM = -7
+} m2c_status;
+
+enum { M2C_BC_TRANSMISSIVE = 0,  /* zero-gradient copy of the boundary cell    */
+       M2C_BC_WALL = 1,          /* mirror image, normal velocity reversed      */
+       M2C_BC_PERIODIC = 2 };
+enum { M2C_PREC_FP64 = 0,        /* everything in FP64                          */
+       M2C_PREC_MIXED = 1 };     /* FP32 reconstruction + HLLC at single-material
+                                    faces; FP64 EOS inversion, FIVER, residual
+                                    accumulation, level set and time step      */
+enum { M2C_GUESS_ACOUSTIC = 0,   /* linearised (acoustic) star-pressure guess   */
+       M2C_GUESS_MLP = 1 };      /* learned guess, judged against the acoustic  */
+
+/* Problem and method parameters (the "Mesh", "Equations", "BoundaryCondition",
+ * "Space", "Time" and "ExactRiemannSolution" input classes of the paper's
+ * input-file table). */
+typedef struct m2c_config {
+    uint32_t struct_size;       /* = sizeof(m2c_config)                        */
+    int32_t nx, ny, nz;         /* cells per axis (>= 1)                       */
+    double lo[3], hi[3];        /* domain box                                  */
+    double gamma[2], pc[2];     /* stiffened gas of material 0 and 1           */
+    int32_t bc[6];              /* -x,+x,-y,+y,-z,+z; periodic must pair up    */
+    double limiter_alpha;       /* MC parameter alpha (paper default 1.2)      */
+    int32_t rk_order;           /* 2 (TVD-RK2); other orders: M2C_ERR_UNIMPLEMENTED */
+    double cfl;                 /* dt = cfl / max_i sum_d (|V_d|+c)/h_d        */
+    double dt_fixed;            /* > 0: constant dt instead of the CFL rule    */
+    int32_t precision;          /* M2C_PREC_*                                  */
+    int32_t guess;              /* M2C_GUESS_*                                 */
+    double riemann_rtol;        /* Newton stop: |dp| <= rtol (p - p_lo)        */
+    int32_t riemann_maxit;      /* Newton steps before the bisection fallback  */
+    int32_t tile_x, tile_y, tile_z;  /* stage-kernel tile; 0 = library choice  */
+} m2c_config;
+
+/* Counters and timings since m2c_create (or the last m2c_reset_stats). */
+typedef struct m2c_stats {
+    int64_t steps;              /* completed steps                              */
+    double t;                   /* simulated time                               */
+    double dt_last;             /* dt of the last completed step                */
+    int64_t iface_faces_last;   /* interface faces (Riemann problems per stage)
+                                   of the last step                             */
+    int64_t riemann_solves;     /* interface Riemann problems solved            */
+    int64_t newton_iters;       /* Newton steps summed over all solves          */
+    int64_t bisection_fallbacks;
+    int64_t flips;              /* cells whose material changed                 */
+    int64_t orphans;            /* flipped cells without a neighbour of their
+                                   new material (state kept, re-encoded)        */
+    int64_t mlp_fallbacks;      /* learned guesses rejected by the judge        */
+    int32_t err_code;           /* m2c_status of the failing step, 0 if none    */
+    int32_t pad0;
+    int64_t err_cell;           /* first cell (or face/3) found failing, -1     */
+    double ms_stage;            /* device time of the bulk stage kernels        */
+    double ms_fiver;            /* device time of the interface Riemann kernel  */
+    double ms_other;            /* device time of every other kernel of a step  */
+    int64_t stage_launches;     /* bulk stage-kernel launches timed             */
+    int64_t fiver_launches;
+} m2c_stats;
+
+typedef struct m2c_ctx m2c_ctx;
+
+/* Fill a configuration with the defaults: 1 cell, unit box, air/water,
+ * transmissive, alpha 1.2, RK2, CFL 0.5, FP64, acoustic guess, rtol 1e-12,
+ * maxit 50, library-chosen tiles. */
+void m2c_config_default(m2c_config* c);
+
+/* Validate the configuration, select device 'current' and allocate every
+ * device buffer of the context (about 160 B per cell).  *out is NULL on
+ * failure. */
+int m2c_create(const m2c_config* c, m2c_ctx** out);
+void m2c_destroy(m2c_ctx* ctx);
+const char* m2c_last_error(const m2c_ctx* ctx);
+const char* m2c_strerror(int status);
+
+/* Use a caller stream (hipStream_t, e.g. a torch stream) for every later
+ * launch of the context; NULL selects the default stream. */
+int m2c_set_stream(m2c_ctx* ctx, void* hip_stream);
+
+/* Initial / replacement state from host primitives prim6 = [rho,u,v,w,p,phi][N].
+ * Rejects rho <= 0, p + p_c <= 0 and non-finite values (M2C_ERR_NONPHYSICAL,
+ * err_cell set) without changing the context's state.  Synchronous. */
+int m2c_set_state(m2c_ctx* ctx, const double* prim6);
+/* Same from device memory (6N doubles); asynchronous on the context stream
+ * except for the validity check, which synchronises. */
+int m2c_set_state_device(m2c_ctx* ctx, const double* dprim6);
+
+/* Current state as host primitives [rho,u,v,w,p,phi][N]; id (nullable)
+ * receives the N material ids.  Synchronous. */
+int m2c_get_state(m2c_ctx* ctx, double* prim6, uint8_t* id);
+int m2c_get_state_device(m2c_ctx* ctx, double* dprim6);
+
+/* Conservative state [rho, rho u, rho v, rho w, rho E, phi][N] -- a bit-exact
+ * checkpoint (primitive <-> conservative is not a bit-exact round trip). */
+int m2c_get_conserved(m2c_ctx* ctx, double* w6);
+int m2c_set_conserved(m2c_ctx* ctx, const double* w6);
+
+/* Advance nsteps full time steps (each: CFL dt, RK stages, phase update).
+ * Transactional per step: on M2C_ERR_NONPHYSICAL or M2C_ERR_RIEMANN the
+ * state is the one after the last completed step and the error is in
+ * m2c_get_stats.  *t_out (nullable) receives the simulated time.  Returns
+ * after the device has finished. */
+int m2c_step(m2c_ctx* ctx, int32_t nsteps, double* t_out);
+/* Same, but with dt imposed for every step instead of the CFL rule. */
+int m2c_step_dt(m2c_ctx* ctx, int32_t nsteps, double dt, double* t_out);
+
+int m2c_get_stats(m2c_ctx* ctx, m2c_stats* s);
+int m2c_reset_stats(m2c_ctx* ctx);
+/* 1: time kernel classes with HIP events on the context stream (adds one
+ * synchronisation per step); 0: off (default). */
+int m2c_set_profiling(m2c_ctx* ctx, int on);
+
+/* Interface faces of the current material field: ascending face ids
+ * f = 3c + d (face between cell c and its +d neighbour, periodic wrap
+ * included), exactly as the Riemann work queue holds them.  Writes at most
+ * cap ids to the host array out (nullable) and the total to *count. */
+int m2c_interface_faces(m2c_ctx* ctx, int32_t* out, int64_t cap, int64_t* count);
+
+/* ---- kernel-level entry points (device pointers, given stream) ---------- */
+
+/* HLLC flux at n faces in the face frame: qL, qR = [rho,u_n,v_t1,v_t2,p][n]
+ * (SoA), one stiffened gas (gamma, pc); F = [5][n].  prec selects the FP64
+ * or the FP32 flux of the mixed form (inputs and outputs stay FP64). */
+int m2c_eval_hllc(int64_t n, const double* qL, const double* qR, double gamma, double pc,
+                  int32_t prec, double* F, void* hip_stream);
+
+/* Exact two-material Riemann problems: in = [rho_L,u_L,p_L,rho_R,u_R,p_R][n],
+ * eos = [gamma_L,pc_L,gamma_R,pc_R][n], out = [p*,u*,rho*_L,rho*_R][n],
+ * iters (nullable) = Newton steps per problem (negative: bisection fallback;
+ * 0: no admissible star pressure, out = NaN).  Always-FP64 safeguarded Newton
+ * from the acoustic guess (or the loaded MLP guess, judged by |g|).
+ * Returns M2C_ERR_RIEMANN if any problem had no admissible star pressure. */
+int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t guess,
+                      double rtol, int32_t maxit, double* out, int32_t* iters,
+                      void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* M2C_H */

@@ -1,0 +1,278 @@
+"""ctypes declarations of the C ABI (``include/m2c.h``) and a small wrapper.
+
+Argument marshalling only: no arithmetic of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libm2c.so")
+
+M2C_OK, M2C_ERR_ARG, M2C_ERR_NONPHYSICAL, M2C_ERR_RIEMANN = 0, -1, -2, -3
+M2C_ERR_DEVICE, M2C_ERR_STATE, M2C_ERR_UNIMPLEMENTED, M2C_ERR_NOMEM = -4, -5, -6, -7
+M2C_BC_TRANSMISSIVE, M2C_BC_WALL, M2C_BC_PERIODIC = 0, 1, 2
+M2C_PREC_FP64, M2C_PREC_MIXED = 0, 1
+M2C_GUESS_ACOUSTIC, M2C_GUESS_MLP = 0, 1
+
+# Every symbol the header declares (checked by the CPU test suite).
+EXPORTS = [
+    "m2c_config_default", "m2c_create", "m2c_destroy", "m2c_last_error", "m2c_strerror",
+    "m2c_set_stream", "m2c_set_state", "m2c_set_state_device", "m2c_get_state",
+    "m2c_get_state_device", "m2c_get_conserved", "m2c_set_conserved", "m2c_step", "m2c_step_dt",
+    "m2c_get_stats", "m2c_reset_stats", "m2c_set_profiling", "m2c_interface_faces",
+    "m2c_eval_hllc", "m2c_riemann_solve",
+]
+
+
+class Config(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("gamma", C.c_double * 2), ("pc", C.c_double * 2), ("bc", C.c_int32 * 6),
+                ("limiter_alpha", C.c_double), ("rk_order", C.c_int32), ("cfl", C.c_double),
+                ("dt_fixed", C.c_double), ("precision", C.c_int32), ("guess", C.c_int32),
+                ("riemann_rtol", C.c_double), ("riemann_maxit", C.c_int32),
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt_last", C.c_double),
+                ("iface_faces_last", C.c_int64), ("riemann_solves", C.c_int64),
+                ("newton_iters", C.c_int64), ("bisection_fallbacks", C.c_int64),
+                ("flips", C.c_int64), ("orphans", C.c_int64), ("mlp_fallbacks", C.c_int64),
+                ("err_code", C.c_int32), ("pad0", C.c_int32), ("err_cell", C.c_int64),
+                ("ms_stage", C.c_double), ("ms_fiver", C.c_double), ("ms_other", C.c_double),
+                ("stage_launches", C.c_int64), ("fiver_launches", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+
+
+class M2CError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"m2c error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _declare(L):
+    vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.m2c_config_default.argtypes = [C.POINTER(Config)]
+    L.m2c_config_default.restype = None
+    L.m2c_create.argtypes = [C.POINTER(Config), C.POINTER(vp)]
+    L.m2c_destroy.argtypes = [vp]
+    L.m2c_destroy.restype = None
+    L.m2c_last_error.argtypes = [vp]
+    L.m2c_last_error.restype = C.c_char_p
+    L.m2c_strerror.argtypes = [C.c_int]
+    L.m2c_strerror.restype = C.c_char_p
+    L.m2c_set_stream.argtypes = [vp, vp]
+    L.m2c_set_state.argtypes = [vp, vp]
+    L.m2c_set_state_device.argtypes = [vp, vp]
+    L.m2c_get_state.argtypes = [vp, vp, vp]
+    L.m2c_get_state_device.argtypes = [vp, vp]
+    L.m2c_get_conserved.argtypes = [vp, vp]
+    L.m2c_set_conserved.argtypes = [vp, vp]
+    L.m2c_step.argtypes = [vp, i32, C.POINTER(d)]
+    L.m2c_step_dt.argtypes = [vp, i32, d, C.POINTER(d)]
+    L.m2c_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.m2c_reset_stats.argtypes = [vp]
+    L.m2c_set_profiling.argtypes = [vp, C.c_int]
+    L.m2c_interface_faces.argtypes = [vp, vp, i64, C.POINTER(i64)]
+    L.m2c_eval_hllc.argtypes = [i64, vp, vp, d, d, i32, vp, vp]
+    L.m2c_riemann_solve.argtypes = [i64, vp, vp, i32, d, i32, vp, vp, vp]
+    for name in EXPORTS:
+        if name not in ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror"):
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+def lib():
+    """Load ``libm2c.so``; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python -m paper_2508_16387_amd.build` (there is no CPU fallback)")
+        _lib = _declare(C.CDLL(_LIB_PATH))
+    return _lib
+
+
+def exported_symbols(path: str | None = None):
+    """Names from EXPORTS that the shared object resolves (no GPU needed)."""
+    L = C.CDLL(path or _LIB_PATH)
+    return [n for n in EXPORTS if hasattr(L, n)]
+
+
+def config_default() -> Config:
+    c = Config()
+    lib().m2c_config_default(C.byref(c))
+    return c
+
+
+def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None) -> Config:
+    """Configuration for a problem description with attributes n, lo, hi,
+    gamma, pc, bc, cfl, dt_fixed (as built by the ``workloads`` module)."""
+    c = config_default()
+    c.nx, c.ny, c.nz = (int(v) for v in problem.n)
+    for d in range(3):
+        c.lo[d], c.hi[d] = problem.lo[d], problem.hi[d]
+    for m in range(2):
+        c.gamma[m], c.pc[m] = problem.gamma[m], problem.pc[m]
+    for f in range(6):
+        c.bc[f] = int(problem.bc[f])
+    c.limiter_alpha = alpha
+    c.cfl = problem.cfl
+    c.dt_fixed = problem.dt_fixed
+    c.precision = precision
+    c.riemann_rtol = rtol
+    c.riemann_maxit = maxit
+    if tile is not None:
+        c.tile_x, c.tile_y, c.tile_z = tile
+    return c
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()          # torch tensor
+
+
+class Sim:
+    """One simulation context on the current HIP device."""
+
+    def __init__(self, cfg: Config, prim=None):
+        self.L = lib()
+        self.cfg = cfg
+        self.n = (cfg.nx, cfg.ny, cfg.nz)
+        self.N = cfg.nx * cfg.ny * cfg.nz
+        h = C.c_void_p()
+        rc = self.L.m2c_create(C.byref(cfg), C.byref(h))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_create failed: " + self.L.m2c_strerror(rc).decode())
+        self.h = h
+        if prim is not None:
+            self.set_state(prim)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.m2c_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != M2C_OK:
+            raise M2CError(rc, self.L.m2c_last_error(self.h).decode())
+        return rc
+
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, an int handle or None."""
+        handle = None if stream is None else getattr(stream, "cuda_stream", stream)
+        return self._check(self.L.m2c_set_stream(self.h, handle))
+
+    def set_state(self, prim, check=True):
+        a = np.ascontiguousarray(prim, dtype=np.float64).reshape(-1)
+        assert a.size == 6 * self.N
+        rc = self.L.m2c_set_state(self.h, a.ctypes.data)
+        return self._check(rc) if check else rc
+
+    def set_state_device(self, dprim):
+        assert dprim.numel() == 6 * self.N and dprim.is_contiguous()
+        return self._check(self.L.m2c_set_state_device(self.h, dprim.data_ptr()))
+
+    def get_state(self):
+        nx, ny, nz = self.n
+        out = np.empty(6 * self.N)
+        chi = np.empty(self.N, dtype=np.uint8)
+        self._check(self.L.m2c_get_state(self.h, out.ctypes.data, chi.ctypes.data))
+        return out.reshape(6, nz, ny, nx), chi.reshape(nz, ny, nx)
+
+    def get_state_device(self, dprim):
+        assert dprim.numel() == 6 * self.N and dprim.is_contiguous()
+        return self._check(self.L.m2c_get_state_device(self.h, dprim.data_ptr()))
+
+    def get_conserved(self):
+        nx, ny, nz = self.n
+        out = np.empty(6 * self.N)
+        self._check(self.L.m2c_get_conserved(self.h, out.ctypes.data))
+        return out.reshape(6, nz, ny, nx)
+
+    def set_conserved(self, w6):
+        a = np.ascontiguousarray(w6, dtype=np.float64).reshape(-1)
+        assert a.size == 6 * self.N
+        return self._check(self.L.m2c_set_conserved(self.h, a.ctypes.data))
+
+    def step(self, n=1, check=True):
+        t = C.c_double(0.0)
+        rc = self.L.m2c_step(self.h, n, C.byref(t))
+        if check:
+            self._check(rc)
+        return rc
+
+    def step_dt(self, n, dt, check=True):
+        t = C.c_double(0.0)
+        rc = self.L.m2c_step_dt(self.h, n, dt, C.byref(t))
+        if check:
+            self._check(rc)
+        return rc
+
+    def stats(self):
+        s = Stats()
+        self._check(self.L.m2c_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def reset_stats(self):
+        return self._check(self.L.m2c_reset_stats(self.h))
+
+    def set_profiling(self, on=True):
+        return self._check(self.L.m2c_set_profiling(self.h, 1 if on else 0))
+
+    def interface_faces(self):
+        cnt = C.c_int64(0)
+        self._check(self.L.m2c_interface_faces(self.h, None, 0, C.byref(cnt)))
+        out = np.empty(max(cnt.value, 1), dtype=np.int32)
+        self._check(self.L.m2c_interface_faces(self.h, out.ctypes.data, cnt.value, C.byref(cnt)))
+        return out[:cnt.value]
+
+    def last_error(self):
+        return self.L.m2c_last_error(self.h).decode()
+
+
+def eval_hllc(qL, qR, gamma, pc, precision=M2C_PREC_FP64, F=None, stream=None):
+    """HLLC at n faces; qL, qR: torch float64 cuda tensors [5, n] (face frame)."""
+    import torch
+    n = qL.shape[1]
+    if F is None:
+        F = torch.empty((5, n), dtype=torch.float64, device=qL.device)
+    s = torch.cuda.current_stream(qL.device).cuda_stream if stream is None else stream
+    rc = lib().m2c_eval_hllc(n, _ptr(qL), _ptr(qR), gamma, pc, precision, _ptr(F), s)
+    if rc != M2C_OK:
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return F
+
+
+def riemann_solve(inp, eos, guess=M2C_GUESS_ACOUSTIC, rtol=1e-12, maxit=50, stream=None, check=True):
+    """Two-material Riemann problems; inp [6, n], eos [4, n] float64 cuda
+    tensors.  Returns (out [4, n], iters [n], rc)."""
+    import torch
+    n = inp.shape[1]
+    out = torch.empty((4, n), dtype=torch.float64, device=inp.device)
+    iters = torch.empty((n,), dtype=torch.int32, device=inp.device)
+    s = torch.cuda.current_stream(inp.device).cuda_stream if stream is None else stream
+    rc = lib().m2c_riemann_solve(n, _ptr(inp), _ptr(eos), guess, rtol, maxit, _ptr(out), _ptr(iters), s)
+    if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return out, iters, rc

@@ -1,0 +1,394 @@
+// k_interface.hip -- interface-face work queue, FIVER fluxes and the phase
+// update.
+//
+// FIVER (section "Spatial discretization of governing equations", eq.
+// 1DRiemannProblem): at a face whose two cells hold different materials the
+// flux is not one HLLC flux but two one-sided fluxes built on the exact
+// solution of the two-material Riemann problem along the face normal.  Those
+// faces are a thin sheet (well under 1% of all faces), so they are gathered
+// into a dense queue once per step (material ids are frozen during a step)
+// and solved by one thread each, away from the bulk stage kernel whose
+// wavefronts would otherwise diverge on the Newton iteration.
+//
+// Queue order is ascending face id f = 3c + d (face between cell c and its
+// +d neighbour); the compaction is a deterministic three-pass scan
+// (per-block count, one-block exclusive scan, scatter with wavefront prefix
+// sums), so the queue is bit-identical from run to run.  The face -> slot
+// map is written only at the faces of the new queue and read only at faces
+// whose cells differ in material under the same frozen ids, so entries left
+// from earlier queues are never read and need no clearing.
+#include "m2c_device.h"
+#include "m2c_internal.h"
+#include "m2c_kernels.h"
+
+namespace m2c {
+
+// Upper neighbour of cell (i,j,k) across axis d, or -1 when the face lies on
+// a non-periodic domain boundary (no interface there: the boundary image
+// carries the boundary cell's material).
+__device__ __forceinline__ long long upper_neighbour(const Grid& G, int i, int j, int k, int d, long long c)
+{
+    const long long sxy = (long long)G.nx * G.ny;
+    if (d == 0) {
+        if (i + 1 < G.nx) return c + 1;
+        return G.bc[1] == BC_PERIODIC ? c - (G.nx - 1) : -1;
+    }
+    if (d == 1) {
+        if (j + 1 < G.ny) return c + G.nx;
+        return G.bc[3] == BC_PERIODIC ? c - (long long)(G.ny - 1) * G.nx : -1;
+    }
+    if (k + 1 < G.nz) return c + sxy;
+    return G.bc[5] == BC_PERIODIC ? c - (long long)(G.nz - 1) * sxy : -1;
+}
+
+// Interface-face bits of one cell: bit d set when the +d face separates
+// two materials.
+__device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t* __restrict__ chi,
+                                                   int i, int j, int k, long long c)
+{
+    const uint8_t x = chi[c];
+    unsigned bits = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (!G.act[d]) continue;
+        const long long n = upper_neighbour(G, i, j, k, d, c);
+        if (n >= 0 && chi[n] != x) bits |= 1u << d;
+    }
+    return bits;
+}
+
+// Walk the COMPACT_CELLS_PER_THREAD consecutive cells of this thread,
+// calling f(c, bits) for each cell.
+template <typename F>
+__device__ __forceinline__ void walk_cells(const Grid& G, const uint8_t* __restrict__ chi, long long c0, F f)
+{
+    if (c0 >= G.N) return;
+    const long long sxy = (long long)G.nx * G.ny;
+    int k = (int)(c0 / sxy);
+    const long long r = c0 - (long long)k * sxy;
+    int j = (int)(r / G.nx);
+    int i = (int)(r - (long long)j * G.nx);
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
+        const long long c = c0 + e;
+        if (c >= G.N) break;
+        f(c, cell_face_bits(G, chi, i, j, k, c));
+        if (++i == G.nx) {
+            i = 0;
+            if (++j == G.ny) {
+                j = 0;
+                ++k;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int block_sum(int v, int* sRed)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sRed[w] = v;
+    __syncthreads();
+    int t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sRed[k];
+    return t;
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a)
+{
+    __shared__ int sRed[COMPACT_THREADS / 64];
+    const long long c0 = (long long)blockIdx.x * COMPACT_CELLS_PER_BLOCK +
+                         (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
+    int cnt = 0;
+    walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
+    const int t = block_sum(cnt, sRed);
+    if (threadIdx.x == 0) a.blockcnt[blockIdx.x] = t;
+}
+
+// One block: exclusive scan of the block counts (in place), total -> qlen.
+__global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a)
+{
+    __shared__ int sW[16];
+    __shared__ long long sCarry;
+    if (threadIdx.x == 0) sCarry = 0;
+    __syncthreads();
+    const int nb = a.nblk;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int base = 0; base < nb; base += 1024) {
+        const int b = base + threadIdx.x;
+        const int v = b < nb ? a.blockcnt[b] : 0;
+        int incl = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) sW[w] = incl;
+        __syncthreads();
+        int woff = 0;
+        for (int k = 0; k < w; ++k) woff += sW[k];
+        int tot = 0;
+        for (int k = 0; k < 16; ++k) tot += sW[k];
+        const long long carry = sCarry;
+        if (b < nb) a.blockcnt[b] = (int)(carry + woff + incl - v);
+        __syncthreads();
+        if (threadIdx.x == 0) sCarry = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long total = sCarry;
+        if (total > a.qcap) {
+            atomicCAS(&a.sc->err, 0, ST_OVERFLOW);
+            a.sc->qlen = 0;
+        } else {
+            a.sc->qlen = (int)total;
+        }
+    }
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
+{
+    __shared__ int sW[COMPACT_THREADS / 64];
+    if (a.sc->err != 0) return;
+    const long long c0 = (long long)blockIdx.x * COMPACT_CELLS_PER_BLOCK +
+                         (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
+    int cnt = 0;
+    walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
+    // exclusive prefix of cnt over the block, in thread order
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sW[w] = incl;
+    __syncthreads();
+    int off = a.blockcnt[blockIdx.x];
+    for (int k = 0; k < w; ++k) off += sW[k];
+    off += incl - cnt;
+    if (cnt == 0) return;
+    walk_cells(a.g, a.chi, c0, [&](long long c, unsigned bits) {
+        for (int d = 0; d < 3; ++d)
+            if (bits & (1u << d)) {
+                const int f = (int)(3 * c + d);
+                a.queue[off] = f;
+                a.fslot[f] = off;
+                ++off;
+            }
+    });
+}
+
+hipError_t launch_compact(const IfaceArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scatter, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FIVER: one thread per queued face.  The Riemann data are the two cells'
+// own (first-order) primitive states in the face frame (rho, u_n, p); the
+// star states W*_L = (rho*_L, u*, tangential V_L, p*) and W*_R likewise feed
+//   F_lower = HLLC(W_L, W*_L; EOS of the lower cell)
+//   F_upper = HLLC(W*_R, W_R; EOS of the upper cell)
+// with the arguments ordered along the face normal.
+__device__ __forceinline__ void cell_prim(const Grid& G, const double* __restrict__ W, long long c, int x,
+                                          double q[5])
+{
+    const long long N = G.N;
+    double u, v, w;
+    q[4] = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], G.gamma[x] - 1.0, G.gpc[x],
+                    u, v, w);
+    q[0] = W[c];
+    q[1] = u;
+    q[2] = v;
+    q[3] = w;
+}
+
+__global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
+{
+    DevScalars* sc = a.sc;
+    if (sc->err != 0) return;
+    const Grid& G = a.g;
+    const int n = sc->qlen;
+    const long long sxy = (long long)G.nx * G.ny;
+    long long iters = 0, fallbacks = 0;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const int f = a.queue[q];
+        const long long c = f / 3;
+        const int d = f - 3 * (int)c;
+        const int k = (int)(c / sxy);
+        const long long r = c - (long long)k * sxy;
+        const int j = (int)(r / G.nx);
+        const int i = (int)(r - (long long)j * G.nx);
+        const long long cn = upper_neighbour(G, i, j, k, d, c);
+        const int xa = a.chi[c], xb = a.chi[cn];
+        double qa[5], qb[5];
+        cell_prim(G, a.Win, c, xa, qa);
+        cell_prim(G, a.Win, cn, xb, qb);
+        const int t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+        const double ua = qa[1 + d], ub = qb[1 + d];
+        const double gA = G.gamma[xa], pcA = G.pc[xa], gB = G.gamma[xb], pcB = G.pc[xb];
+        double out[4];
+        int it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit,
+                               false, 0.0, out);
+        if (it == 0) {
+            report_error(&sc->err, &sc->err_cell, ST_RIEMANN, c);
+            continue;
+        }
+        iters += it < 0 ? -it : it;
+        fallbacks += it < 0;
+        const double ps = out[0], us = out[1];
+        double Fl[5], Fu[5];
+        hllc<double>(qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA, G.gpc[xa],
+                     G.inv_gm1[xa], Fl);
+        hllc<double>(out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB, G.gpc[xb],
+                     G.inv_gm1[xb], Fu);
+        const long long Q = a.qcap;
+        // face frame (mass, normal, t1, t2, energy) -> global components
+        a.fluxF[0 * Q + q] = Fl[0];
+        a.fluxF[(1 + d) * Q + q] = Fl[1];
+        a.fluxF[t1 * Q + q] = Fl[2];
+        a.fluxF[t2 * Q + q] = Fl[3];
+        a.fluxF[4 * Q + q] = Fl[4];
+        a.fluxF[5 * Q + q] = Fu[0];
+        a.fluxF[(6 + d) * Q + q] = Fu[1];
+        a.fluxF[(5 + t1) * Q + q] = Fu[2];
+        a.fluxF[(5 + t2) * Q + q] = Fu[3];
+        a.fluxF[9 * Q + q] = Fu[4];
+        if (record) {
+            a.star[0 * Q + q] = ps;
+            a.star[1 * Q + q] = us;
+            a.star[2 * Q + q] = out[2];
+            a.star[3 * Q + q] = out[3];
+            a.star[4 * Q + q] = qa[t1];
+            a.star[5 * Q + q] = qa[t2];
+            a.star[6 * Q + q] = qb[t1];
+            a.star[7 * Q + q] = qb[t2];
+        }
+    }
+    // one atomic per wavefront for the counters
+    for (int o = 32; o > 0; o >>= 1) {
+        iters += __shfl_xor(iters, o);
+        fallbacks += __shfl_xor(fallbacks, o);
+    }
+    if ((threadIdx.x & 63) == 0 && (iters | fallbacks)) {
+        atomicAdd((unsigned long long*)&sc->newton_iters, (unsigned long long)iters);
+        atomicAdd((unsigned long long*)&sc->fallbacks, (unsigned long long)fallbacks);
+    }
+}
+
+hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
+{
+    long long nb = (a.qcap + 63) / 64;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(64), 0, s, a, record ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Phase update (step 6 of the time-step outline, section "Code structure"):
+// material ids follow the sign of the new level set; a cell that changed
+// from material A to B takes the mean, over its faces in the order
+// -x,+x,-y,+y,-z,+z whose neighbour held B during the step, of the B-side
+// star state of the last stage's Riemann problem there (rho*_B, the B
+// cell's velocity with its normal component replaced by u*, p*), encoded
+// with B's equation of state.  Without such a face it keeps its primitive
+// state (an "orphan").  The new state also enters the next step's CFL
+// maximum.
+__global__ __launch_bounds__(256) void k_phase(const PhaseArgs a)
+{
+    DevScalars* sc = a.sc;
+    if (sc->err != 0) return;
+    const Grid& G = a.g;
+    const int n = sc->nflip;
+    const long long N = G.N, sxy = (long long)G.nx * G.ny, Q = a.qcap;
+    const long long cstr[3] = {1, G.nx, sxy};
+    const int nd[3] = {G.nx, G.ny, G.nz};
+    double lam = 0.0;
+    long long orphans = 0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const long long c = a.flips[e];
+        const int A = a.chi_old[c], B = a.chi_new[c];
+        const int k = (int)(c / sxy);
+        const long long r = c - (long long)k * sxy;
+        const int j = (int)(r / G.nx);
+        const int i = (int)(r - (long long)j * G.nx);
+        const int ijk[3] = {i, j, k};
+        double sum[5] = {0, 0, 0, 0, 0};
+        int cnt = 0;
+        for (int d = 0; d < 3; ++d) {
+            if (!G.act[d]) continue;
+            for (int side = 0; side < 2; ++side) {
+                int nb = ijk[d] + (side ? 1 : -1);
+                if (nb < 0 || nb >= nd[d]) {
+                    if (G.bc[2 * d + side] != BC_PERIODIC) continue;
+                    nb = (nb + nd[d]) % nd[d];
+                }
+                const long long ck = c + (long long)(nb - ijk[d]) * cstr[d];
+                if (a.chi_old[ck] != B) continue;
+                const long long lower = side ? c : ck;
+                const int sl = a.fslot[3 * lower + d];
+                if (sl < 0) continue;
+                const int t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
+                double qv[5];
+                qv[0] = a.star[(side ? 3 : 2) * Q + sl];
+                qv[1 + d] = a.star[1 * Q + sl];
+                qv[t1] = a.star[(side ? 6 : 4) * Q + sl];
+                qv[t2] = a.star[(side ? 7 : 5) * Q + sl];
+                qv[4] = a.star[0 * Q + sl];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sum[v] += qv[v];
+                ++cnt;
+            }
+        }
+        double q[5];
+        if (cnt) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) q[v] = sum[v] / cnt;
+        } else {
+            double u, vv, w;
+            q[4] = eos_prim(a.W[c], a.W[N + c], a.W[2 * N + c], a.W[3 * N + c], a.W[4 * N + c],
+                            G.gamma[A] - 1.0, G.gpc[A], u, vv, w);
+            q[0] = a.W[c];
+            q[1] = u;
+            q[2] = vv;
+            q[3] = w;
+            ++orphans;
+        }
+        bool ok = q[0] > 0.0 && q[4] + G.pc[B] > 0.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) ok = ok && isfinite(q[v]);
+        if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
+        a.W[c] = q[0];
+        a.W[N + c] = q[0] * q[1];
+        a.W[2 * N + c] = q[0] * q[2];
+        a.W[3 * N + c] = q[0] * q[3];
+        a.W[4 * N + c] = eos_energy<double>(q[0], q[1], q[2], q[3], q[4], G.gpc[B], G.inv_gm1[B]);
+        if (ok) {
+            const double cs = sqrt(G.gamma[B] * (q[4] + G.pc[B]) / q[0]);
+            double l = 0.0;
+            for (int d = 0; d < 3; ++d)
+                if (G.act[d]) l += (fabs(q[1 + d]) + cs) * G.rh[d];
+            lam = fmax(lam, l);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lam = fmax(lam, __shfl_xor(lam, o));
+        orphans += __shfl_xor(orphans, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (lam > 0.0) atomic_max_nonneg(&sc->lam_bits, lam);
+        if (orphans) atomicAdd((unsigned long long*)&sc->orphans, (unsigned long long)orphans);
+    }
+}
+
+hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
+{
+    long long nb = (a.g.N + 255) / 256;
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace m2c

@@ -1,0 +1,663 @@
+// m2c_api.hip -- host runtime behind the C ABI of include/m2c.h.
+//
+// One context owns one grid's device buffers and stream.  A time step is
+// enqueued as a fixed kernel sequence with no host round trip:
+//   begin_step (dt) -> interface compaction -> [FIVER, stage] x 2 -> phase
+//   update -> end_step
+// and every kernel returns at once when an earlier one has reported an
+// error, so the last good state is the start-of-step buffer of the failing
+// step (the two full states alternate between W[0] and W[1]).  The host
+// reads the device scalars once per m2c_step call.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/m2c.h"
+#include "m2c_internal.h"
+#include "m2c_kernels.h"
+
+using namespace m2c;
+
+struct m2c_ctx {
+    m2c_config cfg;
+    Grid g;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double* W[2] = {nullptr, nullptr};
+    double* W1 = nullptr;           // stage-1 state; also scratch for host transfers
+    uint8_t* chi[2] = {nullptr, nullptr};
+    int32_t* queue = nullptr;
+    int32_t* fslot = nullptr;
+    double* fluxF = nullptr;
+    double* star = nullptr;
+    int32_t* flips = nullptr;
+    int32_t* blockcnt = nullptr;
+    DevScalars* sc = nullptr;       // device
+    DevScalars* hsc = nullptr;      // pinned host mirror
+    long long qcap = 0;
+    int nblk_compact = 0;
+    int cur = 0;                    // index of the current state
+    bool has_state = false;
+    bool lam_valid = false;
+    int tx = 32, ty = 8, kz = 8;
+    int tiles[3] = {1, 1, 1};
+    bool profiling = false;
+    std::vector<hipEvent_t> evpool;  // profiling: 7 events per enqueued step
+    int ev_steps = 0;               // steps recorded in the pool, not yet harvested
+    double ms_stage = 0, ms_fiver = 0, ms_other = 0;
+    long long stage_launches = 0, fiver_launches = 0;
+    long long steps_base = 0;       // steps_done at the last stats reset
+    char err[256] = {0};
+};
+
+namespace {
+
+int set_err(m2c_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int set_err(m2c_ctx* c, int code, const char* fmt, ...)
+{
+    if (c) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(c->err, sizeof(c->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return set_err((ctx), M2C_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+bool valid_config(const m2c_config* c, char* why, size_t n)
+{
+    if (!c) return snprintf(why, n, "null config"), false;
+    if (c->struct_size != sizeof(m2c_config))
+        return snprintf(why, n, "struct_size %u != %zu", c->struct_size, sizeof(m2c_config)), false;
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1) return snprintf(why, n, "grid extents must be >= 1"), false;
+    const long long N = (long long)c->nx * c->ny * c->nz;
+    if (3 * N > (long long)INT_MAX) return snprintf(why, n, "grid too large for 32-bit face ids"), false;
+    for (int d = 0; d < 3; ++d) {
+        if (!(c->hi[d] > c->lo[d])) return snprintf(why, n, "empty box along axis %d", d), false;
+        const bool plo = c->bc[2 * d] == M2C_BC_PERIODIC, phi = c->bc[2 * d + 1] == M2C_BC_PERIODIC;
+        if (plo != phi) return snprintf(why, n, "periodic boundaries must pair up (axis %d)", d), false;
+        for (int s = 0; s < 2; ++s)
+            if (c->bc[2 * d + s] < 0 || c->bc[2 * d + s] > 2) return snprintf(why, n, "bad bc"), false;
+    }
+    for (int m = 0; m < 2; ++m)
+        if (!(c->gamma[m] > 1.0) || !(c->pc[m] >= 0.0) || !std::isfinite(c->pc[m]))
+            return snprintf(why, n, "material %d needs gamma > 1 and p_c >= 0", m), false;
+    if (!(c->limiter_alpha >= 1.0 && c->limiter_alpha <= 2.0))
+        return snprintf(why, n, "limiter alpha must lie in [1, 2]"), false;
+    if (c->rk_order != 2) return snprintf(why, n, "only TVD-RK2 is built"), false;
+    if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0)) return snprintf(why, n, "cfl must be > 0"), false;
+    if (c->precision != M2C_PREC_FP64 && c->precision != M2C_PREC_MIXED)
+        return snprintf(why, n, "bad precision"), false;
+    if (c->guess != M2C_GUESS_ACOUSTIC) return snprintf(why, n, "only the acoustic guess is built"), false;
+    if (!(c->riemann_rtol > 0.0) || c->riemann_maxit < 1) return snprintf(why, n, "bad Riemann tolerance"), false;
+    if ((c->tile_x || c->tile_y) && !stage_tile_supported(c->tile_x, c->tile_y))
+        return snprintf(why, n, "unsupported stage tile %dx%d", c->tile_x, c->tile_y), false;
+    if (c->tile_z < 0) return snprintf(why, n, "tile_z must be >= 0"), false;
+    return true;
+}
+
+void fill_grid(Grid& g, const m2c_config& c)
+{
+    memset(&g, 0, sizeof(g));
+    g.nx = c.nx;
+    g.ny = c.ny;
+    g.nz = c.nz;
+    g.N = (long long)c.nx * c.ny * c.nz;
+    const int nd[3] = {c.nx, c.ny, c.nz};
+    for (int d = 0; d < 3; ++d) {
+        g.act[d] = nd[d] > 1;
+        g.h[d] = (c.hi[d] - c.lo[d]) / nd[d];
+        g.rh[d] = 1.0 / g.h[d];
+        g.rh6[d] = 1.0 / (6.0 * g.h[d]);
+    }
+    for (int f = 0; f < 6; ++f) g.bc[f] = c.bc[f];
+    for (int m = 0; m < 2; ++m) {
+        g.gamma[m] = c.gamma[m];
+        g.pc[m] = c.pc[m];
+        g.gpc[m] = c.gamma[m] * c.pc[m];
+        g.inv_gm1[m] = 1.0 / (c.gamma[m] - 1.0);
+    }
+    g.alpha = c.limiter_alpha;
+    g.cfl = c.cfl;
+    g.dt_fixed = c.dt_fixed;
+    g.rtol = c.riemann_rtol;
+    g.maxit = c.riemann_maxit;
+    g.guess = c.guess;
+}
+
+// Reset the error state of the device scalars (host mirror -> device).
+int clear_error(m2c_ctx* c)
+{
+    c->hsc->err = 0;
+    c->hsc->err_cell = LLONG_MAX;
+    HIPCHK(c, hipMemcpyAsync(&c->sc->err, &c->hsc->err, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&c->sc->err_cell, &c->hsc->err_cell, sizeof(long long), hipMemcpyHostToDevice,
+                             c->stream));
+    return M2C_OK;
+}
+
+int pull_scalars(m2c_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2C_OK;
+}
+
+IfaceArgs iface_args(m2c_ctx* c, const double* Win)
+{
+    IfaceArgs a;
+    a.g = c->g;
+    a.Win = Win;
+    a.chi = c->chi[c->cur];
+    a.queue = c->queue;
+    a.fslot = c->fslot;
+    a.fluxF = c->fluxF;
+    a.star = c->star;
+    a.blockcnt = c->blockcnt;
+    a.qcap = c->qcap;
+    a.nblk = c->nblk_compact;
+    a.sc = c->sc;
+    a.mlp = nullptr;
+    return a;
+}
+
+const char* status_name(int s)
+{
+    switch (s) {
+    case M2C_OK: return "ok";
+    case M2C_ERR_ARG: return "invalid argument";
+    case M2C_ERR_NONPHYSICAL: return "non-physical state (rho <= 0, p + p_c <= 0 or non-finite)";
+    case M2C_ERR_RIEMANN: return "interface Riemann problem without admissible star pressure";
+    case M2C_ERR_DEVICE: return "HIP runtime failure";
+    case M2C_ERR_STATE: return "call out of order";
+    case M2C_ERR_UNIMPLEMENTED: return "not implemented";
+    case M2C_ERR_NOMEM: return "out of memory or work-queue capacity";
+    default: return "unknown status";
+    }
+}
+
+// Accumulate the kernel-class times of the steps recorded in the event pool
+// (synchronises on the last recorded event).
+int harvest_events(m2c_ctx* c)
+{
+    if (c->ev_steps == 0) return M2C_OK;
+    HIPCHK(c, hipEventSynchronize(c->evpool[(size_t)c->ev_steps * 7 - 1]));
+    for (int k = 0; k < c->ev_steps; ++k) {
+        hipEvent_t* e = c->evpool.data() + (size_t)k * 7;
+        float t[6];
+        for (int j = 0; j < 6; ++j) HIPCHK(c, hipEventElapsedTime(&t[j], e[j], e[j + 1]));
+        c->ms_other += t[0] + t[5];
+        c->ms_fiver += t[1] + t[3];
+        c->ms_stage += t[2] + t[4];
+        c->stage_launches += 2;
+        c->fiver_launches += 2;
+    }
+    c->ev_steps = 0;
+    return M2C_OK;
+}
+
+// Enqueue one full time step with state parity p (reads W[p], writes W[1-p]).
+int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
+{
+    hipStream_t s = c->stream;
+    const int q = 1 - p;
+    const bool mixed = c->cfg.precision == M2C_PREC_MIXED;
+    hipEvent_t* ev = nullptr;
+    if (c->profiling) {
+        if ((size_t)(c->ev_steps + 1) * 7 > c->evpool.size()) {
+            int rc = harvest_events(c);
+            if (rc) return rc;
+        }
+        ev = c->evpool.data() + (size_t)c->ev_steps * 7;
+    }
+    if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
+    HIPCHK(c, launch_begin_step(c->sc, c->g, dt_imposed, s));
+    IfaceArgs ia = iface_args(c, c->W[p]);
+    ia.chi = c->chi[p];
+    HIPCHK(c, launch_compact(ia, s));
+
+    StageArgs sa;
+    sa.g = c->g;
+    sa.chi = c->chi[p];
+    sa.chi_next = c->chi[q];
+    sa.flips = c->flips;
+    sa.fslot = c->fslot;
+    sa.fluxF = c->fluxF;
+    sa.qcap = c->qcap;
+    sa.sc = c->sc;
+    sa.tiles_x = c->tiles[0];
+    sa.tiles_y = c->tiles[1];
+    sa.tiles_z = c->tiles[2];
+    sa.kz = c->kz;
+
+    // stage 1: W(1) = W^n + dt R(W^n)
+    if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
+    ia.Win = c->W[p];
+    HIPCHK(c, launch_fiver(ia, false, s));
+    if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
+    sa.Win = c->W[p];
+    sa.W0 = c->W[p];
+    sa.Wout = c->W1;
+    HIPCHK(c, launch_stage(1, mixed, c->tx, c->ty, sa, s));
+    // stage 2: W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1)))
+    if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
+    ia.Win = c->W1;
+    HIPCHK(c, launch_fiver(ia, true, s));
+    if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
+    sa.Win = c->W1;
+    sa.W0 = c->W[p];
+    sa.Wout = c->W[q];
+    HIPCHK(c, launch_stage(2, mixed, c->tx, c->ty, sa, s));
+    if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
+
+    PhaseArgs pa;
+    pa.g = c->g;
+    pa.W = c->W[q];
+    pa.chi_old = c->chi[p];
+    pa.chi_new = c->chi[q];
+    pa.flips = c->flips;
+    pa.fslot = c->fslot;
+    pa.star = c->star;
+    pa.qcap = c->qcap;
+    pa.sc = c->sc;
+    HIPCHK(c, launch_phase(pa, s));
+    HIPCHK(c, launch_end_step(c->sc, 2, s));
+    if (ev) {
+        HIPCHK(c, hipEventRecord(ev[6], s));
+        ++c->ev_steps;
+    }
+    return M2C_OK;
+}
+
+int run_steps(m2c_ctx* c, int32_t nsteps, double dt_imposed, double* t_out)
+{
+    if (!c) return M2C_ERR_ARG;
+    if (nsteps < 0) return set_err(c, M2C_ERR_ARG, "nsteps < 0");
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "m2c_step before a state was set");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = clear_error(c);
+    if (rc) return rc;
+    if (!c->lam_valid && !(dt_imposed > 0.0) && !(c->cfg.dt_fixed > 0.0)) {
+        HIPCHK(c, launch_lambda(c->g, c->W[c->cur], c->chi[c->cur], c->sc, c->stream));
+    }
+    rc = pull_scalars(c);
+    if (rc) return rc;
+    const long long done0 = c->hsc->steps_done;
+    int p = c->cur;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        rc = enqueue_step(c, p, dt_imposed);
+        if (rc) return rc;
+        p = 1 - p;
+    }
+    rc = pull_scalars(c);
+    if (rc) return rc;
+    rc = harvest_events(c);
+    if (rc) return rc;
+    const long long done = c->hsc->steps_done - done0;
+    c->cur = (int)((c->cur + done) & 1);
+    if (t_out) *t_out = c->hsc->t;
+    if (c->hsc->err != 0) {
+        c->lam_valid = false;
+        const int e = c->hsc->err;
+        const int code = e == ST_OVERFLOW ? M2C_ERR_NOMEM : e;
+        return set_err(c, code, "step %lld failed: %s (cell %lld)", c->hsc->steps_done + 1, status_name(code),
+                       c->hsc->err_cell);
+    }
+    c->lam_valid = true;
+    return M2C_OK;
+}
+
+int upload_prim(m2c_ctx* c, const double* dprim)
+{
+    int rc = clear_error(c);
+    if (rc) return rc;
+    const int q = 1 - c->cur;
+    HIPCHK(c, launch_prim_to_cons(c->g, dprim, c->W[q], c->chi[q], c->sc, c->stream));
+    rc = pull_scalars(c);
+    if (rc) return rc;
+    if (c->hsc->err != 0) {
+        const long long cell = c->hsc->err_cell;
+        clear_error(c);
+        c->hsc->err_cell = cell;
+        return set_err(c, M2C_ERR_NONPHYSICAL, "set_state: inadmissible primitive state at cell %lld", cell);
+    }
+    c->cur = q;
+    c->has_state = true;
+    c->lam_valid = false;
+    return M2C_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void m2c_config_default(m2c_config* c)
+{
+    if (!c) return;
+    memset(c, 0, sizeof(*c));
+    c->struct_size = sizeof(m2c_config);
+    c->nx = c->ny = c->nz = 1;
+    for (int d = 0; d < 3; ++d) {
+        c->lo[d] = 0.0;
+        c->hi[d] = 1.0;
+    }
+    c->gamma[0] = 1.4;
+    c->pc[0] = 0.0;
+    c->gamma[1] = 6.12;
+    c->pc[1] = 3.43e8;
+    for (int f = 0; f < 6; ++f) c->bc[f] = M2C_BC_TRANSMISSIVE;
+    c->limiter_alpha = 1.2;
+    c->rk_order = 2;
+    c->cfl = 0.5;
+    c->dt_fixed = 0.0;
+    c->precision = M2C_PREC_FP64;
+    c->guess = M2C_GUESS_ACOUSTIC;
+    c->riemann_rtol = 1e-12;
+    c->riemann_maxit = 50;
+}
+
+const char* m2c_strerror(int status) { return status_name(status); }
+
+const char* m2c_last_error(const m2c_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+void m2c_destroy(m2c_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 2; ++k) {
+        (void)hipFree(c->W[k]);
+        (void)hipFree(c->chi[k]);
+    }
+    (void)hipFree(c->W1);
+    (void)hipFree(c->queue);
+    (void)hipFree(c->fslot);
+    (void)hipFree(c->fluxF);
+    (void)hipFree(c->star);
+    (void)hipFree(c->flips);
+    (void)hipFree(c->blockcnt);
+    (void)hipFree(c->sc);
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    for (auto& e : c->evpool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+int m2c_create(const m2c_config* cfg, m2c_ctx** out)
+{
+    if (!out) return M2C_ERR_ARG;
+    *out = nullptr;
+    char why[160];
+    if (!valid_config(cfg, why, sizeof(why))) return M2C_ERR_ARG;
+    m2c_ctx* c = new (std::nothrow) m2c_ctx();
+    if (!c) return M2C_ERR_NOMEM;
+    c->cfg = *cfg;
+    fill_grid(c->g, *cfg);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return M2C_ERR_DEVICE;
+    }
+    const long long N = c->g.N;
+    // interface queue capacity: every face for small grids, one face per
+    // cell beyond that (far above any sheet-like interface)
+    c->qcap = 3 * N;
+    if (c->qcap > 65536 && c->qcap > N) c->qcap = N > 65536 ? N : 65536;
+    c->nblk_compact = (int)((N + COMPACT_CELLS_PER_BLOCK - 1) / COMPACT_CELLS_PER_BLOCK);
+
+    // stage tiles: (tile_x, tile_y) or 32x8; planes per block tile_z or 8
+    c->tx = cfg->tile_x ? cfg->tile_x : 32;
+    c->ty = cfg->tile_y ? cfg->tile_y : 8;
+    if (!cfg->tile_x && c->g.ny == 1) {
+        c->tx = 64;
+        c->ty = 2;
+    }
+    c->kz = cfg->tile_z ? cfg->tile_z : 8;
+    if (c->kz > c->g.nz) c->kz = c->g.nz;
+    c->tiles[0] = (c->g.nx + c->tx - 1) / c->tx;
+    c->tiles[1] = (c->g.ny + c->ty - 1) / c->ty;
+    c->tiles[2] = (c->g.nz + c->kz - 1) / c->kz;
+
+    bool ok = true;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (ok && hipMalloc(p, bytes) != hipSuccess) {
+            ok = false;
+            *p = nullptr;
+        }
+    };
+    for (int k = 0; k < 2; ++k) {
+        alloc((void**)&c->W[k], 6 * N * sizeof(double));
+        alloc((void**)&c->chi[k], N);
+    }
+    alloc((void**)&c->W1, 6 * N * sizeof(double));
+    alloc((void**)&c->queue, c->qcap * sizeof(int32_t));
+    alloc((void**)&c->fslot, 3 * N * sizeof(int32_t));
+    alloc((void**)&c->fluxF, 10 * c->qcap * sizeof(double));
+    alloc((void**)&c->star, 8 * c->qcap * sizeof(double));
+    alloc((void**)&c->flips, N * sizeof(int32_t));
+    alloc((void**)&c->blockcnt, (size_t)c->nblk_compact * sizeof(int32_t));
+    alloc((void**)&c->sc, sizeof(DevScalars));
+    if (ok && hipHostMalloc((void**)&c->hsc, sizeof(DevScalars), hipHostMallocDefault) != hipSuccess) ok = false;
+    if (!ok) {
+        m2c_destroy(c);
+        return M2C_ERR_NOMEM;
+    }
+    memset(c->hsc, 0, sizeof(DevScalars));
+    c->hsc->err_cell = LLONG_MAX;
+    if (hipMemcpy(c->sc, c->hsc, sizeof(DevScalars), hipMemcpyHostToDevice) != hipSuccess ||
+        launch_fill_i32(c->fslot, 3 * N, -1, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        m2c_destroy(c);
+        return M2C_ERR_DEVICE;
+    }
+    *out = c;
+    return M2C_OK;
+}
+
+int m2c_set_stream(m2c_ctx* c, void* s)
+{
+    if (!c) return M2C_ERR_ARG;
+    c->stream = (hipStream_t)s;
+    return M2C_OK;
+}
+
+int m2c_set_state(m2c_ctx* c, const double* prim6)
+{
+    if (!c || !prim6) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(c->W1, prim6, 6 * c->g.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    return upload_prim(c, c->W1);
+}
+
+int m2c_set_state_device(m2c_ctx* c, const double* dprim6)
+{
+    if (!c || !dprim6) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    return upload_prim(c, dprim6);
+}
+
+int m2c_get_state(m2c_ctx* c, double* prim6, uint8_t* id)
+{
+    if (!c || !prim6) return M2C_ERR_ARG;
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_cons_to_prim(c->g, c->W[c->cur], c->chi[c->cur], c->W1, c->stream));
+    HIPCHK(c, hipMemcpyAsync(prim6, c->W1, 6 * c->g.N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (id) HIPCHK(c, hipMemcpyAsync(id, c->chi[c->cur], c->g.N, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2C_OK;
+}
+
+int m2c_get_state_device(m2c_ctx* c, double* dprim6)
+{
+    if (!c || !dprim6) return M2C_ERR_ARG;
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, launch_cons_to_prim(c->g, c->W[c->cur], c->chi[c->cur], dprim6, c->stream));
+    return M2C_OK;
+}
+
+int m2c_get_conserved(m2c_ctx* c, double* w6)
+{
+    if (!c || !w6) return M2C_ERR_ARG;
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipMemcpyAsync(w6, c->W[c->cur], 6 * c->g.N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return M2C_OK;
+}
+
+int m2c_set_conserved(m2c_ctx* c, const double* w6)
+{
+    if (!c || !w6) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    const int q = 1 - c->cur;
+    HIPCHK(c, hipMemcpyAsync(c->W[q], w6, 6 * c->g.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_chi_from_phi(c->g, c->W[q], c->chi[q], c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cur = q;
+    c->has_state = true;
+    c->lam_valid = false;
+    return M2C_OK;
+}
+
+int m2c_step(m2c_ctx* c, int32_t nsteps, double* t_out) { return run_steps(c, nsteps, 0.0, t_out); }
+
+int m2c_step_dt(m2c_ctx* c, int32_t nsteps, double dt, double* t_out)
+{
+    if (!c) return M2C_ERR_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, M2C_ERR_ARG, "dt must be positive and finite");
+    return run_steps(c, nsteps, dt, t_out);
+}
+
+int m2c_get_stats(m2c_ctx* c, m2c_stats* s)
+{
+    if (!c || !s) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = pull_scalars(c);
+    if (rc) return rc;
+    const DevScalars& d = *c->hsc;
+    memset(s, 0, sizeof(*s));
+    s->steps = d.steps_done - c->steps_base;
+    s->t = d.t;
+    s->dt_last = d.dt_last;
+    s->iface_faces_last = d.qlen;
+    s->riemann_solves = d.solves;
+    s->newton_iters = d.newton_iters;
+    s->bisection_fallbacks = d.fallbacks;
+    s->flips = d.flips;
+    s->orphans = d.orphans;
+    s->mlp_fallbacks = d.mlp_fallbacks;
+    s->err_code = d.err == ST_OVERFLOW ? M2C_ERR_NOMEM : d.err;
+    s->err_cell = d.err ? d.err_cell : -1;
+    s->ms_stage = c->ms_stage;
+    s->ms_fiver = c->ms_fiver;
+    s->ms_other = c->ms_other;
+    s->stage_launches = c->stage_launches;
+    s->fiver_launches = c->fiver_launches;
+    return M2C_OK;
+}
+
+int m2c_reset_stats(m2c_ctx* c)
+{
+    if (!c) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = pull_scalars(c);
+    if (rc) return rc;
+    DevScalars& d = *c->hsc;
+    d.solves = d.newton_iters = d.fallbacks = d.flips = d.orphans = d.mlp_fallbacks = 0;
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->steps_base = d.steps_done;
+    c->ms_stage = c->ms_fiver = c->ms_other = 0;
+    c->stage_launches = c->fiver_launches = 0;
+    return M2C_OK;
+}
+
+int m2c_set_profiling(m2c_ctx* c, int on)
+{
+    if (!c) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (on && c->evpool.empty()) {
+        c->evpool.resize(7 * 512, nullptr);
+        for (auto& e : c->evpool) HIPCHK(c, hipEventCreate(&e));
+    }
+    if (!on) {
+        int rc = harvest_events(c);
+        if (rc) return rc;
+    }
+    c->profiling = on != 0;
+    return M2C_OK;
+}
+
+int m2c_interface_faces(m2c_ctx* c, int32_t* out, int64_t cap, int64_t* count)
+{
+    if (!c || !count || cap < 0) return M2C_ERR_ARG;
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = clear_error(c);
+    if (rc) return rc;
+    IfaceArgs ia = iface_args(c, c->W[c->cur]);
+    HIPCHK(c, launch_compact(ia, c->stream));
+    rc = pull_scalars(c);
+    if (rc) return rc;
+    if (c->hsc->err != 0) {
+        clear_error(c);
+        return set_err(c, M2C_ERR_NOMEM, "interface queue capacity %lld exceeded", c->qcap);
+    }
+    const long long n = c->hsc->qlen;
+    *count = n;
+    const long long m = n < cap ? n : cap;
+    if (out && m > 0) {
+        HIPCHK(c, hipMemcpyAsync(out, c->queue, m * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return M2C_OK;
+}
+
+int m2c_eval_hllc(int64_t n, const double* qL, const double* qR, double gamma, double pc, int32_t prec,
+                  double* F, void* hip_stream)
+{
+    if (n < 0 || (n > 0 && (!qL || !qR || !F))) return M2C_ERR_ARG;
+    if (!(gamma > 1.0) || !(pc >= 0.0)) return M2C_ERR_ARG;
+    if (prec != M2C_PREC_FP64 && prec != M2C_PREC_MIXED) return M2C_ERR_ARG;
+    if (n == 0) return M2C_OK;
+    if (launch_hllc_points(n, qL, qR, gamma, pc, prec == M2C_PREC_MIXED, F, (hipStream_t)hip_stream) !=
+        hipSuccess)
+        return M2C_ERR_DEVICE;
+    return M2C_OK;
+}
+
+int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t guess, double rtol, int32_t maxit,
+                      double* out, int32_t* iters, void* hip_stream)
+{
+    if (n < 0 || (n > 0 && (!in || !eos || !out))) return M2C_ERR_ARG;
+    if (!(rtol > 0.0) || maxit < 1) return M2C_ERR_ARG;
+    if (guess != M2C_GUESS_ACOUSTIC) return M2C_ERR_UNIMPLEMENTED;
+    if (n == 0) return M2C_OK;
+    hipStream_t s = (hipStream_t)hip_stream;
+    int32_t* dvac = nullptr;
+    if (hipMalloc((void**)&dvac, sizeof(int32_t)) != hipSuccess) return M2C_ERR_NOMEM;
+    int32_t hv = 0;
+    int rc = M2C_OK;
+    if (hipMemsetAsync(dvac, 0, sizeof(int32_t), s) != hipSuccess ||
+        launch_riemann_points(n, in, eos, guess, nullptr, rtol, maxit, out, iters, dvac, s) != hipSuccess ||
+        hipMemcpyAsync(&hv, dvac, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        rc = M2C_ERR_DEVICE;
+    (void)hipFree(dvac);
+    if (rc == M2C_OK && hv > 0) rc = M2C_ERR_RIEMANN;
+    return rc;
+}
+
+}  // extern "C"

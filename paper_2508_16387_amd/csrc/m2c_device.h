@@ -1,0 +1,246 @@
+// m2c_device.h -- per-face and per-cell device arithmetic of the method.
+//
+// Stiffened gas (eq. NASG_EOS with b = e_c = 0): p = (gamma-1) rho e - gamma p_c,
+// c^2 = gamma (p + p_c)/rho.  Flux and limiter follow the appendices "HLLC
+// flux" and "Slope limiters"; the interface Riemann problem is eq.
+// 1DRiemannProblem for two stiffened gases.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace m2c {
+
+// ---------------------------------------------------------------- EOS ------
+// Conservative -> primitive for one cell; returns the pressure.
+__device__ __forceinline__ double eos_prim(double r, double mx, double my, double mz, double E,
+                                           double gm1, double gpc,
+                                           double& u, double& v, double& w)
+{
+    const double ri = 1.0 / r;
+    u = mx * ri;
+    v = my * ri;
+    w = mz * ri;
+    const double ke = 0.5 * (mx * u + my * v + mz * w);
+    return gm1 * (E - ke) - gpc;
+}
+
+// Total energy per unit volume of a primitive state.
+template <typename T>
+__device__ __forceinline__ T eos_energy(T r, T u, T v, T w, T p, T gpc, T inv_gm1)
+{
+    return (p + gpc) * inv_gm1 + T(0.5) * r * (u * u + v * v + w * w);
+}
+
+// ------------------------------------------------------------ limiter ------
+// MC-limited slope: with theta = dm/dp the paper's phi(theta) dp on a uniform
+// grid equals minmod(alpha dm, (dm + dp)/2, alpha dp); this is the
+// division-free form of the same function.
+template <typename T>
+__device__ __forceinline__ T mc_slope(T dm, T dp, T alpha)
+{
+    const T a = fmin(fmin(alpha * fabs(dm), T(0.5) * fabs(dm + dp)), alpha * fabs(dp));
+    return (dm * dp > T(0)) ? copysign(a, dp) : T(0);
+}
+
+// --------------------------------------------------------------- HLLC ------
+// Flux through a face with normal +n in the face frame: state = (rho, u_n,
+// v_t1, v_t2, p).  Davis wave speeds, contact speed S_*, and the star state
+// rho_K (S_K - u_K)/(S_K - S_*) [1, S_*, v_t1, v_t2, E*_K] with Toro's E*.
+// The case selection reproduces the four cases of the appendix in the
+// same order, without divergent branches.
+template <typename T>
+__device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
+                                     T rR, T uR, T aR, T bR, T pR,
+                                     T g, T pc, T gpc, T inv_gm1, T F[5])
+{
+    const T riL = T(1) / rL, riR = T(1) / rR;
+    const T cL = sqrt(g * (pL + pc) * riL);
+    const T cR = sqrt(g * (pR + pc) * riR);
+    const T EL = eos_energy<T>(rL, uL, aL, bL, pL, gpc, inv_gm1);
+    const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
+    const T SL = fmin(uL - cL, uR - cR);
+    const T SR = fmax(uL + cL, uR + cR);
+    const T dL = rL * (SL - uL), dR = rR * (SR - uR);
+    const T Ss = (pR - pL + uL * dL - uR * dR) / (dL - dR);
+
+    const bool left_sup = T(0) <= SL;
+    const bool useL = left_sup || (T(0) <= Ss);
+    const bool star = useL ? !left_sup : (T(0) <= SR);
+
+    const T r = useL ? rL : rR, u = useL ? uL : uR, a = useL ? aL : aR, b = useL ? bL : bR;
+    const T p = useL ? pL : pR, E = useL ? EL : ER, S = useL ? SL : SR;
+    const T ri = useL ? riL : riR;
+    const T mu = r * u;
+    T Fk[5];
+    Fk[0] = mu;
+    Fk[1] = mu * u + p;
+    Fk[2] = mu * a;
+    Fk[3] = mu * b;
+    Fk[4] = (E + p) * u;
+    if (star) {
+        const T inv = T(1) / (S - Ss);
+        const T fac = r * (S - u) * inv;
+        const T Us0 = fac;
+        const T Us1 = fac * Ss;
+        const T Us2 = fac * a;
+        const T Us3 = fac * b;
+        const T Us4 = fac * E * ri + (Ss - u) * (fac * Ss + p * inv);
+        F[0] = Fk[0] + S * (Us0 - r);
+        F[1] = Fk[1] + S * (Us1 - mu);
+        F[2] = Fk[2] + S * (Us2 - r * a);
+        F[3] = Fk[3] + S * (Us3 - r * b);
+        F[4] = Fk[4] + S * (Us4 - E);
+    } else {
+        for (int v = 0; v < 5; ++v) F[v] = Fk[v];
+    }
+}
+
+// ----------------------------------------------- two-material Riemann ------
+// For a stiffened gas the shifted pressure pbar = p + p_c follows the
+// ideal-gas shock and rarefaction relations, so side K contributes the
+// classical wave function f_K(p); the star pressure is the root of
+// g(p) = f_L + f_R + u_R - u_L on p > p_lo = -min(pc_L, pc_R).
+struct RSide {
+    double r, u, p, pc, pbar, c, A, B, mu, z, k2c, rc;
+};
+
+__device__ __forceinline__ void rside_init(RSide& s, double r, double u, double p, double g, double pc)
+{
+    s.r = r; s.u = u; s.p = p; s.pc = pc;
+    s.pbar = p + pc;
+    s.c = sqrt(g * s.pbar / r);
+    s.mu = (g - 1.0) / (g + 1.0);
+    s.A = 2.0 / ((g + 1.0) * r);
+    s.B = s.mu * s.pbar;
+    s.z = (g - 1.0) / (2.0 * g);
+    s.k2c = 2.0 * s.c / (g - 1.0);
+    s.rc = r * s.c;
+}
+
+// f_K(p) and f_K'(p).  Shock: (p - p_K) sqrt(A/(pbar + B)); rarefaction:
+// 2c/(gamma-1) ((pbar/pbar_K)^z - 1) with z = (gamma-1)/(2 gamma); the
+// derivative of the latter is (pbar/pbar_K)^(z-1) / (rho c).
+__device__ __forceinline__ double rside_f(const RSide& s, double p, double& df)
+{
+    const double pb = p + s.pc;
+    if (p > s.p) {
+        const double den = pb + s.B;
+        const double q = sqrt(s.A / den);
+        df = q * (1.0 - (p - s.p) / (2.0 * den));
+        return (p - s.p) * q;
+    }
+    const double x = pb / s.pbar;
+    const double t = pow(x, s.z);
+    df = t / (x * s.rc);
+    return s.k2c * (t - 1.0);
+}
+
+__device__ __forceinline__ double rside_f(const RSide& s, double p)
+{
+    double d;
+    return rside_f(s, p, d);
+}
+
+__device__ __forceinline__ double rside_star_rho(const RSide& s, double g, double ps)
+{
+    const double x = (ps + s.pc) / s.pbar;
+    if (ps > s.p) return s.r * (x + s.mu) / (s.mu * x + 1.0);
+    return s.r * pow(x, 1.0 / g);
+}
+
+// Safeguarded Newton from p0 (clamped into the admissible range), then
+// bisection if maxit steps did not meet |dp| <= rtol (p - p_lo).
+// Returns the Newton step count (negative: bisection fallback, 0: no
+// admissible root).  out = (p*, u*, rho*_L, rho*_R).
+__device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, double gL, double pcL,
+                                             double rR, double uR, double pR, double gR, double pcR,
+                                             double rtol, int maxit, bool have_guess, double guess,
+                                             double out[4])
+{
+    RSide L, R;
+    rside_init(L, rL, uL, pL, gL, pcL);
+    rside_init(R, rR, uR, pR, gR, pcR);
+    const double du = uR - uL;
+    const double plo = -fmin(pcL, pcR);
+    const double glo = rside_f(L, plo) + rside_f(R, plo) + du;
+    if (!(glo < 0.0)) {
+        out[0] = out[1] = out[2] = out[3] = __builtin_nan("");
+        return 0;
+    }
+    const double ZL = L.rc, ZR = R.rc;
+    const double pac = (ZR * pL + ZL * pR + ZL * ZR * (uL - uR)) / (ZL + ZR);
+    double p = fmax(pac, plo + 1e-6 * fmin(pL - plo, pR - plo));
+    if (have_guess) p = guess;
+    int it = 0;
+    bool conv = false;
+    while (it < maxit) {
+        double dLf, dRf;
+        const double gv = rside_f(L, p, dLf) + rside_f(R, p, dRf) + du;
+        double pn = p - gv / (dLf + dRf);
+        if (pn <= plo) pn = plo + 0.5 * (p - plo);
+        ++it;
+        conv = fabs(pn - p) <= rtol * (pn - plo);
+        p = pn;
+        if (conv) break;
+    }
+    if (!conv) {
+        double a = plo, b = fmax(pL, pR);
+        for (int k = 0; k < 2000 && rside_f(L, b) + rside_f(R, b) + du < 0.0; ++k) b = plo + 2.0 * (b - plo);
+        for (int k = 0; k < 400 && (b - a) > rtol * (b - plo); ++k) {
+            const double m = 0.5 * (a + b);
+            if (rside_f(L, m) + rside_f(R, m) + du < 0.0) a = m; else b = m;
+        }
+        p = 0.5 * (a + b);
+        it = -it;
+    }
+    out[0] = p;
+    out[1] = 0.5 * (uL + uR) + 0.5 * (rside_f(R, p) - rside_f(L, p));
+    out[2] = rside_star_rho(L, gL, p);
+    out[3] = rside_star_rho(R, gR, p);
+    return it;
+}
+
+// Acoustic (linearised) guess and the admissible floor, for judging a
+// learned guess.
+__device__ __forceinline__ double riemann_g(double rL, double uL, double pL, double gL, double pcL,
+                                           double rR, double uR, double pR, double gR, double pcR,
+                                           double p)
+{
+    RSide L, R;
+    rside_init(L, rL, uL, pL, gL, pcL);
+    rside_init(R, rR, uR, pR, gR, pcR);
+    return rside_f(L, p) + rside_f(R, p) + uR - uL;
+}
+
+// --------------------------------------------------------- atomics --------
+__device__ __forceinline__ void atomic_max_nonneg(unsigned long long* addr, double v)
+{
+    atomicMax(addr, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void report_error(int* err, long long* err_cell, int code, long long cell)
+{
+    atomicCAS(err, 0, code);
+    atomicMin(err_cell, cell);
+}
+
+// Source index along one axis for a (possibly ghost) index i in [-2, n+1]
+// under the boundary types of the two ends; 'mirror' is set when the ghost
+// is a wall image (its normal velocity must be reversed).
+__device__ __forceinline__ int bc_index(int i, int n, int blo, int bhi, bool& mirror)
+{
+    mirror = false;
+    if (i < 0) {
+        if (blo == 2) i += n;
+        else if (blo == 1) { i = -1 - i; mirror = true; }
+        else i = 0;
+    } else if (i >= n) {
+        if (bhi == 2) i -= n;
+        else if (bhi == 1) { i = 2 * n - 1 - i; mirror = true; }
+        else i = n - 1;
+    }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+}  // namespace m2c

@@ -1,0 +1,64 @@
+// m2c_internal.h -- structures shared by the host runtime and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace m2c {
+
+enum { BC_TRANSMISSIVE = 0, BC_WALL = 1, BC_PERIODIC = 2 };
+enum { ST_OK = 0, ST_NONPHYSICAL = -2, ST_RIEMANN = -3, ST_OVERFLOW = -7 };
+
+// Device-resident scalars of one simulation.  Everything a step needs from
+// the previous step (dt, error state) stays on the device so a whole step
+// can be enqueued (or graph-replayed) without host round trips.
+struct DevScalars {
+    unsigned long long lam_bits;   // max_i lambda_i of the current state (bits of a
+                                   // non-negative double: integer max == double max)
+    double dt;                     // dt of the step in flight
+    double t;                      // simulated time
+    int32_t qlen;                  // interface faces in the work queue
+    int32_t qlen_prev;             // queue length before the last compaction
+    int32_t nflip;                 // flipped cells of the step in flight
+    int32_t err;                   // 0 or the first error status
+    long long err_cell;            // first failing cell (min over reports)
+    long long steps_done;
+    long long solves, newton_iters, fallbacks, flips, orphans, mlp_fallbacks;
+    double dt_last;
+    int32_t chi_dirty;             // material field changed since the last compaction
+    int32_t pad;
+};
+
+// One simulation grid as the kernels see it.
+struct Grid {
+    int nx, ny, nz;
+    long long N;
+    int act[3];                    // axis has more than one cell
+    int bc[6];
+    double h[3], rh[3], rh6[3];    // width, 1/width, 1/(6 width)
+    double gamma[2], pc[2], gpc[2], inv_gm1[2];
+    double alpha;
+    double cfl, dt_fixed;
+    double rtol;
+    int maxit;
+    int guess;
+};
+
+// Device buffers of one simulation.
+struct Bufs {
+    double* W[2];                  // two full states [6][N]: rho, rho u, rho v, rho w, rho E, phi
+    double* W1;                    // RK stage state [6][N]
+    uint8_t* chi[2];               // material ids of the two states
+    int32_t* queue;                // interface face ids, ascending
+    int32_t* fslot;                // [3N] face id -> queue index, or -1
+    double* fluxF;                 // [10][qcap]: flux for the lower cell (5), upper cell (5)
+    double* star;                  // [8][qcap]: p*, u*, rho*_L, rho*_R, vt1_L, vt2_L, vt1_R, vt2_R
+    int32_t* flips;                // [N] flipped cells of the step in flight
+    int32_t* blockcnt;             // compaction partial counts
+    DevScalars* sc;
+    long long qcap;
+    int nblk_compact;
+};
+
+struct MlpDev;                     // learned star-pressure guess (optional)
+
+}  // namespace m2c

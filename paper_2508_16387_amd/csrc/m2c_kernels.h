@@ -1,0 +1,81 @@
+// m2c_kernels.h -- launch interfaces of the device kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "m2c_internal.h"
+
+namespace m2c {
+
+// Arguments of one bulk Runge-Kutta stage launch.
+struct StageArgs {
+    Grid g;
+    const double* Win;             // stage input state [6][N]
+    const double* W0;              // start-of-step state [6][N] (stage 2)
+    double* Wout;                  // stage output [6][N]
+    const uint8_t* chi;            // material ids frozen for the step
+    uint8_t* chi_next;             // stage 2: ids of the new level set
+    int32_t* flips;                // stage 2: flipped cells (append)
+    const int32_t* fslot;          // [3N] face -> queue slot or -1
+    const double* fluxF;           // [10][qcap] one-sided interface fluxes
+    long long qcap;
+    DevScalars* sc;
+    int tiles_x, tiles_y, tiles_z, kz;
+};
+
+// Interface work-queue arguments (compaction, FIVER, phase update).
+struct IfaceArgs {
+    Grid g;
+    const double* Win;             // stage input state [6][N]
+    const uint8_t* chi;            // ids frozen for the step
+    int32_t* queue;
+    int32_t* fslot;
+    double* fluxF;                 // [10][qcap]
+    double* star;                  // [8][qcap]
+    int32_t* blockcnt;
+    long long qcap;
+    int nblk;                      // compaction blocks
+    DevScalars* sc;
+    const double* mlp;             // learned-guess parameters (device, FP32 as double) or null
+};
+
+struct PhaseArgs {
+    Grid g;
+    double* W;                     // new state [6][N] (updated in place at flipped cells)
+    const uint8_t* chi_old;        // ids of the step
+    const uint8_t* chi_new;        // ids of the new level set
+    const int32_t* flips;
+    const int32_t* fslot;
+    const double* star;
+    long long qcap;
+    DevScalars* sc;
+};
+
+bool stage_tile_supported(int tx, int ty);
+hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
+
+// Interface kernels (k_interface.hip).
+constexpr int COMPACT_THREADS = 256;
+constexpr int COMPACT_CELLS_PER_THREAD = 16;
+constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THREAD;
+hipError_t launch_compact(const IfaceArgs& a, hipStream_t s);
+hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s);
+hipError_t launch_phase(const PhaseArgs& a, hipStream_t s);
+
+// Per-step bookkeeping and state conversion (k_misc.hip).
+hipError_t launch_begin_step(DevScalars* sc, const Grid& g, double dt_imposed, hipStream_t s);
+hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
+hipError_t launch_lambda(const Grid& g, const double* W, const uint8_t* chi, DevScalars* sc, hipStream_t s);
+hipError_t launch_prim_to_cons(const Grid& g, const double* prim6, double* W, uint8_t* chi,
+                               DevScalars* sc, hipStream_t s);
+hipError_t launch_cons_to_prim(const Grid& g, const double* W, const uint8_t* chi, double* prim6,
+                               hipStream_t s);
+hipError_t launch_chi_from_phi(const Grid& g, const double* W, uint8_t* chi, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t s);
+hipError_t launch_hllc_points(long long n, const double* qL, const double* qR, double gamma, double pc,
+                              bool mixed, double* F, hipStream_t s);
+hipError_t launch_riemann_points(long long n, const double* in, const double* eos, int guess,
+                                 const double* mlp, double rtol, int maxit, double* out, int32_t* iters,
+                                 int32_t* nvac, hipStream_t s);
+
+}  // namespace m2c
