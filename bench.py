@@ -39,7 +39,27 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps timed for the CPU baseline (bounded sample)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy five times (reference "
+                         "for scaling hardware byte counters to bytes)")
     return ap.parse_args()
+
+
+def measured_traffic(precision):
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summary, if it was taken on the stage-kernel sources as they are now."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_stage_traffic.json")
+    if precision != "fp64" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    m = hashlib.sha256()
+    for src in rec["sources"]:
+        m.update(open(os.path.join(ROOT, src), "rb").read())
+    if m.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["bytes_per_launch_mean"]
 
 
 def cpu_baseline(problem, steps):
@@ -65,10 +85,20 @@ def main():
         sys.exit(2)
     import torch
 
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copy_probe_bytes_written": y.numel() * 8}))
+        return
+
     import paper_2508_16387_amd as m2c
     import workloads as W
 
-    torch.cuda.set_device(0)
     p = W.shock_bubble(args.seed, n=args.n)
     prec = m2c.M2C_PREC_MIXED if args.precision == "mixed" else m2c.M2C_PREC_FP64
     sim = m2c.Sim(m2c.config_for(p, precision=prec))
@@ -108,7 +138,7 @@ def main():
         "config": {"workload": f"shock_bubble_{args.n}^3", "grid": [args.n] * 3, "steps": args.steps,
                    "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
                      "kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "fiver": {"solves": st["riemann_solves"], "ms": st["ms_fiver"],

@@ -10,7 +10,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libm2c.so")
+# M2C_LIBRARY may name another build of the same library (tuning runs).
+_LIB_PATH = os.environ.get("M2C_LIBRARY") or os.path.join(_HERE, "libm2c.so")
 
 M2C_OK, M2C_ERR_ARG, M2C_ERR_NONPHYSICAL, M2C_ERR_RIEMANN = 0, -1, -2, -3
 M2C_ERR_DEVICE, M2C_ERR_STATE, M2C_ERR_UNIMPLEMENTED, M2C_ERR_NOMEM = -4, -5, -6, -7

@@ -11,49 +11,45 @@
 // x fastest, no ghost cells (boundary images are produced on load).
 //
 // Work decomposition (MI355X): a block owns a TX x TY tile of an xy-plane
-// and marches along z over KZ planes (2.5D).  Per plane the tile's
+// and marches along z over kz planes (2.5D).  Per plane the tile's
 // primitives plus a 2-cell halo ring are staged in LDS; the x- and y-faces
-// of the tile are evaluated once each as a flat work list over the block's
-// threads and parked in LDS; the z-face above each column is computed by
-// the column's own thread from a 3-plane register window and carried to
-// the next plane.  Each face flux is therefore evaluated once.  Faces whose
-// two cells hold different materials are not evaluated here: their two
-// one-sided FIVER fluxes come from the interface kernel through the face ->
-// queue slot map.  Blocks are renumbered so that each XCD receives a
-// contiguous run of neighbouring tiles (halo reuse in its L2).
+// of the tile are evaluated once each as one flat work list over the
+// block's threads, by one code path whose only axis dependence is an LDS
+// stride and a component permutation (no divergence between x and y faces
+// inside a wavefront), and parked in LDS; the z-face above each column is
+// computed by the column's own thread from a 3-plane register window and
+// carried to the next plane.  Each face flux is therefore evaluated once.
+// Faces whose two cells hold different materials are not evaluated here:
+// their two one-sided FIVER fluxes come from the interface kernel through
+// the face -> queue slot map.  Blocks are renumbered so that each XCD
+// receives a contiguous run of neighbouring tiles (halo reuse in its L2).
+//
+// Register budget: the column window keeps primitives of three planes,
+// the z-slope and lower z-flux of the current plane, phi of five planes and
+// the raw state of the prefetched plane; the stage-input state of the cell
+// being updated is re-read (a cache hit) instead of being carried.
 #include "m2c_device.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
 
+#ifndef M2C_STAGE_WAVES
+// Minimum waves per SIMD imposed on the register allocation.  Measured on
+// the 128^3 shock-bubble stage: an imposed 2 or 3 waves (spills) is slower
+// than the unconstrained allocation, which lands at 2 waves per SIMD.
+#define M2C_STAGE_WAVES 1
+#endif
+
 namespace m2c {
 
-// Flux through a face with normal axis D from the two reconstructed face
-// states given in global component order (rho, u, v, w, p); result in global
-// order (mass, x-, y-, z-momentum, energy).
-template <int D, typename T>
-__device__ __forceinline__ void face_flux(const T qa[5], const T qb[5], T g, T pc, T gpc, T igm1, T F[5])
-{
-    constexpr int N = 1 + D, T1 = 1 + (D + 1) % 3, T2 = 1 + (D + 2) % 3;
-    T Fr[5];
-    hllc<T>(qa[0], qa[N], qa[T1], qa[T2], qa[4], qb[0], qb[N], qb[T1], qb[T2], qb[4], g, pc, gpc, igm1, Fr);
-    F[0] = Fr[0];
-    F[N] = Fr[1];
-    F[T1] = Fr[2];
-    F[T2] = Fr[3];
-    F[4] = Fr[4];
-}
-
 template <int STAGE, int TX, int TY, typename TF>
-__global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
+__global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageArgs a)
 {
-    constexpr int NT = TX * TY, LX = TX + 4, LY = TY + 4;
-    constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
-    __shared__ double sQ[6][LY][LX];
-    __shared__ uint8_t sX[LY][LX];
-    __shared__ double sFx[5][TY][TX + 1];
-    __shared__ double sFy[5][TY + 1][TX];
-    __shared__ int sSx[TY][TX + 1];
-    __shared__ int sSy[TY + 1][TX];
+    constexpr int NT = TX * TY, LX = TX + 4, LY = TY + 4, PL = LX * LY;
+    constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NF = NXF + NYF;
+    __shared__ double sQ[6 * PL];          // primitives rho,u,v,w,p and phi of the plane + halo
+    __shared__ uint8_t sX[PL];             // material ids
+    __shared__ double sF[5 * NF];          // in-plane face fluxes seen by the lower cell
+    __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
 
@@ -64,6 +60,7 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
     if (threadIdx.x == 0) sErr = sc->err;
     __syncthreads();
     if (sErr != 0) return;
+
     const Grid& G = a.g;
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const long long N = G.N;
@@ -91,105 +88,123 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
     const int sj = bc_index(gj, ny, G.bc[2], G.bc[3], miry);
     if (!xact) mirx = false;
     if (!yact) miry = false;
-    const long long sxy = (long long)nx * ny;
-    const long long col = si + (long long)nx * sj;
-
+    const uint32_t sxy = (uint32_t)nx * ny;
+    const uint32_t col = si + (uint32_t)nx * sj;
     const TF alpha = (TF)G.alpha;
 
-    // Load one cell of this thread's column at plane k (any k in [-2, nz+1]).
-    auto load_col = [&](int k, double q[5], double w[6], uint8_t& x) {
-        bool mz = false;
+    // Raw state of this thread's column at plane k (any k in [-2, nz+1]).
+    auto load_raw = [&](int k, double w[6], uint8_t& x, bool& mz) {
         const int sk = bc_index(k, nz, G.bc[4], G.bc[5], mz);
-        const long long c = col + sxy * sk;
+        const uint32_t c = col + sxy * sk;
 #pragma unroll
-        for (int v = 0; v < 6; ++v) w[v] = Win[v * N + c];
+        for (int v = 0; v < 6; ++v) w[v] = ldf(Win + v * N, c);
         x = chi[c];
+    };
+    // Primitives of a raw state, velocities mirrored at wall images.
+    auto to_prim = [&](const double w[6], uint8_t x, bool mz, double q[5]) {
         double u, vv, ww;
-        const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], G.gamma[x] - 1.0, G.gpc[x], u, vv, ww);
+        const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
         q[0] = w[0];
         q[1] = mirx ? -u : u;
         q[2] = miry ? -vv : vv;
         q[3] = (mz && zact) ? -ww : ww;
         q[4] = p;
     };
-
     // z-slope of a cell from its column neighbours (zero next to another
     // material along z).
-    auto zslope = [&](const double qm[5], const double q0[5], const double qp[5],
-                      uint8_t xm, uint8_t x0, uint8_t xp, TF s[5]) {
+    auto zslope = [&](const double qm[5], const double q0[5], const double qp[5], uint8_t xm, uint8_t x0,
+                      uint8_t xp, TF s[5]) {
         const bool flat = (xm != x0) || (xp != x0);
 #pragma unroll
         for (int v = 0; v < 5; ++v)
             s[v] = flat ? TF(0) : mc_slope<TF>(TF(q0[v] - qm[v]), TF(qp[v] - q0[v]), alpha);
     };
-
-    // z-face between planes k (lower) and k+1 of this column: flux seen by the
-    // lower cell (Fl) and by the upper cell (Fu).
-    auto zface = [&](int k, const double ql[5], const TF sl[5], uint8_t xl,
-                     const double qu[5], const TF su[5], uint8_t xu, double Fl[5], double Fu[5]) {
+    // z-face between planes k (lower) and k+1: flux seen by the lower cell
+    // (Fl) and by the upper cell (Fu).
+    auto zface = [&](int k, const double ql[5], const TF sl[5], uint8_t xl, const double qu[5], const TF su[5],
+                     uint8_t xu, double Fl[5], double Fu[5]) {
+        double f0, f1, f2, f3, f4, g0, g1, g2, g3, g4;
         if (xl == xu) {
-            TF fa[5], fb[5], F[5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                fa[v] = TF(ql[v]) + TF(0.5) * sl[v];
-                fb[v] = TF(qu[v]) - TF(0.5) * su[v];
-            }
-            face_flux<2, TF>(fa, fb, TF(G.gamma[xl]), TF(G.pc[xl]), TF(G.gpc[xl]), TF(G.inv_gm1[xl]), F);
-#pragma unroll
-            for (int v = 0; v < 5; ++v) Fl[v] = Fu[v] = (double)F[v];
+            TF Fr[5];
+            const TF g = TF(pick(G.gamma, xl)), pc = TF(pick(G.pc, xl)), gpc = TF(pick(G.gpc, xl)),
+                     igm1 = TF(pick(G.inv_gm1, xl));
+            // face frame: normal w, tangential u, v
+            hllc<TF>(TF(ql[0]) + TF(0.5) * sl[0], TF(ql[3]) + TF(0.5) * sl[3], TF(ql[1]) + TF(0.5) * sl[1],
+                     TF(ql[2]) + TF(0.5) * sl[2], TF(ql[4]) + TF(0.5) * sl[4], TF(qu[0]) - TF(0.5) * su[0],
+                     TF(qu[3]) - TF(0.5) * su[3], TF(qu[1]) - TF(0.5) * su[1], TF(qu[2]) - TF(0.5) * su[2],
+                     TF(qu[4]) - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
+            g0 = f0 = (double)Fr[0];
+            g3 = f3 = (double)Fr[1];
+            g1 = f1 = (double)Fr[2];
+            g2 = f2 = (double)Fr[3];
+            g4 = f4 = (double)Fr[4];
         } else {
             bool m;
             const int lk = bc_index(k, nz, G.bc[4], G.bc[5], m);
-            const long long fid = 3 * (col + sxy * lk) + 2;
+            const uint32_t fid = 3 * (col + sxy * lk) + 2;
             const int q = a.fslot[fid];
-            if (q < 0) {
-                report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-#pragma unroll
-                for (int v = 0; v < 5; ++v) Fl[v] = Fu[v] = 0.0;
-                return;
-            }
-#pragma unroll
-            for (int v = 0; v < 5; ++v) {
-                Fl[v] = a.fluxF[v * a.qcap + q];
-                Fu[v] = a.fluxF[(5 + v) * a.qcap + q];
-            }
+            if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
+            const uint32_t Q = (uint32_t)a.qcap, qq = q < 0 ? 0 : q;
+            f0 = a.fluxF[qq];
+            f1 = a.fluxF[Q + qq];
+            f2 = a.fluxF[2 * Q + qq];
+            f3 = a.fluxF[3 * Q + qq];
+            f4 = a.fluxF[4 * Q + qq];
+            g0 = a.fluxF[5 * Q + qq];
+            g1 = a.fluxF[6 * Q + qq];
+            g2 = a.fluxF[7 * Q + qq];
+            g3 = a.fluxF[8 * Q + qq];
+            g4 = a.fluxF[9 * Q + qq];
         }
+        Fl[0] = f0; Fl[1] = f1; Fl[2] = f2; Fl[3] = f3; Fl[4] = f4;
+        Fu[0] = g0; Fu[1] = g1; Fu[2] = g2; Fu[3] = g3; Fu[4] = g4;
     };
 
     // ---- prologue: column window and the z-face below plane kz0 ----------
     double Q0[5], Q1[5], Q2[5];       // primitives at k, k+1, k+2
-    double W0c[6], W1c[6], W2c[6];    // stage-input state at k, k+1, k+2
     double PH[5];                     // phi at k-2 .. k+2
-    uint8_t Xm, X0, X1, X2;           // ids at k-1 .. k+2
+    uint8_t X0, X1, X2;               // ids at k .. k+2
     TF S0[5];                         // z-slope of plane k
     double Fzlo[5];                   // flux seen by plane k through its lower z-face
     {
-        double qm2[5], qm1[5], w[6];
-        uint8_t xm2;
-        load_col(kz0 - 2, qm2, w, xm2);
-        PH[0] = w[5];
-        load_col(kz0 - 1, qm1, w, Xm);
-        PH[1] = w[5];
-        load_col(kz0, Q0, W0c, X0);
-        PH[2] = W0c[5];
-        load_col(kz0 + 1, Q1, W1c, X1);
-        PH[3] = W1c[5];
-        load_col(kz0 + 2, Q2, W2c, X2);
-        PH[4] = W2c[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) Fzlo[v] = 0.0;
+        double w[6], qm1[5];
+        uint8_t xm1;
+        bool mz;
         if (zact) {
-            zslope(qm1, Q0, Q1, Xm, X0, X1, S0);
-            if (inside) {
-                // slope of plane kz0-1 needs plane kz0-2
-                TF Sm[5];
-                zslope(qm2, qm1, Q0, xm2, Xm, X0, Sm);
-                double Fl[5];
-                zface(kz0 - 1, qm1, Sm, Xm, Q0, S0, X0, Fl, Fzlo);
-            }
+            double qm2[5];
+            uint8_t xm2;
+            load_raw(kz0 - 2, w, xm2, mz);
+            PH[0] = w[5];
+            to_prim(w, xm2, mz, qm2);
+            load_raw(kz0 - 1, w, xm1, mz);
+            PH[1] = w[5];
+            to_prim(w, xm1, mz, qm1);
+            load_raw(kz0, w, X0, mz);
+            PH[2] = w[5];
+            to_prim(w, X0, mz, Q0);
+            load_raw(kz0 + 1, w, X1, mz);
+            PH[3] = w[5];
+            to_prim(w, X1, mz, Q1);
+            load_raw(kz0 + 2, w, X2, mz);
+            PH[4] = w[5];
+            to_prim(w, X2, mz, Q2);
+            zslope(qm1, Q0, Q1, xm1, X0, X1, S0);
+            TF Sm[5];
+            zslope(qm2, qm1, Q0, xm2, xm1, X0, Sm);
+            double Fl[5];
+            if (inside) zface(kz0 - 1, qm1, Sm, xm1, Q0, S0, X0, Fl, Fzlo);
         } else {
+            load_raw(kz0, w, X0, mz);
+            to_prim(w, X0, mz, Q0);
+            PH[2] = w[5];
 #pragma unroll
-            for (int v = 0; v < 5; ++v) S0[v] = TF(0);
+            for (int v = 0; v < 5; ++v) {
+                S0[v] = TF(0);
+                Fzlo[v] = 0.0;
+                Q1[v] = Q2[v] = Q0[v];
+            }
+            PH[0] = PH[1] = PH[3] = PH[4] = PH[2];
+            X1 = X2 = X0;
         }
     }
 
@@ -198,21 +213,23 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
 
     for (int k = kz0; k < kz1; ++k) {
         // lead load of plane k+3 (consumed at the end of the iteration)
-        double Qn[5], Wn[6];
-        uint8_t Xn;
-        if (zact) load_col(k + 3, Qn, Wn, Xn);
+        double Wn[6];
+        uint8_t Xn = 0;
+        bool mzn = false;
+        if (zact) load_raw(k + 3, Wn, Xn, mzn);
 
         // (1) own plane-k values into the LDS tile
+        {
+            const int o = (ty + 2) * LX + tx + 2;
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sQ[v][ty + 2][tx + 2] = Q0[v];
-        sQ[5][ty + 2][tx + 2] = PH[2];
-        sX[ty + 2][tx + 2] = X0;
-
+            for (int v = 0; v < 5; ++v) sQ[v * PL + o] = Q0[v];
+            sQ[5 * PL + o] = PH[2];
+            sX[o] = X0;
+        }
         // (2) halo ring of plane k (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX columns)
         {
             const int nxh = xact ? 4 * TY : 0, nyh = yact ? 4 * TX : 0;
-            bool mz;
-            const int sk = bc_index(k, nz, G.bc[4], G.bc[5], mz);
+            const uint32_t plane = sxy * k;
             for (int h = tid; h < nxh + nyh; h += NT) {
                 int li, lj;
                 if (h < nxh) {
@@ -228,95 +245,79 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
                 bool mx = false, my = false;
                 const int hi_ = bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
                 const int hj_ = bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
-                const long long c = hi_ + (long long)nx * hj_ + sxy * sk;
+                const uint32_t c = hi_ + nx * hj_ + plane;
                 const uint8_t x = chi[c];
                 double u, vv, ww;
-                const double r0 = Win[c];
-                const double p = eos_prim(r0, Win[N + c], Win[2 * N + c], Win[3 * N + c], Win[4 * N + c],
-                                          G.gamma[x] - 1.0, G.gpc[x], u, vv, ww);
-                sQ[0][lj][li] = r0;
-                sQ[1][lj][li] = (mx && xact) ? -u : u;
-                sQ[2][lj][li] = (my && yact) ? -vv : vv;
-                sQ[3][lj][li] = ww;
-                sQ[4][lj][li] = p;
-                sQ[5][lj][li] = Win[5 * N + c];
-                sX[lj][li] = x;
+                const double r0 = ldf(Win, c);
+                const double p = eos_prim(r0, ldf(Win + N, c), ldf(Win + 2 * N, c), ldf(Win + 3 * N, c), ldf(Win + 4 * N, c),
+                                          pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
+                const int o = lj * LX + li;
+                sQ[o] = r0;
+                sQ[PL + o] = (mx && xact) ? -u : u;
+                sQ[2 * PL + o] = (my && yact) ? -vv : vv;
+                sQ[3 * PL + o] = ww;
+                sQ[4 * PL + o] = p;
+                sQ[5 * PL + o] = ldf(Win + 5 * N, c);
+                sX[o] = x;
             }
         }
         __syncthreads();
 
-        // (3) x- and y-faces of the tile as one work list
-        {
-            const int nxf = xact ? NXF : 0, nyf = yact ? NYF : 0;
-            for (int t = tid; t < nxf + nyf; t += NT) {
-                if (t < nxf) {
-                    const int fi = t % (TX + 1), lj = t / (TX + 1);
-                    const int gx = i0 + fi, gy = j0 + lj;
-                    if (gx > nx || gy >= ny) continue;
-                    const int r = lj + 2, ca = fi + 1, cb = fi + 2;
-                    const uint8_t xa = sX[r][ca], xb = sX[r][cb];
-                    if (xa == xb) {
-                        const bool fa = sX[r][ca - 1] != xa, fb = sX[r][cb + 1] != xb;
-                        TF qa[5], qb[5], F[5];
+        // (3) x- and y-faces of the tile as one work list, one code path
+        for (int t = tid; t < NF; t += NT) {
+            const bool isx = t < NXF;
+            const int tt = isx ? t : t - NXF;
+            const int W_ = isx ? TX + 1 : TX;          // faces per row of the list
+            const int fa = tt % W_, fb = tt / W_;
+            // LDS offsets of the two cells (A lower, B upper) and the step
+            const int step = isx ? 1 : LX;
+            const int oA = isx ? (fb + 2) * LX + (fa + 1) : (fb + 1) * LX + (fa + 2);
+            const int oB = oA + step;
+            const int gx = i0 + fa, gy = j0 + fb;       // x: face left of cell gx; y: below gy
+            const bool valid = isx ? (xact && gx <= nx && gy < ny) : (yact && gx < nx && gy <= ny);
+            if (!valid) continue;
+            const int nrm = isx ? 1 : 2, ta = isx ? 2 : 3, tb = isx ? 3 : 1;
+            const uint8_t xa = sX[oA], xb = sX[oB];
+            if (xa == xb) {
+                const bool flatA = sX[oA - step] != xa || sX[oB] != xa;
+                const bool flatB = sX[oA] != xb || sX[oB + step] != xb;
+                TF qa[5], qb[5];
+                const int comp[5] = {0, nrm, ta, tb, 4};
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) {
-                            const double m1 = sQ[v][r][ca - 1], a0 = sQ[v][r][ca];
-                            const double b0 = sQ[v][r][cb], p1 = sQ[v][r][cb + 1];
-                            const TF sa = fa ? TF(0) : mc_slope<TF>(TF(a0 - m1), TF(b0 - a0), alpha);
-                            const TF sb = fb ? TF(0) : mc_slope<TF>(TF(b0 - a0), TF(p1 - b0), alpha);
-                            qa[v] = TF(a0) + TF(0.5) * sa;
-                            qb[v] = TF(b0) - TF(0.5) * sb;
-                        }
-                        face_flux<0, TF>(qa, qb, TF(G.gamma[xa]), TF(G.pc[xa]), TF(G.gpc[xa]), TF(G.inv_gm1[xa]), F);
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) sFx[v][lj][fi] = (double)F[v];
-                        sSx[lj][fi] = -1;
-                    } else {
-                        bool m;
-                        const int lx = bc_index(gx - 1, nx, G.bc[0], G.bc[1], m);
-                        const long long fid = 3 * (lx + (long long)nx * gy + sxy * k);
-                        const int q = a.fslot[fid];
-                        if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-                        const int qq = q < 0 ? 0 : q;
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) sFx[v][lj][fi] = a.fluxF[v * a.qcap + qq];
-                        sSx[lj][fi] = qq;
-                    }
-                } else {
-                    const int tt = t - nxf;
-                    const int li = tt % TX, fj = tt / TX;
-                    const int gx = i0 + li, gy = j0 + fj;
-                    if (gx >= nx || gy > ny) continue;
-                    const int c = li + 2, ra = fj + 1, rb = fj + 2;
-                    const uint8_t xa = sX[ra][c], xb = sX[rb][c];
-                    if (xa == xb) {
-                        const bool fa = sX[ra - 1][c] != xa, fb = sX[rb + 1][c] != xb;
-                        TF qa[5], qb[5], F[5];
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) {
-                            const double m1 = sQ[v][ra - 1][c], a0 = sQ[v][ra][c];
-                            const double b0 = sQ[v][rb][c], p1 = sQ[v][rb + 1][c];
-                            const TF sa = fa ? TF(0) : mc_slope<TF>(TF(a0 - m1), TF(b0 - a0), alpha);
-                            const TF sb = fb ? TF(0) : mc_slope<TF>(TF(b0 - a0), TF(p1 - b0), alpha);
-                            qa[v] = TF(a0) + TF(0.5) * sa;
-                            qb[v] = TF(b0) - TF(0.5) * sb;
-                        }
-                        face_flux<1, TF>(qa, qb, TF(G.gamma[xa]), TF(G.pc[xa]), TF(G.gpc[xa]), TF(G.inv_gm1[xa]), F);
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) sFy[v][fj][li] = (double)F[v];
-                        sSy[fj][li] = -1;
-                    } else {
-                        bool m;
-                        const int ly = bc_index(gy - 1, ny, G.bc[2], G.bc[3], m);
-                        const long long fid = 3 * (gx + (long long)nx * ly + sxy * k) + 1;
-                        const int q = a.fslot[fid];
-                        if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-                        const int qq = q < 0 ? 0 : q;
-#pragma unroll
-                        for (int v = 0; v < 5; ++v) sFy[v][fj][li] = a.fluxF[v * a.qcap + qq];
-                        sSy[fj][li] = qq;
-                    }
+                for (int v = 0; v < 5; ++v) {
+                    const double* s = sQ + comp[v] * PL;
+                    const double m1 = s[oA - step], a0 = s[oA], b0 = s[oB], p1 = s[oB + step];
+                    const TF sa = flatA ? TF(0) : mc_slope<TF>(TF(a0 - m1), TF(b0 - a0), alpha);
+                    const TF sb = flatB ? TF(0) : mc_slope<TF>(TF(b0 - a0), TF(p1 - b0), alpha);
+                    qa[v] = TF(a0) + TF(0.5) * sa;
+                    qb[v] = TF(b0) - TF(0.5) * sb;
                 }
+                TF Fr[5];
+                hllc<TF>(qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], TF(pick(G.gamma, xa)),
+                         TF(pick(G.pc, xa)), TF(pick(G.gpc, xa)), TF(pick(G.inv_gm1, xa)), Fr);
+                sF[t] = (double)Fr[0];
+                sF[nrm * NF + t] = (double)Fr[1];
+                sF[ta * NF + t] = (double)Fr[2];
+                sF[tb * NF + t] = (double)Fr[3];
+                sF[4 * NF + t] = (double)Fr[4];
+                sS[t] = -1;
+            } else {
+                bool m;
+                uint32_t lower;
+                if (isx) {
+                    const int lx = bc_index(gx - 1, nx, G.bc[0], G.bc[1], m);
+                    lower = lx + (uint32_t)nx * gy;
+                } else {
+                    const int ly = bc_index(gy - 1, ny, G.bc[2], G.bc[3], m);
+                    lower = gx + (uint32_t)nx * ly;
+                }
+                const uint32_t fid = 3 * (lower + sxy * k) + (isx ? 0 : 1);
+                const int q = a.fslot[fid];
+                if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
+                const int qq = q < 0 ? 0 : q;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) sF[v * NF + t] = a.fluxF[v * a.qcap + qq];
+                sS[t] = qq;
             }
         }
 
@@ -331,25 +332,26 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
 
         // (5) residual and stage update of cell (gi, gj, k)
         if (inside) {
-            const long long c = col + sxy * k;
+            const uint32_t c = col + sxy * k;
             double acc[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) acc[v] = 0.0;
             if (xact) {
-                const int ql = sSx[ty][tx];
+                const int fl = ty * (TX + 1) + tx, fr = fl + 1;
+                const int ql = sS[fl];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sFx[v][ty][tx];
-                    acc[v] = (sFx[v][ty][tx + 1] - lo) * G.rh[0];
+                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sF[v * NF + fl];
+                    acc[v] = (sF[v * NF + fr] - lo) * G.rh[0];
                 }
-            } else {
-#pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] = 0.0;
             }
             if (yact) {
-                const int ql = sSy[ty][tx];
+                const int fl = NXF + ty * TX + tx, fr = fl + TX;
+                const int ql = sS[fl];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sFy[v][ty][tx];
-                    acc[v] += (sFy[v][ty + 1][tx] - lo) * G.rh[1];
+                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sF[v * NF + fl];
+                    acc[v] += (sF[v * NF + fr] - lo) * G.rh[1];
                 }
             }
             if (zact) {
@@ -357,37 +359,35 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
                 for (int v = 0; v < 5; ++v) acc[v] += (Fzhi[v] - Fzlo[v]) * G.rh[2];
             }
             // level set: third-order upwind-biased differences, upwinded by V_d of the cell
-            double Ls = 0.0;
             auto ls_term = [&](double V, double f0, double f1, double f2, double f3, double f4, double rh6) {
                 const double D = V > 0.0 ? (2.0 * f3 + 3.0 * f2 - 6.0 * f1 + f0) * rh6
                                : (V < 0.0 ? (-f4 + 6.0 * f3 - 3.0 * f2 - 2.0 * f1) * rh6 : 0.0);
                 return V * D;
             };
-            if (xact)
-                Ls += ls_term(Q0[1], sQ[5][ty + 2][tx], sQ[5][ty + 2][tx + 1], sQ[5][ty + 2][tx + 2],
-                              sQ[5][ty + 2][tx + 3], sQ[5][ty + 2][tx + 4], G.rh6[0]);
-            if (yact)
-                Ls += ls_term(Q0[2], sQ[5][ty][tx + 2], sQ[5][ty + 1][tx + 2], sQ[5][ty + 2][tx + 2],
-                              sQ[5][ty + 3][tx + 2], sQ[5][ty + 4][tx + 2], G.rh6[1]);
+            double Ls = 0.0;
+            const double* sp = sQ + 5 * PL + (ty + 2) * LX + tx + 2;
+            if (xact) Ls += ls_term(Q0[1], sp[-2], sp[-1], sp[0], sp[1], sp[2], G.rh6[0]);
+            if (yact) Ls += ls_term(Q0[2], sp[-2 * LX], sp[-LX], sp[0], sp[LX], sp[2 * LX], G.rh6[1]);
             if (zact) Ls += ls_term(Q0[3], PH[0], PH[1], PH[2], PH[3], PH[4], G.rh6[2]);
 
             double wn[6];
             if (STAGE == 1) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) wn[v] = W0c[v] + dt * (-acc[v]);
-                wn[5] = W0c[5] + dt * (-Ls);
+                for (int v = 0; v < 5; ++v) wn[v] = ldf(Win + v * N, c) + dt * (-acc[v]);
+                wn[5] = PH[2] + dt * (-Ls);
             } else {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) wn[v] = 0.5 * a.W0[v * N + c] + 0.5 * (W0c[v] + dt * (-acc[v]));
-                wn[5] = 0.5 * a.W0[5 * N + c] + 0.5 * (W0c[5] + dt * (-Ls));
+                for (int v = 0; v < 5; ++v)
+                    wn[v] = 0.5 * ldf(a.W0 + v * N, c) + 0.5 * (ldf(Win + v * N, c) + dt * (-acc[v]));
+                wn[5] = 0.5 * ldf(a.W0 + 5 * N, c) + 0.5 * (PH[2] + dt * (-Ls));
             }
             double u, vv, ww;
-            const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], G.gamma[X0] - 1.0, G.gpc[X0], u, vv, ww);
-            const bool ok = wn[0] > 0.0 && p + G.pc[X0] > 0.0 && isfinite(p) && isfinite(u) && isfinite(vv) &&
+            const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], pick(G.gamma, X0) - 1.0, pick(G.gpc, X0), u, vv, ww);
+            const bool ok = wn[0] > 0.0 && p + pick(G.pc, X0) > 0.0 && isfinite(p) && isfinite(u) && isfinite(vv) &&
                             isfinite(ww) && isfinite(wn[5]);
             if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
 #pragma unroll
-            for (int v = 0; v < 6; ++v) a.Wout[v * N + c] = wn[v];
+            for (int v = 0; v < 6; ++v) stf(a.Wout + v * N, c, wn[v]);
             if (STAGE == 2) {
                 const uint8_t xn = wn[5] < 0.0 ? 1 : 0;
                 a.chi_next[c] = xn;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
                     const int slot = atomicAdd(&sc->nflip, 1);
                     a.flips[slot] = (int)c;
                 } else if (ok) {
-                    const double cs = sqrt(G.gamma[X0] * (p + G.pc[X0]) / wn[0]);
+                    const double cs = sqrt(pick(G.gamma, X0) * (p + pick(G.pc, X0)) / wn[0]);
                     double l = 0.0;
                     if (xact) l += (fabs(u) + cs) * G.rh[0];
                     if (yact) l += (fabs(vv) + cs) * G.rh[1];
@@ -407,6 +407,8 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
 
         // (6) advance the column window
         if (zact) {
+            double Qn[5];
+            to_prim(Wn, Xn, mzn, Qn);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 Q0[v] = Q1[v];
@@ -415,18 +417,11 @@ __global__ __launch_bounds__(TX * TY) void k_stage(const StageArgs a)
                 S0[v] = S1[v];
                 Fzlo[v] = Fzup[v];
             }
-#pragma unroll
-            for (int v = 0; v < 6; ++v) {
-                W0c[v] = W1c[v];
-                W1c[v] = W2c[v];
-                W2c[v] = Wn[v];
-            }
             PH[0] = PH[1];
             PH[1] = PH[2];
             PH[2] = PH[3];
             PH[3] = PH[4];
             PH[4] = Wn[5];
-            Xm = X0;
             X0 = X1;
             X1 = X2;
             X2 = Xn;

@@ -84,7 +84,7 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
         return snprintf(why, n, "struct_size %u != %zu", c->struct_size, sizeof(m2c_config)), false;
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return snprintf(why, n, "grid extents must be >= 1"), false;
     const long long N = (long long)c->nx * c->ny * c->nz;
-    if (3 * N > (long long)INT_MAX) return snprintf(why, n, "grid too large for 32-bit face ids"), false;
+    if (N > (1ll << 29)) return snprintf(why, n, "grid larger than 2^29 cells"), false;
     for (int d = 0; d < 3; ++d) {
         if (!(c->hi[d] > c->lo[d])) return snprintf(why, n, "empty box along axis %d", d), false;
         const bool plo = c->bc[2 * d] == M2C_BC_PERIODIC, phi = c->bc[2 * d + 1] == M2C_BC_PERIODIC;
@@ -416,9 +416,9 @@ int m2c_create(const m2c_config* cfg, m2c_ctx** out)
     if (c->qcap > 65536 && c->qcap > N) c->qcap = N > 65536 ? N : 65536;
     c->nblk_compact = (int)((N + COMPACT_CELLS_PER_BLOCK - 1) / COMPACT_CELLS_PER_BLOCK);
 
-    // stage tiles: (tile_x, tile_y) or 32x8; planes per block tile_z or 8
-    c->tx = cfg->tile_x ? cfg->tile_x : 32;
-    c->ty = cfg->tile_y ? cfg->tile_y : 8;
+    // stage tiles: (tile_x, tile_y) or 16x16; planes per block tile_z or 8
+    c->tx = cfg->tile_x ? cfg->tile_x : 16;
+    c->ty = cfg->tile_y ? cfg->tile_y : 16;
     if (!cfg->tile_x && c->g.ny == 1) {
         c->tx = 64;
         c->ty = 2;

@@ -11,6 +11,23 @@
 
 namespace m2c {
 
+// Material parameter of material x (0 or 1) as a select rather than an
+// indexed load, so that per-lane material ids never force the parameter
+// arrays into private memory.
+__device__ __forceinline__ double pick(const double (&a)[2], int x) { return x ? a[1] : a[0]; }
+
+// Field access through a 32-bit byte offset from a wave-uniform base (grids
+// are limited to 2^29 cells), so the address lives in one VGPR instead of a
+// 64-bit pair per field and access.
+__device__ __forceinline__ double ldf(const double* base, uint32_t c)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + (c << 3));
+}
+__device__ __forceinline__ void stf(double* base, uint32_t c, double v)
+{
+    *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (c << 3)) = v;
+}
+
 // ---------------------------------------------------------------- EOS ------
 // Conservative -> primitive for one cell; returns the pressure.
 __device__ __forceinline__ double eos_prim(double r, double mx, double my, double mz, double E,
