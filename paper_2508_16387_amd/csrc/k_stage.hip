@@ -28,6 +28,12 @@
 // the z-slope and lower z-flux of the current plane, phi of five planes and
 // the raw state of the prefetched plane; the stage-input state of the cell
 // being updated is re-read (a cache hit) instead of being carried.
+//
+// Precision: TF is the type of reconstruction, HLLC and of the primitives
+// and single-material fluxes staged in LDS and registers (double, or float
+// for the mixed form).  EOS inversion, the level set, the FIVER fluxes of
+// interface faces (read straight from their FP64 buffer), the residual
+// accumulation and the update are FP64 in both forms.
 #include "m2c_device.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
@@ -38,17 +44,21 @@
 // than the unconstrained allocation, which lands at 2 waves per SIMD.
 #define M2C_STAGE_WAVES 1
 #endif
+#ifndef M2C_STAGE_WAVES_MIXED
+#define M2C_STAGE_WAVES_MIXED 4
+#endif
 
 namespace m2c {
 
 template <int STAGE, int TX, int TY, typename TF>
-__global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageArgs a)
+__global__ __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES) void k_stage(const StageArgs a)
 {
     constexpr int NT = TX * TY, LX = TX + 4, LY = TY + 4, PL = LX * LY;
     constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NF = NXF + NYF;
-    __shared__ double sQ[6 * PL];          // primitives rho,u,v,w,p and phi of the plane + halo
+    __shared__ TF sQ[5 * PL];              // primitives rho,u,v,w,p of the plane + halo
+    __shared__ double sPhi[PL];            // level set of the plane + halo (always FP64)
     __shared__ uint8_t sX[PL];             // material ids
-    __shared__ double sF[5 * NF];          // in-plane face fluxes seen by the lower cell
+    __shared__ TF sF[5 * NF];              // in-plane single-material face fluxes
     __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
@@ -101,77 +111,68 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
         x = chi[c];
     };
     // Primitives of a raw state, velocities mirrored at wall images.
-    auto to_prim = [&](const double w[6], uint8_t x, bool mz, double q[5]) {
+    auto to_prim = [&](const double w[6], uint8_t x, bool mz, TF q[5]) {
         double u, vv, ww;
         const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
-        q[0] = w[0];
-        q[1] = mirx ? -u : u;
-        q[2] = miry ? -vv : vv;
-        q[3] = (mz && zact) ? -ww : ww;
-        q[4] = p;
+        q[0] = TF(w[0]);
+        q[1] = TF(mirx ? -u : u);
+        q[2] = TF(miry ? -vv : vv);
+        q[3] = TF((mz && zact) ? -ww : ww);
+        q[4] = TF(p);
     };
     // z-slope of a cell from its column neighbours (zero next to another
     // material along z).
-    auto zslope = [&](const double qm[5], const double q0[5], const double qp[5], uint8_t xm, uint8_t x0,
-                      uint8_t xp, TF s[5]) {
+    auto zslope = [&](const TF qm[5], const TF q0[5], const TF qp[5], uint8_t xm, uint8_t x0, uint8_t xp,
+                      TF s[5]) {
         const bool flat = (xm != x0) || (xp != x0);
 #pragma unroll
-        for (int v = 0; v < 5; ++v)
-            s[v] = flat ? TF(0) : mc_slope<TF>(TF(q0[v] - qm[v]), TF(qp[v] - q0[v]), alpha);
+        for (int v = 0; v < 5; ++v) s[v] = flat ? TF(0) : mc_slope<TF>(q0[v] - qm[v], qp[v] - q0[v], alpha);
     };
-    // z-face between planes k (lower) and k+1: flux seen by the lower cell
-    // (Fl) and by the upper cell (Fu).
-    auto zface = [&](int k, const double ql[5], const TF sl[5], uint8_t xl, const double qu[5], const TF su[5],
-                     uint8_t xu, double Fl[5], double Fu[5]) {
-        double f0, f1, f2, f3, f4, g0, g1, g2, g3, g4;
+    // z-face between planes k (lower) and k+1.  A single-material face gets
+    // its HLLC flux in F and slot -1; an interface face returns the queue
+    // slot of its two FP64 one-sided FIVER fluxes.
+    auto zface = [&](int k, const TF ql[5], const TF sl[5], uint8_t xl, const TF qu[5], const TF su[5],
+                     uint8_t xu, TF F[5]) -> int {
         if (xl == xu) {
             TF Fr[5];
             const TF g = TF(pick(G.gamma, xl)), pc = TF(pick(G.pc, xl)), gpc = TF(pick(G.gpc, xl)),
                      igm1 = TF(pick(G.inv_gm1, xl));
             // face frame: normal w, tangential u, v
-            hllc<TF>(TF(ql[0]) + TF(0.5) * sl[0], TF(ql[3]) + TF(0.5) * sl[3], TF(ql[1]) + TF(0.5) * sl[1],
-                     TF(ql[2]) + TF(0.5) * sl[2], TF(ql[4]) + TF(0.5) * sl[4], TF(qu[0]) - TF(0.5) * su[0],
-                     TF(qu[3]) - TF(0.5) * su[3], TF(qu[1]) - TF(0.5) * su[1], TF(qu[2]) - TF(0.5) * su[2],
-                     TF(qu[4]) - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
-            g0 = f0 = (double)Fr[0];
-            g3 = f3 = (double)Fr[1];
-            g1 = f1 = (double)Fr[2];
-            g2 = f2 = (double)Fr[3];
-            g4 = f4 = (double)Fr[4];
-        } else {
-            bool m;
-            const int lk = bc_index(k, nz, G.bc[4], G.bc[5], m);
-            const uint32_t fid = 3 * (col + sxy * lk) + 2;
-            const int q = a.fslot[fid];
-            if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-            const uint32_t Q = (uint32_t)a.qcap, qq = q < 0 ? 0 : q;
-            f0 = a.fluxF[qq];
-            f1 = a.fluxF[Q + qq];
-            f2 = a.fluxF[2 * Q + qq];
-            f3 = a.fluxF[3 * Q + qq];
-            f4 = a.fluxF[4 * Q + qq];
-            g0 = a.fluxF[5 * Q + qq];
-            g1 = a.fluxF[6 * Q + qq];
-            g2 = a.fluxF[7 * Q + qq];
-            g3 = a.fluxF[8 * Q + qq];
-            g4 = a.fluxF[9 * Q + qq];
+            hllc<TF>(ql[0] + TF(0.5) * sl[0], ql[3] + TF(0.5) * sl[3], ql[1] + TF(0.5) * sl[1],
+                     ql[2] + TF(0.5) * sl[2], ql[4] + TF(0.5) * sl[4], qu[0] - TF(0.5) * su[0],
+                     qu[3] - TF(0.5) * su[3], qu[1] - TF(0.5) * su[1], qu[2] - TF(0.5) * su[2],
+                     qu[4] - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
+            F[0] = Fr[0];
+            F[3] = Fr[1];
+            F[1] = Fr[2];
+            F[2] = Fr[3];
+            F[4] = Fr[4];
+            return -1;
         }
-        Fl[0] = f0; Fl[1] = f1; Fl[2] = f2; Fl[3] = f3; Fl[4] = f4;
-        Fu[0] = g0; Fu[1] = g1; Fu[2] = g2; Fu[3] = g3; Fu[4] = g4;
+        bool m;
+        const int lk = bc_index(k, nz, G.bc[4], G.bc[5], m);
+        const uint32_t fid = 3 * (col + sxy * lk) + 2;
+        const int q = a.fslot[fid];
+        if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) F[v] = TF(0);
+        return q < 0 ? 0 : q;
     };
 
     // ---- prologue: column window and the z-face below plane kz0 ----------
-    double Q0[5], Q1[5], Q2[5];       // primitives at k, k+1, k+2
+    TF Q0[5], Q1[5], Q2[5];           // primitives at k, k+1, k+2
     double PH[5];                     // phi at k-2 .. k+2
     uint8_t X0, X1, X2;               // ids at k .. k+2
     TF S0[5];                         // z-slope of plane k
-    double Fzlo[5];                   // flux seen by plane k through its lower z-face
+    TF Fzlo[5];                       // single-material flux through the lower z-face of plane k
+    int qzlo = -1;                    // or the queue slot of that face's FIVER fluxes
     {
-        double w[6], qm1[5];
+        double w[6];
+        TF qm1[5];
         uint8_t xm1;
         bool mz;
         if (zact) {
-            double qm2[5];
+            TF qm2[5];
             uint8_t xm2;
             load_raw(kz0 - 2, w, xm2, mz);
             PH[0] = w[5];
@@ -191,8 +192,7 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
             zslope(qm1, Q0, Q1, xm1, X0, X1, S0);
             TF Sm[5];
             zslope(qm2, qm1, Q0, xm2, xm1, X0, Sm);
-            double Fl[5];
-            if (inside) zface(kz0 - 1, qm1, Sm, xm1, Q0, S0, X0, Fl, Fzlo);
+            if (inside) qzlo = zface(kz0 - 1, qm1, Sm, xm1, Q0, S0, X0, Fzlo);
         } else {
             load_raw(kz0, w, X0, mz);
             to_prim(w, X0, mz, Q0);
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 S0[v] = TF(0);
-                Fzlo[v] = 0.0;
+                Fzlo[v] = TF(0);
                 Q1[v] = Q2[v] = Q0[v];
             }
             PH[0] = PH[1] = PH[3] = PH[4] = PH[2];
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
             const int o = (ty + 2) * LX + tx + 2;
 #pragma unroll
             for (int v = 0; v < 5; ++v) sQ[v * PL + o] = Q0[v];
-            sQ[5 * PL + o] = PH[2];
+            sPhi[o] = PH[2];
             sX[o] = X0;
         }
         // (2) halo ring of plane k (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX columns)
@@ -252,12 +252,12 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
                 const double p = eos_prim(r0, ldf(Win + N, c), ldf(Win + 2 * N, c), ldf(Win + 3 * N, c), ldf(Win + 4 * N, c),
                                           pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
                 const int o = lj * LX + li;
-                sQ[o] = r0;
-                sQ[PL + o] = (mx && xact) ? -u : u;
-                sQ[2 * PL + o] = (my && yact) ? -vv : vv;
-                sQ[3 * PL + o] = ww;
-                sQ[4 * PL + o] = p;
-                sQ[5 * PL + o] = ldf(Win + 5 * N, c);
+                sQ[o] = TF(r0);
+                sQ[PL + o] = TF((mx && xact) ? -u : u);
+                sQ[2 * PL + o] = TF((my && yact) ? -vv : vv);
+                sQ[3 * PL + o] = TF(ww);
+                sQ[4 * PL + o] = TF(p);
+                sPhi[o] = ldf(Win + 5 * N, c);
                 sX[o] = x;
             }
         }
@@ -285,21 +285,21 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
                 const int comp[5] = {0, nrm, ta, tb, 4};
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    const double* s = sQ + comp[v] * PL;
-                    const double m1 = s[oA - step], a0 = s[oA], b0 = s[oB], p1 = s[oB + step];
-                    const TF sa = flatA ? TF(0) : mc_slope<TF>(TF(a0 - m1), TF(b0 - a0), alpha);
-                    const TF sb = flatB ? TF(0) : mc_slope<TF>(TF(b0 - a0), TF(p1 - b0), alpha);
-                    qa[v] = TF(a0) + TF(0.5) * sa;
-                    qb[v] = TF(b0) - TF(0.5) * sb;
+                    const TF* s = sQ + comp[v] * PL;
+                    const TF m1 = s[oA - step], a0 = s[oA], b0 = s[oB], p1 = s[oB + step];
+                    const TF sa = flatA ? TF(0) : mc_slope<TF>(a0 - m1, b0 - a0, alpha);
+                    const TF sb = flatB ? TF(0) : mc_slope<TF>(b0 - a0, p1 - b0, alpha);
+                    qa[v] = a0 + TF(0.5) * sa;
+                    qb[v] = b0 - TF(0.5) * sb;
                 }
                 TF Fr[5];
                 hllc<TF>(qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], TF(pick(G.gamma, xa)),
                          TF(pick(G.pc, xa)), TF(pick(G.gpc, xa)), TF(pick(G.inv_gm1, xa)), Fr);
-                sF[t] = (double)Fr[0];
-                sF[nrm * NF + t] = (double)Fr[1];
-                sF[ta * NF + t] = (double)Fr[2];
-                sF[tb * NF + t] = (double)Fr[3];
-                sF[4 * NF + t] = (double)Fr[4];
+                sF[t] = Fr[0];
+                sF[nrm * NF + t] = Fr[1];
+                sF[ta * NF + t] = Fr[2];
+                sF[tb * NF + t] = Fr[3];
+                sF[4 * NF + t] = Fr[4];
                 sS[t] = -1;
             } else {
                 bool m;
@@ -314,19 +314,16 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
                 const uint32_t fid = 3 * (lower + sxy * k) + (isx ? 0 : 1);
                 const int q = a.fslot[fid];
                 if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-                const int qq = q < 0 ? 0 : q;
-#pragma unroll
-                for (int v = 0; v < 5; ++v) sF[v * NF + t] = a.fluxF[v * a.qcap + qq];
-                sS[t] = qq;
+                sS[t] = q < 0 ? 0 : q;
             }
         }
 
         // (4) z-face above plane k for this column
-        TF S1[5];
-        double Fzhi[5], Fzup[5];
+        TF S1[5], Fzhi[5];
+        int qzhi = -1;
         if (zact) {
             zslope(Q0, Q1, Q2, X0, X1, X2, S1);
-            if (inside) zface(k, Q0, S0, X0, Q1, S1, X1, Fzhi, Fzup);
+            if (inside) qzhi = zface(k, Q0, S0, X0, Q1, S1, X1, Fzhi);
         }
         __syncthreads();
 
@@ -336,49 +333,64 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
             double acc[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) acc[v] = 0.0;
-            if (xact) {
-                const int fl = ty * (TX + 1) + tx, fr = fl + 1;
-                const int ql = sS[fl];
+            // flux difference across one axis: single-material fluxes from LDS
+            // (or registers for z), interface faces from the FP64 FIVER buffer
+            // (lower face: the flux seen by its upper cell, i.e. this one;
+            // upper face: the flux seen by its lower cell)
+            const long long Q = a.qcap;
+            auto axis = [&](int qlo, int qhi, const TF* flo, const TF* fhi, int stride, double rh) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sF[v * NF + fl];
-                    acc[v] = (sF[v * NF + fr] - lo) * G.rh[0];
+                    const double lo = qlo >= 0 ? a.fluxF[(5 + v) * Q + qlo] : (double)flo[v * stride];
+                    const double hi = qhi >= 0 ? a.fluxF[v * Q + qhi] : (double)fhi[v * stride];
+                    acc[v] += (hi - lo) * rh;
                 }
+            };
+            if (xact) {
+                const int fl = ty * (TX + 1) + tx, fr = fl + 1;
+                axis(sS[fl], sS[fr], sF + fl, sF + fr, NF, G.rh[0]);
             }
             if (yact) {
                 const int fl = NXF + ty * TX + tx, fr = fl + TX;
-                const int ql = sS[fl];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    const double lo = ql >= 0 ? a.fluxF[(5 + v) * a.qcap + ql] : sF[v * NF + fl];
-                    acc[v] += (sF[v * NF + fr] - lo) * G.rh[1];
-                }
+                axis(sS[fl], sS[fr], sF + fl, sF + fr, NF, G.rh[1]);
             }
-            if (zact) {
-#pragma unroll
-                for (int v = 0; v < 5; ++v) acc[v] += (Fzhi[v] - Fzlo[v]) * G.rh[2];
-            }
+            if (zact) axis(qzlo, qzhi, Fzlo, Fzhi, 1, G.rh[2]);
             // level set: third-order upwind-biased differences, upwinded by V_d of the cell
             auto ls_term = [&](double V, double f0, double f1, double f2, double f3, double f4, double rh6) {
                 const double D = V > 0.0 ? (2.0 * f3 + 3.0 * f2 - 6.0 * f1 + f0) * rh6
                                : (V < 0.0 ? (-f4 + 6.0 * f3 - 3.0 * f2 - 2.0 * f1) * rh6 : 0.0);
                 return V * D;
             };
+            // stage-input state of the cell (FP64)
+            double wi[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) wi[v] = ldf(Win + v * N, c);
+            // cell velocity for the level-set upwinding, in FP64
+            double Vc[3];
+            if constexpr (sizeof(TF) == sizeof(double)) {
+                Vc[0] = Q0[1];
+                Vc[1] = Q0[2];
+                Vc[2] = Q0[3];
+            } else {
+                const double ri = 1.0 / wi[0];
+                Vc[0] = wi[1] * ri;
+                Vc[1] = wi[2] * ri;
+                Vc[2] = wi[3] * ri;
+            }
             double Ls = 0.0;
-            const double* sp = sQ + 5 * PL + (ty + 2) * LX + tx + 2;
-            if (xact) Ls += ls_term(Q0[1], sp[-2], sp[-1], sp[0], sp[1], sp[2], G.rh6[0]);
-            if (yact) Ls += ls_term(Q0[2], sp[-2 * LX], sp[-LX], sp[0], sp[LX], sp[2 * LX], G.rh6[1]);
-            if (zact) Ls += ls_term(Q0[3], PH[0], PH[1], PH[2], PH[3], PH[4], G.rh6[2]);
+            const double* sp = sPhi + (ty + 2) * LX + tx + 2;
+            if (xact) Ls += ls_term(Vc[0], sp[-2], sp[-1], sp[0], sp[1], sp[2], G.rh6[0]);
+            if (yact) Ls += ls_term(Vc[1], sp[-2 * LX], sp[-LX], sp[0], sp[LX], sp[2 * LX], G.rh6[1]);
+            if (zact) Ls += ls_term(Vc[2], PH[0], PH[1], PH[2], PH[3], PH[4], G.rh6[2]);
 
             double wn[6];
             if (STAGE == 1) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) wn[v] = ldf(Win + v * N, c) + dt * (-acc[v]);
+                for (int v = 0; v < 5; ++v) wn[v] = wi[v] + dt * (-acc[v]);
                 wn[5] = PH[2] + dt * (-Ls);
             } else {
 #pragma unroll
-                for (int v = 0; v < 5; ++v)
-                    wn[v] = 0.5 * ldf(a.W0 + v * N, c) + 0.5 * (ldf(Win + v * N, c) + dt * (-acc[v]));
+                for (int v = 0; v < 5; ++v) wn[v] = 0.5 * ldf(a.W0 + v * N, c) + 0.5 * (wi[v] + dt * (-acc[v]));
                 wn[5] = 0.5 * ldf(a.W0 + 5 * N, c) + 0.5 * (PH[2] + dt * (-Ls));
             }
             double u, vv, ww;
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
 
         // (6) advance the column window
         if (zact) {
-            double Qn[5];
+            TF Qn[5];
             to_prim(Wn, Xn, mzn, Qn);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
@@ -415,8 +427,9 @@ __global__ __launch_bounds__(TX * TY, M2C_STAGE_WAVES) void k_stage(const StageA
                 Q1[v] = Q2[v];
                 Q2[v] = Qn[v];
                 S0[v] = S1[v];
-                Fzlo[v] = Fzup[v];
+                Fzlo[v] = Fzhi[v];
             }
+            qzlo = qzhi;
             PH[0] = PH[1];
             PH[1] = PH[2];
             PH[2] = PH[3];
