@@ -119,6 +119,9 @@ typedef struct m2c_ctx m2c_ctx;
  * transmissive, alpha 1.2, RK2, CFL 0.5, FP64, acoustic guess, rtol 1e-12,
  * maxit 50, library-chosen tiles. */
 void m2c_config_default(m2c_config* c);
+/* M2C_OK if m2c_create would accept the configuration, else M2C_ERR_ARG
+ * (no device work, usable without a GPU). */
+int m2c_validate_config(const m2c_config* c);
 
 /* Validate the configuration, select device 'current' and allocate every
  * device buffer of the context (about 160 B per cell).  *out is NULL on
@@ -170,6 +173,39 @@ int m2c_set_profiling(m2c_ctx* ctx, int on);
  * included), exactly as the Riemann work queue holds them.  Writes at most
  * cap ids to the host array out (nullable) and the total to *count. */
 int m2c_interface_faces(m2c_ctx* ctx, int32_t* out, int64_t cap, int64_t* count);
+
+/* Time every supported stage tile (tile_x, tile_y, planes per block) on the
+ * context's own grid and state for `steps` steps each and keep the fastest.
+ * The state, statistics and simulated time are restored afterwards (the call
+ * allocates a temporary copy of the state).  tile_out (nullable) receives
+ * the chosen tile, ms_out (nullable) its mean time per step. */
+int m2c_autotune(m2c_ctx* ctx, int32_t steps, int32_t tile_out[3], float* ms_out);
+int m2c_get_tile(const m2c_ctx* ctx, int32_t tile[3]);
+
+/* ---- batched form: many independent runs advanced together ---------------
+ * n runs of uneven grid sizes (one precision and one stage tile for all).
+ * One step of all runs is one persistent stage kernel per Runge-Kutta stage
+ * (a work list of (run, tile) items over the whole batch) plus the interface
+ * kernels, captured once into a hipGraph and replayed per step; every run
+ * keeps its own CFL time step, error state and state parity in device
+ * memory.  Runs are numbered 0..n-1 in the order of cfgs; the state and
+ * statistics calls mean the same as for a single context.  A run that fails
+ * a step stops advancing (its last good state is kept) while the others go
+ * on; m2c_batch_step then returns the first failing run's status. */
+typedef struct m2c_batch m2c_batch;
+int m2c_batch_create(int32_t n, const m2c_config* cfgs, m2c_batch** out);
+void m2c_batch_destroy(m2c_batch* b);
+const char* m2c_batch_last_error(const m2c_batch* b);
+int m2c_batch_size(const m2c_batch* b);
+int m2c_batch_set_state(m2c_batch* b, int32_t run, const double* prim6);
+int m2c_batch_get_state(m2c_batch* b, int32_t run, double* prim6, uint8_t* id);
+int m2c_batch_get_conserved(m2c_batch* b, int32_t run, double* w6);
+int m2c_batch_step(m2c_batch* b, int32_t nsteps);
+int m2c_batch_get_stats(m2c_batch* b, int32_t run, m2c_stats* s);
+int m2c_batch_set_tile(m2c_batch* b, int32_t tile_x, int32_t tile_y, int32_t planes);
+int m2c_batch_get_tile(const m2c_batch* b, int32_t tile[3]);
+/* Autotuner of the batch: as m2c_autotune, over all runs at once. */
+int m2c_batch_autotune(m2c_batch* b, int32_t steps, int32_t tile_out[3], float* ms_out);
 
 /* ---- kernel-level entry points (device pointers, given stream) ---------- */
 

@@ -25,8 +25,13 @@ EXPORTS = [
     "m2c_set_stream", "m2c_set_state", "m2c_set_state_device", "m2c_get_state",
     "m2c_get_state_device", "m2c_get_conserved", "m2c_set_conserved", "m2c_step", "m2c_step_dt",
     "m2c_get_stats", "m2c_reset_stats", "m2c_set_profiling", "m2c_interface_faces",
-    "m2c_eval_hllc", "m2c_riemann_solve",
+    "m2c_eval_hllc", "m2c_riemann_solve", "m2c_validate_config", "m2c_autotune", "m2c_get_tile",
+    "m2c_batch_create", "m2c_batch_destroy", "m2c_batch_last_error", "m2c_batch_size",
+    "m2c_batch_set_state", "m2c_batch_get_state", "m2c_batch_get_conserved", "m2c_batch_step",
+    "m2c_batch_get_stats", "m2c_batch_set_tile", "m2c_batch_get_tile", "m2c_batch_autotune",
 ]
+_NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
+              "m2c_batch_last_error")
 
 
 class Config(C.Structure):
@@ -91,8 +96,25 @@ def _declare(L):
     L.m2c_interface_faces.argtypes = [vp, vp, i64, C.POINTER(i64)]
     L.m2c_eval_hllc.argtypes = [i64, vp, vp, d, d, i32, vp, vp]
     L.m2c_riemann_solve.argtypes = [i64, vp, vp, i32, d, i32, vp, vp, vp]
+    L.m2c_validate_config.argtypes = [C.POINTER(Config)]
+    L.m2c_autotune.argtypes = [vp, i32, vp, C.POINTER(C.c_float)]
+    L.m2c_get_tile.argtypes = [vp, vp]
+    L.m2c_batch_create.argtypes = [i32, vp, C.POINTER(vp)]
+    L.m2c_batch_destroy.argtypes = [vp]
+    L.m2c_batch_destroy.restype = None
+    L.m2c_batch_last_error.argtypes = [vp]
+    L.m2c_batch_last_error.restype = C.c_char_p
+    L.m2c_batch_size.argtypes = [vp]
+    L.m2c_batch_set_state.argtypes = [vp, i32, vp]
+    L.m2c_batch_get_state.argtypes = [vp, i32, vp, vp]
+    L.m2c_batch_get_conserved.argtypes = [vp, i32, vp]
+    L.m2c_batch_step.argtypes = [vp, i32]
+    L.m2c_batch_get_stats.argtypes = [vp, i32, C.POINTER(Stats)]
+    L.m2c_batch_set_tile.argtypes = [vp, i32, i32, i32]
+    L.m2c_batch_get_tile.argtypes = [vp, vp]
+    L.m2c_batch_autotune.argtypes = [vp, i32, vp, C.POINTER(C.c_float)]
     for name in EXPORTS:
-        if name not in ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror"):
+        if name not in _NO_STATUS:
             getattr(L, name).restype = C.c_int
     return L
 
@@ -250,6 +272,120 @@ class Sim:
 
     def last_error(self):
         return self.L.m2c_last_error(self.h).decode()
+
+    def tile(self):
+        t = (C.c_int32 * 3)()
+        self._check(self.L.m2c_get_tile(self.h, t))
+        return tuple(t)
+
+    def autotune(self, steps=3):
+        """Time every supported stage tile on this grid and keep the fastest;
+        the state is restored.  Returns (tile, ms per step)."""
+        t = (C.c_int32 * 3)()
+        ms = C.c_float(0.0)
+        self._check(self.L.m2c_autotune(self.h, steps, t, C.byref(ms)))
+        return tuple(t), ms.value
+
+
+class Batch:
+    """Many independent runs advanced together (persistent kernels, hipGraph)."""
+
+    def __init__(self, cfgs, prims=None):
+        self.L = lib()
+        n = len(cfgs)
+        arr = (Config * n)(*cfgs)
+        self.cfgs = list(cfgs)
+        self.n = n
+        h = C.c_void_p()
+        rc = self.L.m2c_batch_create(n, arr, C.byref(h))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_batch_create failed: " + self.L.m2c_strerror(rc).decode())
+        self.h = h
+        if prims is not None:
+            for k, p in enumerate(prims):
+                self.set_state(k, p)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.m2c_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _check(self, rc):
+        if rc != M2C_OK:
+            raise M2CError(rc, self.L.m2c_batch_last_error(self.h).decode())
+        return rc
+
+    def _shape(self, k):
+        c = self.cfgs[k]
+        return c.nx, c.ny, c.nz
+
+    def set_state(self, k, prim, check=True):
+        nx, ny, nz = self._shape(k)
+        a = np.ascontiguousarray(prim, dtype=np.float64).reshape(-1)
+        assert a.size == 6 * nx * ny * nz
+        rc = self.L.m2c_batch_set_state(self.h, k, a.ctypes.data)
+        return self._check(rc) if check else rc
+
+    def get_state(self, k):
+        nx, ny, nz = self._shape(k)
+        out = np.empty(6 * nx * ny * nz)
+        chi = np.empty(nx * ny * nz, dtype=np.uint8)
+        self._check(self.L.m2c_batch_get_state(self.h, k, out.ctypes.data, chi.ctypes.data))
+        return out.reshape(6, nz, ny, nx), chi.reshape(nz, ny, nx)
+
+    def get_conserved(self, k):
+        nx, ny, nz = self._shape(k)
+        out = np.empty(6 * nx * ny * nz)
+        self._check(self.L.m2c_batch_get_conserved(self.h, k, out.ctypes.data))
+        return out.reshape(6, nz, ny, nx)
+
+    def step(self, n=1, check=True):
+        rc = self.L.m2c_batch_step(self.h, n)
+        if check:
+            self._check(rc)
+        return rc
+
+    def stats(self, k):
+        s = Stats()
+        self._check(self.L.m2c_batch_get_stats(self.h, k, C.byref(s)))
+        return s.as_dict()
+
+    def set_tile(self, tx, ty, kz):
+        return self._check(self.L.m2c_batch_set_tile(self.h, tx, ty, kz))
+
+    def tile(self):
+        t = (C.c_int32 * 3)()
+        self._check(self.L.m2c_batch_get_tile(self.h, t))
+        return tuple(t)
+
+    def autotune(self, steps=3, cache=None, key=None):
+        """Time every supported tile on the batch and keep the fastest (state
+        restored).  With ``cache`` (a JSON file path) and ``key``, a tile
+        found earlier for the same key is reused instead of timing again."""
+        import json
+        if cache and key and os.path.exists(cache):
+            try:
+                known = json.load(open(cache))
+            except (OSError, ValueError):
+                known = {}
+            if key in known:
+                self.set_tile(*known[key]["tile"])
+                return tuple(known[key]["tile"]), known[key]["ms_per_step"]
+        t = (C.c_int32 * 3)()
+        ms = C.c_float(0.0)
+        self._check(self.L.m2c_batch_autotune(self.h, steps, t, C.byref(ms)))
+        if cache and key:
+            try:
+                known = json.load(open(cache)) if os.path.exists(cache) else {}
+            except (OSError, ValueError):
+                known = {}
+            known[key] = {"tile": list(t), "ms_per_step": ms.value}
+            with open(cache, "w") as f:
+                json.dump(known, f, indent=1)
+        return tuple(t), ms.value
 
 
 def eval_hllc(qL, qR, gamma, pc, precision=M2C_PREC_FP64, F=None, stream=None):

@@ -93,19 +93,21 @@ __device__ __forceinline__ int block_sum(int v, int* sRed)
     return t;
 }
 
-__global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a)
+__device__ __forceinline__ void count_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sRed[COMPACT_THREADS / 64];
-    const long long c0 = (long long)blockIdx.x * COMPACT_CELLS_PER_BLOCK +
+    const long long c0 = (long long)blk * COMPACT_CELLS_PER_BLOCK +
                          (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
     int cnt = 0;
     walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
     const int t = block_sum(cnt, sRed);
-    if (threadIdx.x == 0) a.blockcnt[blockIdx.x] = t;
+    if (threadIdx.x == 0) a.blockcnt[blk] = t;
 }
 
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a) { count_body(a, blockIdx.x); }
+
 // One block: exclusive scan of the block counts (in place), total -> qlen.
-__global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a)
+__device__ __forceinline__ void scan_body(const IfaceArgs& a)
 {
     __shared__ int sW[16];
     __shared__ long long sCarry;
@@ -144,11 +146,13 @@ __global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a)
     }
 }
 
-__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
+__global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a) { scan_body(a); }
+
+__device__ __forceinline__ void scatter_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sW[COMPACT_THREADS / 64];
     if (a.sc->err != 0) return;
-    const long long c0 = (long long)blockIdx.x * COMPACT_CELLS_PER_BLOCK +
+    const long long c0 = (long long)blk * COMPACT_CELLS_PER_BLOCK +
                          (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
     int cnt = 0;
     walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
     }
     if (lane == 63) sW[w] = incl;
     __syncthreads();
-    int off = a.blockcnt[blockIdx.x];
+    int off = a.blockcnt[blk];
     for (int k = 0; k < w; ++k) off += sW[k];
     off += incl - cnt;
     if (cnt == 0) return;
@@ -175,6 +179,8 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
             }
     });
 }
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a) { scatter_body(a, blockIdx.x); }
 
 hipError_t launch_compact(const IfaceArgs& a, hipStream_t s)
 {
@@ -204,7 +210,7 @@ __device__ __forceinline__ void cell_prim(const Grid& G, const double* __restric
     q[3] = w;
 }
 
-__global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
+__device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk)
 {
     DevScalars* sc = a.sc;
     if (sc->err != 0) return;
@@ -212,7 +218,7 @@ __global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
     const int n = sc->qlen;
     const long long sxy = (long long)G.nx * G.ny;
     long long iters = 0, fallbacks = 0;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+    for (int q = blk * blockDim.x + threadIdx.x; q < n; q += nblk * blockDim.x) {
         const int f = a.queue[q];
         const long long c = f / 3;
         const int d = f - 3 * (int)c;
@@ -277,6 +283,11 @@ __global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
     }
 }
 
+__global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
+{
+    fiver_body(a, record, blockIdx.x, gridDim.x);
+}
+
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
 {
     long long nb = (a.qcap + 63) / 64;
@@ -296,7 +307,7 @@ hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
 // with B's equation of state.  Without such a face it keeps its primitive
 // state (an "orphan").  The new state also enters the next step's CFL
 // maximum.
-__global__ __launch_bounds__(256) void k_phase(const PhaseArgs a)
+__device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk)
 {
     DevScalars* sc = a.sc;
     if (sc->err != 0) return;
@@ -307,7 +318,7 @@ __global__ __launch_bounds__(256) void k_phase(const PhaseArgs a)
     const int nd[3] = {G.nx, G.ny, G.nz};
     double lam = 0.0;
     long long orphans = 0;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    for (int e = blk * blockDim.x + threadIdx.x; e < n; e += nblk * blockDim.x) {
         const long long c = a.flips[e];
         const int A = a.chi_old[c], B = a.chi_new[c];
         const int k = (int)(c / sxy);
@@ -383,11 +394,103 @@ __global__ __launch_bounds__(256) void k_phase(const PhaseArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_phase(const PhaseArgs a) { phase_body(a, blockIdx.x, gridDim.x); }
+
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
 {
     long long nb = (a.g.N + 255) / 256;
     if (nb > 1024) nb = 1024;
     hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms: the same bodies over many independent runs.  Each run's
+// arguments are rebuilt on the device from its descriptor and its
+// device-side state parity (sc->cur), so a captured graph is valid for
+// every step.
+__device__ __forceinline__ IfaceArgs iface_of_run(const RunDesc& R, int stage)
+{
+    IfaceArgs a;
+    const int cur = R.sc->cur;
+    a.g = R.g;
+    a.Win = stage == 2 ? R.W1 : R.W[cur];
+    a.chi = R.chi[cur];
+    a.queue = R.queue;
+    a.fslot = R.fslot;
+    a.fluxF = R.fluxF;
+    a.star = R.star;
+    a.blockcnt = R.blockcnt;
+    a.qcap = R.qcap;
+    a.nblk = R.nblk_compact;
+    a.sc = R.sc;
+    a.mlp = nullptr;
+    return a;
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count_batch(const RunDesc* __restrict__ runs,
+                                                                 const int2* __restrict__ cmap)
+{
+    const int2 m = cmap[blockIdx.x];
+    count_body(iface_of_run(runs[m.x], 1), m.y);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_batch(const RunDesc* __restrict__ runs)
+{
+    scan_body(iface_of_run(runs[blockIdx.x], 1));
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter_batch(const RunDesc* __restrict__ runs,
+                                                                   const int2* __restrict__ cmap)
+{
+    const int2 m = cmap[blockIdx.x];
+    scatter_body(iface_of_run(runs[m.x], 1), m.y);
+}
+
+hipError_t launch_compact_batch(const RunDesc* runs, int nruns, const int2* cmap, int ncblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_batch, dim3(ncblocks), dim3(COMPACT_THREADS), 0, s, runs, cmap);
+    hipLaunchKernelGGL(k_scan_batch, dim3(nruns), dim3(1024), 0, s, runs);
+    hipLaunchKernelGGL(k_scatter_batch, dim3(ncblocks), dim3(COMPACT_THREADS), 0, s, runs, cmap);
+    return hipGetLastError();
+}
+
+constexpr int FIVER_BLOCKS_PER_RUN = 32;
+constexpr int PHASE_BLOCKS_PER_RUN = 8;
+
+__global__ __launch_bounds__(64) void k_fiver_batch(const RunDesc* __restrict__ runs, int stage)
+{
+    const int r = blockIdx.x / FIVER_BLOCKS_PER_RUN, b = blockIdx.x % FIVER_BLOCKS_PER_RUN;
+    fiver_body(iface_of_run(runs[r], stage), stage == 2, b, FIVER_BLOCKS_PER_RUN);
+}
+
+hipError_t launch_fiver_batch(const RunDesc* runs, int nruns, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fiver_batch, dim3(nruns * FIVER_BLOCKS_PER_RUN), dim3(64), 0, s, runs, stage);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_phase_batch(const RunDesc* __restrict__ runs)
+{
+    const int r = blockIdx.x / PHASE_BLOCKS_PER_RUN, b = blockIdx.x % PHASE_BLOCKS_PER_RUN;
+    const RunDesc& R = runs[r];
+    const int cur = R.sc->cur;
+    PhaseArgs a;
+    a.g = R.g;
+    a.W = R.W[cur ^ 1];
+    a.chi_old = R.chi[cur];
+    a.chi_new = R.chi[cur ^ 1];
+    a.flips = R.flips;
+    a.fslot = R.fslot;
+    a.star = R.star;
+    a.qcap = R.qcap;
+    a.sc = R.sc;
+    phase_body(a, b, PHASE_BLOCKS_PER_RUN);
+}
+
+hipError_t launch_phase_batch(const RunDesc* runs, int nruns, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_phase_batch, dim3(nruns * PHASE_BLOCKS_PER_RUN), dim3(256), 0, s, runs);
     return hipGetLastError();
 }
 

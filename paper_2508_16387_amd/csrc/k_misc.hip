@@ -55,6 +55,50 @@ hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s)
     return hipGetLastError();
 }
 
+// Batched begin / end of a step: one thread per run; a completed step also
+// flips the run's state parity.
+__global__ void k_begin_batch(const RunDesc* __restrict__ runs, int n, double dt_imposed)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const RunDesc& R = runs[r];
+    DevScalars* sc = R.sc;
+    if (sc->err != 0) return;
+    double dt;
+    if (dt_imposed > 0.0) dt = dt_imposed;
+    else if (R.g.dt_fixed > 0.0) dt = R.g.dt_fixed;
+    else dt = R.g.cfl / __longlong_as_double((long long)sc->lam_bits);
+    sc->dt = dt;
+    sc->lam_bits = 0ull;
+    sc->nflip = 0;
+}
+
+__global__ void k_end_batch(const RunDesc* __restrict__ runs, int n, int stages)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    DevScalars* sc = runs[r].sc;
+    if (sc->err != 0) return;
+    sc->steps_done += 1;
+    sc->t += sc->dt;
+    sc->dt_last = sc->dt;
+    sc->solves += (long long)sc->qlen * stages;
+    sc->flips += sc->nflip;
+    sc->cur ^= 1;
+}
+
+hipError_t launch_begin_batch(const RunDesc* runs, int nruns, double dt_imposed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_begin_batch, dim3((nruns + 63) / 64), dim3(64), 0, s, runs, nruns, dt_imposed);
+    return hipGetLastError();
+}
+
+hipError_t launch_end_batch(const RunDesc* runs, int nruns, int stages, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_end_batch, dim3((nruns + 63) / 64), dim3(64), 0, s, runs, nruns, stages);
+    return hipGetLastError();
+}
+
 // max_i lambda_i of a state (the CFL maximum of the first step after a
 // state is set); non-negative doubles order like their bit patterns.
 __global__ __launch_bounds__(256) void k_lambda(const Grid G, const double* __restrict__ W,

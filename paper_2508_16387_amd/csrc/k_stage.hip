@@ -50,8 +50,11 @@
 
 namespace m2c {
 
+// One tile (TX x TY columns, a.kz planes) of one stage.  Called once per
+// block by the single-grid kernel and once per work item by the persistent
+// batched kernel; the whole block takes part.
 template <int STAGE, int TX, int TY, typename TF>
-__global__ __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES) void k_stage(const StageArgs a)
+__device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
     constexpr int NT = TX * TY, LX = TX + 4, LY = TY + 4, PL = LX * LY;
     constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NF = NXF + NYF;
@@ -63,10 +66,11 @@ __global__ __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : 
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
 
-    // Skip the launch when an earlier kernel of the step failed; the flag is
+    // Skip the tile when an earlier kernel of the step failed; the flag is
     // read once per block so that the whole block takes the same branch
-    // (other blocks of this launch may raise it meanwhile).
+    // (other blocks may raise it meanwhile).
     DevScalars* sc = a.sc;
+    __syncthreads();
     if (threadIdx.x == 0) sErr = sc->err;
     __syncthreads();
     if (sErr != 0) return;
@@ -78,11 +82,6 @@ __global__ __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : 
     const double* __restrict__ Win = a.Win;
     const uint8_t* __restrict__ chi = a.chi;
 
-    // ---- XCD-aware tile numbering (dispatch is round-robin over 8 XCDs) --
-    const int nblk = gridDim.x;
-    const int bq = nblk / 8, br = nblk % 8;
-    const int xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-    const int tile = (xcd < br ? xcd * (bq + 1) : br * (bq + 1) + (xcd - br) * bq) + idx;
     const int bx = tile % a.tiles_x;
     const int rest = tile / a.tiles_x;
     const int by = rest % a.tiles_y;
@@ -455,7 +454,71 @@ __global__ __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : 
     }
 }
 
-// ---- launcher ---------------------------------------------------------------
+// XCD-aware block numbering: dispatch is round-robin over the 8 XCDs, so
+// block b runs on XCD b % 8; map each XCD's blocks onto one contiguous run
+// of neighbouring tiles (halo reuse in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int b, int nblk)
+{
+    const int bq = nblk / 8, br = nblk % 8;
+    const int xcd = b % 8, idx = b / 8;
+    return (xcd < br ? xcd * (bq + 1) : br * (bq + 1) + (xcd - br) * bq) + idx;
+}
+
+#define M2C_STAGE_BOUNDS(TX, TY, TF) __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES)
+
+template <int STAGE, int TX, int TY, typename TF>
+__global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
+{
+    stage_tile<STAGE, TX, TY, TF>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Persistent batched stage: the grid is sized to the resident capacity and
+// walks a list of (run, tile) items of many independent grids; each XCD
+// takes a contiguous share of the list.  The state parity of each run lives
+// in its device scalars, so one captured graph serves every step.
+template <int STAGE, int TX, int TY, typename TF>
+__global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage_batch(const RunDesc* __restrict__ runs,
+                                                           const int2* __restrict__ items, int nitems)
+{
+    const int G = gridDim.x;
+    int lb, per, lo, hi;
+    if (G >= 8) {
+        const int xcd = blockIdx.x % 8;
+        lb = blockIdx.x / 8;
+        per = (G + 7 - xcd) / 8;                           // blocks on this XCD
+        lo = (int)((long long)nitems * xcd / 8);
+        hi = (int)((long long)nitems * (xcd + 1) / 8);
+    } else {
+        lb = blockIdx.x;
+        per = G;
+        lo = 0;
+        hi = nitems;
+    }
+    for (int t = lo + lb; t < hi; t += per) {
+        const int2 it = items[t];
+        const RunDesc& R = runs[it.x];
+        const int cur = R.sc->cur;
+        StageArgs a;
+        a.g = R.g;
+        a.Win = STAGE == 1 ? R.W[cur] : R.W1;
+        a.W0 = R.W[cur];
+        a.Wout = STAGE == 1 ? R.W1 : R.W[cur ^ 1];
+        a.chi = R.chi[cur];
+        a.chi_next = R.chi[cur ^ 1];
+        a.flips = R.flips;
+        a.fslot = R.fslot;
+        a.fluxF = R.fluxF;
+        a.qcap = R.qcap;
+        a.sc = R.sc;
+        a.tiles_x = R.tiles_x;
+        a.tiles_y = R.tiles_y;
+        a.tiles_z = R.tiles_z;
+        a.kz = R.kz;
+        stage_tile<STAGE, TX, TY, TF>(a, it.y);
+    }
+}
+
+// ---- launchers ----------------------------------------------------------------
 template <int TX, int TY, typename TF>
 static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
 {
@@ -467,22 +530,54 @@ static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int TX, int TY, typename TF>
+static hipError_t launch_tile_batch(int stage, const RunDesc* runs, const int2* items, int nitems, hipStream_t s)
+{
+    int dev = 0, ncu = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<1, TX, TY, TF>, TX * TY, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<2, TX, TY, TF>, TX * TY, 0);
+    if (e != hipSuccess) return e;
+    long long nblk = (long long)ncu * (per > 0 ? per : 1);
+    if (nblk > nitems) nblk = nitems > 0 ? nitems : 1;
+    if (stage == 1)
+        hipLaunchKernelGGL((k_stage_batch<1, TX, TY, TF>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, runs, items, nitems);
+    else
+        hipLaunchKernelGGL((k_stage_batch<2, TX, TY, TF>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, runs, items, nitems);
+    return hipGetLastError();
+}
+
 bool stage_tile_supported(int tx, int ty)
 {
-    return (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 16) ||
-           (tx == 32 && ty == 4) || (tx == 64 && ty == 2);
+    return (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 16) || (tx == 64 && ty == 2);
 }
+
+#define M2C_TILES(F)                                                                    \
+    F(32, 8)                                                                            \
+    F(64, 4)                                                                            \
+    F(16, 16)                                                                           \
+    F(64, 2)
 
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s)
 {
 #define M2C_TILE(TX_, TY_)                                                              \
     if (tx == TX_ && ty == TY_)                                                         \
         return mixed ? launch_tile<TX_, TY_, float>(stage, a, s) : launch_tile<TX_, TY_, double>(stage, a, s);
-    M2C_TILE(32, 8)
-    M2C_TILE(64, 4)
-    M2C_TILE(16, 16)
-    M2C_TILE(32, 4)
-    M2C_TILE(64, 2)
+    M2C_TILES(M2C_TILE)
+#undef M2C_TILE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDesc* runs, const int2* items,
+                              int nitems, hipStream_t s)
+{
+#define M2C_TILE(TX_, TY_)                                                                          \
+    if (tx == TX_ && ty == TY_)                                                                     \
+        return mixed ? launch_tile_batch<TX_, TY_, float>(stage, runs, items, nitems, s)           \
+                     : launch_tile_batch<TX_, TY_, double>(stage, runs, items, nitems, s);
+    M2C_TILES(M2C_TILE)
 #undef M2C_TILE
     return hipErrorInvalidValue;
 }

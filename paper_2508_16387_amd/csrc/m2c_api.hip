@@ -342,7 +342,15 @@ int upload_prim(m2c_ctx* c, const double* dprim)
 
 }  // namespace
 
+void m2c_fill_grid(Grid* g, const m2c_config* c) { fill_grid(*g, *c); }
+
 extern "C" {
+
+int m2c_validate_config(const m2c_config* c)
+{
+    char why[160];
+    return valid_config(c, why, sizeof(why)) ? M2C_OK : M2C_ERR_ARG;
+}
 
 void m2c_config_default(m2c_config* c)
 {
@@ -658,6 +666,99 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
     (void)hipFree(dvac);
     if (rc == M2C_OK && hv > 0) rc = M2C_ERR_RIEMANN;
     return rc;
+}
+
+int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
+{
+    static const int cands[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {32, 8, 4}, {64, 4, 8}, {64, 4, 4}};
+    if (!c || steps < 1) return M2C_ERR_ARG;
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    HIPCHK(c, hipSetDevice(c->device));
+    int rc = pull_scalars(c);
+    if (rc) return rc;
+    const DevScalars sc0 = *c->hsc;
+    const int cur0 = c->cur;
+    const bool lam0 = c->lam_valid;
+    const long long N = c->g.N;
+    double* snapW = nullptr;
+    uint8_t* snapX = nullptr;
+    HIPCHK(c, hipMalloc((void**)&snapW, 6 * N * sizeof(double)));
+    if (hipMalloc((void**)&snapX, N) != hipSuccess) {
+        (void)hipFree(snapW);
+        return set_err(c, M2C_ERR_NOMEM, "autotune snapshot");
+    }
+    auto restore = [&]() -> int {
+        c->cur = cur0;
+        c->lam_valid = lam0;
+        *c->hsc = sc0;
+        HIPCHK(c, hipMemcpyAsync(c->W[cur0], snapW, 6 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->chi[cur0], snapX, N, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->sc, c->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return M2C_OK;
+    };
+    auto set_tile = [&](int tx, int ty, int kz) {
+        c->tx = tx;
+        c->ty = ty;
+        c->kz = kz < c->g.nz ? kz : c->g.nz;
+        c->tiles[0] = (c->g.nx + tx - 1) / tx;
+        c->tiles[1] = (c->g.ny + ty - 1) / ty;
+        c->tiles[2] = (c->g.nz + c->kz - 1) / c->kz;
+    };
+    if (hipMemcpyAsync(snapW, c->W[cur0], 6 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(snapX, c->chi[cur0], N, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+        rc = set_err(c, M2C_ERR_DEVICE, "autotune snapshot copy");
+    const bool prof = c->profiling;
+    c->profiling = false;
+    int bt[3] = {c->tx, c->ty, c->kz};
+    float best = -1.0f;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = set_err(c, M2C_ERR_DEVICE, "event create");
+    for (const auto& cand : cands) {
+        if (rc) break;
+        set_tile(cand[0], cand[1], cand[2]);
+        if ((rc = restore()) || (rc = run_steps(c, 1, 0.0, nullptr)) || (rc = restore())) break;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = M2C_ERR_DEVICE; break; }
+        if ((rc = run_steps(c, steps, 0.0, nullptr))) break;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = M2C_ERR_DEVICE;
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            bt[0] = cand[0];
+            bt[1] = cand[1];
+            bt[2] = cand[2];
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    set_tile(bt[0], bt[1], bt[2]);
+    const int rc2 = restore();
+    c->profiling = prof;
+    (void)hipFree(snapW);
+    (void)hipFree(snapX);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    if (tile_out) {
+        tile_out[0] = bt[0];
+        tile_out[1] = bt[1];
+        tile_out[2] = bt[2];
+    }
+    if (ms_out) *ms_out = best / steps;
+    return M2C_OK;
+}
+
+int m2c_get_tile(const m2c_ctx* c, int32_t tile[3])
+{
+    if (!c || !tile) return M2C_ERR_ARG;
+    tile[0] = c->tx;
+    tile[1] = c->ty;
+    tile[2] = c->kz;
+    return M2C_OK;
 }
 
 }  // extern "C"

@@ -25,7 +25,7 @@ struct DevScalars {
     long long solves, newton_iters, fallbacks, flips, orphans, mlp_fallbacks;
     double dt_last;
     int32_t chi_dirty;             // material field changed since the last compaction
-    int32_t pad;
+    int32_t cur;                   // batched runs: index (0/1) of the current full state
 };
 
 // One simulation grid as the kernels see it.

@@ -7,6 +7,25 @@
 
 namespace m2c {
 
+// Device buffers of one run of a batch (the kernels pick the state buffers
+// from the run's device-side parity sc->cur).
+struct RunDesc {
+    Grid g;
+    double* W[2];
+    double* W1;
+    uint8_t* chi[2];
+    int32_t* queue;
+    int32_t* fslot;
+    double* fluxF;
+    double* star;
+    int32_t* flips;
+    int32_t* blockcnt;
+    DevScalars* sc;
+    long long qcap;
+    int nblk_compact;
+    int tiles_x, tiles_y, tiles_z, kz;
+};
+
 // Arguments of one bulk Runge-Kutta stage launch.
 struct StageArgs {
     Grid g;
@@ -53,6 +72,9 @@ struct PhaseArgs {
 
 bool stage_tile_supported(int tx, int ty);
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
+// items: (run, tile) pairs over all runs of a batch
+hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDesc* runs, const int2* items,
+                              int nitems, hipStream_t s);
 
 // Interface kernels (k_interface.hip).
 constexpr int COMPACT_THREADS = 256;
@@ -61,10 +83,16 @@ constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THRE
 hipError_t launch_compact(const IfaceArgs& a, hipStream_t s);
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s);
+// Batched forms: cmap maps each compaction block to (run, block of run).
+hipError_t launch_compact_batch(const RunDesc* runs, int nruns, const int2* cmap, int ncblocks, hipStream_t s);
+hipError_t launch_fiver_batch(const RunDesc* runs, int nruns, int stage, hipStream_t s);
+hipError_t launch_phase_batch(const RunDesc* runs, int nruns, hipStream_t s);
 
 // Per-step bookkeeping and state conversion (k_misc.hip).
 hipError_t launch_begin_step(DevScalars* sc, const Grid& g, double dt_imposed, hipStream_t s);
 hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
+hipError_t launch_begin_batch(const RunDesc* runs, int nruns, double dt_imposed, hipStream_t s);
+hipError_t launch_end_batch(const RunDesc* runs, int nruns, int stages, hipStream_t s);
 hipError_t launch_lambda(const Grid& g, const double* W, const uint8_t* chi, DevScalars* sc, hipStream_t s);
 hipError_t launch_prim_to_cons(const Grid& g, const double* prim6, double* W, uint8_t* chi,
                                DevScalars* sc, hipStream_t s);
