@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4,
                     help="oracle steps timed for the CPU baseline (bounded sample)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed-precision, batched and standalone-FIVER measurements")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (reference "
                          "for scaling hardware byte counters to bytes)")
@@ -60,6 +63,83 @@ def measured_traffic(precision):
     if m.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
     return rec["bytes_per_launch_mean"]
+
+
+def time_sim(m2c, torch, problem, precision, steps, warmup, tile=None):
+    """Cell-updates/s per RK stage of one context over `steps` steps."""
+    sim = m2c.Sim(m2c.config_for(problem, precision=precision, tile=tile))
+    sim.set_stream(torch.cuda.current_stream())
+    sim.set_state(problem.prim)
+    if warmup:
+        sim.step(warmup)
+        sim.set_state(problem.prim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    return problem.ncells * steps * 2 / T, T
+
+
+def batched_forms(m2c, torch, steps):
+    """64 independent shock-bubble runs with grid edges from {32,...,128} per
+    axis, advanced by the batched form (autotuned tile, graph replay), against
+    the same runs stepped one context after another on the FP64 path."""
+    import workloads as W
+
+    probs = W.batched_shock_bubbles(0, steps=steps)
+    cells = sum(p.ncells for p in probs)
+    out = {"workload": "64 shock-bubble runs, edges in {32,48,64,96,128}, radius U[0.1,0.25], "
+                       "shock log-U[1e7,1e9] Pa", "cells": cells, "steps": steps}
+    for prec, name in ((m2c.M2C_PREC_FP64, "fp64"), (m2c.M2C_PREC_MIXED, "mixed")):
+        b = m2c.Batch([m2c.config_for(p, precision=prec) for p in probs], [p.prim for p in probs])
+        tile, _ = b.autotune(steps=2)
+        b.step(2)                                   # warm-up (graph instantiation)
+        for k, p in enumerate(probs):
+            b.set_state(k, p.prim)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        out[f"value_{name}"] = cells * steps * 2 / T
+        out[f"tile_{name}"] = list(tile)
+        b.close()
+    # the same runs on the plain FP64 path, one context after another
+    sims = [m2c.Sim(m2c.config_for(p), p.prim) for p in probs]
+    for s in sims:
+        s.step(1)
+    for s, p in zip(sims, probs):
+        s.set_state(p.prim)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.step(steps)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    out["value_sequential_fp64"] = cells * steps * 2 / T
+    out["speedup_batched_fp64_vs_sequential_fp64"] = out["value_fp64"] / out["value_sequential_fp64"]
+    out["speedup_batched_mixed_vs_sequential_fp64"] = out["value_mixed"] / out["value_sequential_fp64"]
+    return out
+
+
+def fiver_standalone(m2c, torch, n=1_000_000):
+    """Exact two-material Riemann solves/s on n water/air problems."""
+    import workloads as W
+
+    inp, eos = W.riemann_problem_set(1, n)
+    di = torch.tensor(inp.T.copy(), device="cuda")
+    de = torch.tensor(eos.T.copy(), device="cuda")
+    m2c.riemann_solve(di, de)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, iters, rc = m2c.riemann_solve(di, de)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    it = iters.abs().double()
+    ok = (iters != 0)
+    return {"problems": n, "solves_per_s": n / T, "ms": T * 1e3,
+            "newton_iters_per_solve": float(it[ok].mean()), "vacuum": int((~ok).sum())}
 
 
 def cpu_baseline(problem, steps):
@@ -146,6 +226,17 @@ def main():
                   "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1)},
         "time_split_ms": {"stage": st["ms_stage"], "fiver": st["ms_fiver"], "other": st["ms_other"]},
     }
+    if not args.no_forms:
+        other = m2c.M2C_PREC_MIXED if prec == m2c.M2C_PREC_FP64 else m2c.M2C_PREC_FP64
+        v_other, _ = time_sim(m2c, torch, p, other, args.steps, args.warmup)
+        v64, vmx = (value, v_other) if prec == m2c.M2C_PREC_FP64 else (v_other, value)
+        out["forms"] = {
+            "fp64": v64,
+            "mixed": vmx,
+            "speedup_mixed_vs_fp64": vmx / v64,
+            "batched": batched_forms(m2c, torch, args.batch_steps),
+            "fiver_standalone": fiver_standalone(m2c, torch),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)
