@@ -11,7 +11,8 @@ Contents
 * ``exact_riemann.py`` -- an independent derivative-free (bisection) solver of
   the two-material stiffened-gas Riemann problem in high precision, plus the
   self-similar exact solution used to pin the scheme.
-* ``mlp_ref.py`` -- FP64 forward/backward of the star-pressure MLP.
+* ``mlp_ref.py`` -- FP64 features, forward, backward and Adam of the learned
+  star-pressure guess.
 
 Parity status: the phase-update rule is a reading of an under-specified step
 and is "parity unpinned" beyond the translation and self-consistency tests;
@@ -106,6 +107,8 @@ def load(path: str | None = None):
     lib.ora_hllc.argtypes = [_D, _D, C.c_double, C.c_double, _D]
     lib.ora_riemann.restype = C.c_int
     lib.ora_riemann.argtypes = [_D, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32)]
+    lib.ora_riemann_many.restype = C.c_int64
+    lib.ora_riemann_many.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_int32, _D, C.c_void_p]
     lib.ora_ls_derivative.restype = C.c_double
     lib.ora_ls_derivative.argtypes = [_D, C.c_double, C.c_double]
     return lib
@@ -218,6 +221,19 @@ def riemann(inp, eos, rtol=1e-12, maxit=50):
     rc = lib().ora_riemann(np.asarray(inp, dtype=np.float64), np.asarray(eos, dtype=np.float64),
                            rtol, maxit, out, C.byref(it))
     return rc, out, it.value
+
+
+def riemann_many(inp, eos, rtol=1e-12, maxit=50):
+    """Star states of many problems: inp [n,6], eos [n,4] -> (out [n,4],
+    iters [n], number without an admissible root)."""
+    inp = np.ascontiguousarray(inp, dtype=np.float64)
+    eos = np.ascontiguousarray(eos, dtype=np.float64)
+    n = inp.shape[0]
+    out = np.empty((n, 4))
+    it = np.empty(n, dtype=np.int32)
+    bad = lib().ora_riemann_many(n, inp.reshape(-1), eos.reshape(-1), rtol, maxit, out.reshape(-1),
+                                 it.ctypes.data)
+    return out, it, int(bad)
 
 
 def sound_speed(rho, p, gamma, pc):

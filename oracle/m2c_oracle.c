@@ -240,6 +240,24 @@ int ora_riemann(const double* in, const double* eos, double rtol, int32_t maxit,
     return ORA_OK;
 }
 
+/* The same for n problems stored row by row (in[n][6], eos[n][4],
+ * out[n][4], iters[n]); returns the number without an admissible root. */
+int64_t ora_riemann_many(int64_t n, const double* in, const double* eos, double rtol, int32_t maxit,
+                         double* out, int32_t* iters)
+{
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t it = 0;
+        if (ora_riemann(in + 6 * i, eos + 4 * i, rtol, maxit, out + 4 * i, &it) != ORA_OK) {
+            ++bad;
+            for (int v = 0; v < 4; ++v) out[4 * i + v] = NAN;
+            it = 0;
+        }
+        if (iters) iters[i] = it;
+    }
+    return bad;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Level-set derivative, section "Level set method": finite differences with
  * a third-order upwind scheme.  Reading: the one-sided four-point stencils

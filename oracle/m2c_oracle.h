@@ -94,6 +94,10 @@ void ora_hllc(const double* qL, const double* qR, double gamma, double pc, doubl
  * out = (p*, u*, rho*_L, rho*_R); returns ORA_OK or ORA_ERR_RIEMANN (vacuum). */
 int  ora_riemann(const double* in, const double* eos, double rtol, int32_t maxit,
                  double* out, int32_t* iters);
+/* ora_riemann over n problems stored row by row; returns the number of
+ * problems without an admissible star pressure (their out = NaN). */
+int64_t ora_riemann_many(int64_t n, const double* in, const double* eos, double rtol, int32_t maxit,
+                         double* out, int32_t* iters);
 /* Third-order upwind-biased derivative of phi at the centre of a 5-point
  * stencil f[0..4] = phi_{i-2..i+2} for advection speed v. */
 double ora_ls_derivative(const double* f, double v, double h);
