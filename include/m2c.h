@@ -225,6 +225,57 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
                       double rtol, int32_t maxit, double* out, int32_t* iters,
                       void* hip_stream);
 
+/* ---- learned star-pressure guess --------------------------------------------
+ * The paper accelerates its exact two-material Riemann solver without new
+ * approximations (section "Spatial discretization of governing equations").
+ * Here the acceleration is a learned initial guess for the star-pressure
+ * Newton iteration: a network 8 -> 64 -> 64 -> 1 (tanh hidden layers; BF16
+ * weights on the matrix cores, FP32 accumulation) maps eight dimensionless
+ * features of a problem to y = ln((p* - p_lo)/P), p_lo = -min(pc_L, pc_R),
+ * P = sqrt((p_L - p_lo)(p_R - p_lo)).  The solver starts Newton from the
+ * learned guess p_lo + P exp(y) only when it is finite, admissible and has a
+ * smaller |g| than the acoustic guess ("fallback and judge"), then iterates
+ * to the same tolerance, so the star state does not depend on the network.
+ * Parameters: 4801 FP32 values, W1 (64x8 row-major), b1 (64), W2 (64x64
+ * row-major), b2 (64), w3 (64), b3 (1).  Device pointers below are in the
+ * given stream's device memory; n-long arrays are SoA. */
+typedef struct m2c_mlp m2c_mlp;
+typedef struct m2c_train_opts {
+    uint32_t struct_size;       /* = sizeof(m2c_train_opts)                      */
+    int32_t epochs;             /* passes over the data set                      */
+    int32_t batch;              /* minibatch size (>= 16)                        */
+    float lr, lr_final;         /* Adam step size, decayed geometrically to lr_final */
+    float beta1, beta2, eps;    /* Adam moments                                  */
+} m2c_train_opts;
+void m2c_train_opts_default(m2c_train_opts* o);
+/* params: host array of 4801 values, or NULL for seeded Glorot-uniform weights. */
+int m2c_mlp_create(const float* params, uint64_t seed, m2c_mlp** out);
+void m2c_mlp_destroy(m2c_mlp* m);
+int m2c_mlp_get_params(const m2c_mlp* m, float* params);
+/* Features X8 [8][n] (and targets [n] when pstar is given) of n problems
+ * in [6][n] = (rho_L,u_L,p_L,rho_R,u_R,p_R), eos [4][n] = (gamma_L,pc_L,
+ * gamma_R,pc_R); device pointers. */
+int m2c_mlp_features(int64_t n, const double* in, const double* eos, const double* pstar, float* X8,
+                     float* target, void* hip_stream);
+/* Network outputs y [n] for features X8 [8][n] (device pointers). */
+int m2c_mlp_forward(const m2c_mlp* m, int64_t n, const float* X8, float* y, void* hip_stream);
+/* Gradient of the mean squared error over the n samples into the host
+ * array grad[4801]; *loss (nullable) = the mean squared error. */
+int m2c_mlp_grad(const m2c_mlp* m, int64_t n, const float* X8, const float* t, float* grad, float* loss,
+                 void* hip_stream);
+/* Minibatch Adam on the GPU over the data set (device X8 [8][n], t [n]);
+ * loss_per_epoch (host, nullable) receives the epoch-mean squared error. */
+int m2c_mlp_train(m2c_mlp* m, int64_t n, const float* X8, const float* t, const m2c_train_opts* opts,
+                  float* loss_per_epoch, void* hip_stream);
+/* As m2c_riemann_solve with the learned guess (m NULL: acoustic guess);
+ * *n_fallback (nullable) counts problems that started from the acoustic
+ * guess because it was better or the network output was unusable. */
+int m2c_riemann_solve_learned(const m2c_mlp* m, int64_t n, const double* in, const double* eos, double rtol,
+                              int32_t maxit, double* out, int32_t* iters, int64_t* n_fallback, void* hip_stream);
+/* Use a copy of the network for every interface Riemann problem of later
+ * steps (NULL: back to the acoustic guess). */
+int m2c_set_guess(m2c_ctx* ctx, const m2c_mlp* m);
+
 #ifdef __cplusplus
 }
 #endif

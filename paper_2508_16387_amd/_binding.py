@@ -29,9 +29,12 @@ EXPORTS = [
     "m2c_batch_create", "m2c_batch_destroy", "m2c_batch_last_error", "m2c_batch_size",
     "m2c_batch_set_state", "m2c_batch_get_state", "m2c_batch_get_conserved", "m2c_batch_step",
     "m2c_batch_get_stats", "m2c_batch_set_tile", "m2c_batch_get_tile", "m2c_batch_autotune",
+    "m2c_train_opts_default", "m2c_mlp_create", "m2c_mlp_destroy", "m2c_mlp_get_params", "m2c_mlp_features",
+    "m2c_mlp_forward", "m2c_mlp_grad", "m2c_mlp_train", "m2c_riemann_solve_learned", "m2c_set_guess",
 ]
 _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
-              "m2c_batch_last_error")
+              "m2c_batch_last_error", "m2c_train_opts_default", "m2c_mlp_destroy")
+NPARAM = 4801
 
 
 class Config(C.Structure):
@@ -55,6 +58,12 @@ class Stats(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_int32), ("batch", C.c_int32),
+                ("lr", C.c_float), ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
 
 
 class M2CError(RuntimeError):
@@ -113,6 +122,18 @@ def _declare(L):
     L.m2c_batch_set_tile.argtypes = [vp, i32, i32, i32]
     L.m2c_batch_get_tile.argtypes = [vp, vp]
     L.m2c_batch_autotune.argtypes = [vp, i32, vp, C.POINTER(C.c_float)]
+    L.m2c_train_opts_default.argtypes = [C.POINTER(TrainOpts)]
+    L.m2c_train_opts_default.restype = None
+    L.m2c_mlp_create.argtypes = [vp, C.c_uint64, C.POINTER(vp)]
+    L.m2c_mlp_destroy.argtypes = [vp]
+    L.m2c_mlp_destroy.restype = None
+    L.m2c_mlp_get_params.argtypes = [vp, vp]
+    L.m2c_mlp_features.argtypes = [i64, vp, vp, vp, vp, vp, vp]
+    L.m2c_mlp_forward.argtypes = [vp, i64, vp, vp, vp]
+    L.m2c_mlp_grad.argtypes = [vp, i64, vp, vp, vp, C.POINTER(C.c_float), vp]
+    L.m2c_mlp_train.argtypes = [vp, i64, vp, vp, C.POINTER(TrainOpts), vp, vp]
+    L.m2c_riemann_solve_learned.argtypes = [vp, i64, vp, vp, d, i32, vp, vp, C.POINTER(i64), vp]
+    L.m2c_set_guess.argtypes = [vp, vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(L, name).restype = C.c_int
@@ -278,6 +299,10 @@ class Sim:
         self._check(self.L.m2c_get_tile(self.h, t))
         return tuple(t)
 
+    def set_guess(self, mlp):
+        """Use the learned guess of an Mlp for later steps (None: acoustic)."""
+        return self._check(self.L.m2c_set_guess(self.h, None if mlp is None else mlp.h))
+
     def autotune(self, steps=3):
         """Time every supported stage tile on this grid and keep the fastest;
         the state is restored.  Returns (tile, ms per step)."""
@@ -413,3 +438,96 @@ def riemann_solve(inp, eos, guess=M2C_GUESS_ACOUSTIC, rtol=1e-12, maxit=50, stre
     if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
         raise M2CError(rc, lib().m2c_strerror(rc).decode())
     return out, iters, rc
+
+
+def _stream_of(t, stream):
+    import torch
+    return torch.cuda.current_stream(t.device).cuda_stream if stream is None else stream
+
+
+class Mlp:
+    """The learned star-pressure guess network (weights in device memory)."""
+
+    def __init__(self, params=None, seed=0):
+        self.L = lib()
+        h = C.c_void_p()
+        arr = None
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+            assert arr.size == NPARAM
+        rc = self.L.m2c_mlp_create(None if arr is None else arr.ctypes.data, seed, C.byref(h))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_mlp_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.m2c_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def params(self):
+        out = np.empty(NPARAM, dtype=np.float32)
+        rc = self.L.m2c_mlp_get_params(self.h, out.ctypes.data)
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_mlp_get_params failed")
+        return out
+
+    def forward(self, X, stream=None):
+        import torch
+        n = X.shape[1]
+        y = torch.empty(n, dtype=torch.float32, device=X.device)
+        rc = self.L.m2c_mlp_forward(self.h, n, _ptr(X), _ptr(y), _stream_of(X, stream))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_mlp_forward failed")
+        return y
+
+    def grad(self, X, t, stream=None):
+        n = X.shape[1]
+        g = np.empty(NPARAM, dtype=np.float32)
+        loss = C.c_float(0.0)
+        rc = self.L.m2c_mlp_grad(self.h, n, _ptr(X), _ptr(t), g.ctypes.data, C.byref(loss), _stream_of(X, stream))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_mlp_grad failed")
+        return g, loss.value
+
+    def train(self, X, t, epochs=20, batch=4096, lr=3e-3, lr_final=1e-4, stream=None):
+        o = TrainOpts()
+        self.L.m2c_train_opts_default(C.byref(o))
+        o.epochs, o.batch, o.lr, o.lr_final = epochs, batch, lr, lr_final
+        hist = np.zeros(epochs, dtype=np.float32)
+        rc = self.L.m2c_mlp_train(self.h, X.shape[1], _ptr(X), _ptr(t), C.byref(o), hist.ctypes.data,
+                                  _stream_of(X, stream))
+        if rc != M2C_OK:
+            raise M2CError(rc, "m2c_mlp_train failed")
+        return hist
+
+
+def mlp_features(inp, eos, pstar=None, stream=None):
+    """Features X [8, n] (and targets [n] when pstar is given) of problems
+    inp [6, n], eos [4, n] (float64 cuda tensors)."""
+    import torch
+    n = inp.shape[1]
+    X = torch.empty((8, n), dtype=torch.float32, device=inp.device)
+    t = torch.empty(n, dtype=torch.float32, device=inp.device) if pstar is not None else None
+    rc = lib().m2c_mlp_features(n, _ptr(inp), _ptr(eos), _ptr(pstar), _ptr(X), _ptr(t), _stream_of(inp, stream))
+    if rc != M2C_OK:
+        raise M2CError(rc, "m2c_mlp_features failed")
+    return X, t
+
+
+def riemann_solve_learned(mlp, inp, eos, rtol=1e-12, maxit=50, stream=None):
+    """Riemann problems with the learned guess (mlp None: acoustic).
+    Returns (out [4, n], iters [n], rc, n_fallback)."""
+    import torch
+    n = inp.shape[1]
+    out = torch.empty((4, n), dtype=torch.float64, device=inp.device)
+    iters = torch.empty((n,), dtype=torch.int32, device=inp.device)
+    nfb = C.c_int64(0)
+    rc = lib().m2c_riemann_solve_learned(None if mlp is None else mlp.h, n, _ptr(inp), _ptr(eos), rtol, maxit,
+                                         _ptr(out), _ptr(iters), C.byref(nfb), _stream_of(inp, stream))
+    if rc not in (M2C_OK, M2C_ERR_RIEMANN):
+        raise M2CError(rc, "m2c_riemann_solve_learned failed")
+    return out, iters, rc, nfb.value

@@ -217,7 +217,7 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
     const Grid& G = a.g;
     const int n = sc->qlen;
     const long long sxy = (long long)G.nx * G.ny;
-    long long iters = 0, fallbacks = 0;
+    long long iters = 0, fallbacks = 0, mlp_fb = 0;
     for (int q = blk * blockDim.x + threadIdx.x; q < n; q += nblk * blockDim.x) {
         const int f = a.queue[q];
         const long long c = f / 3;
@@ -235,8 +235,11 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         const double ua = qa[1 + d], ub = qb[1 + d];
         const double gA = G.gamma[xa], pcA = G.pc[xa], gB = G.gamma[xb], pcB = G.pc[xb];
         double out[4];
-        int it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit,
-                               false, 0.0, out);
+        bool used = false;
+        const bool hg = a.guess != nullptr;
+        int it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg,
+                               hg ? a.guess[q] : 0.0, out, &used);
+        mlp_fb += hg && !used && it != 0;
         if (it == 0) {
             report_error(&sc->err, &sc->err_cell, ST_RIEMANN, c);
             continue;
@@ -276,10 +279,12 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
     for (int o = 32; o > 0; o >>= 1) {
         iters += __shfl_xor(iters, o);
         fallbacks += __shfl_xor(fallbacks, o);
+        mlp_fb += __shfl_xor(mlp_fb, o);
     }
-    if ((threadIdx.x & 63) == 0 && (iters | fallbacks)) {
+    if ((threadIdx.x & 63) == 0 && (iters | fallbacks | mlp_fb)) {
         atomicAdd((unsigned long long*)&sc->newton_iters, (unsigned long long)iters);
         atomicAdd((unsigned long long*)&sc->fallbacks, (unsigned long long)fallbacks);
+        if (mlp_fb) atomicAdd((unsigned long long*)&sc->mlp_fallbacks, (unsigned long long)mlp_fb);
     }
 }
 
@@ -424,7 +429,7 @@ __device__ __forceinline__ IfaceArgs iface_of_run(const RunDesc& R, int stage)
     a.qcap = R.qcap;
     a.nblk = R.nblk_compact;
     a.sc = R.sc;
-    a.mlp = nullptr;
+    a.guess = nullptr;
     return a;
 }
 

@@ -258,32 +258,37 @@ hipError_t launch_hllc_points(long long n, const double* qL, const double* qR, d
 }
 
 // Independent two-material Riemann problems, in = [6][n], eos = [4][n],
-// out = [4][n] (p*, u*, rho*_L, rho*_R).
+// out = [4][n] (p*, u*, rho*_L, rho*_R); optional candidate guesses.
 __global__ __launch_bounds__(64) void k_riemann_points(long long n, const double* __restrict__ in,
-                                                       const double* __restrict__ eos, double rtol, int maxit,
+                                                       const double* __restrict__ eos,
+                                                       const double* __restrict__ guess, double rtol, int maxit,
                                                        double* __restrict__ out, int32_t* __restrict__ iters,
-                                                       int32_t* nvac)
+                                                       int32_t* nvac, unsigned long long* nfb)
 {
+    unsigned long long fb = 0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double o[4];
+        bool used = false;
         const int it = riemann_solve(in[i], in[n + i], in[2 * n + i], eos[i], eos[n + i], in[3 * n + i],
                                      in[4 * n + i], in[5 * n + i], eos[2 * n + i], eos[3 * n + i], rtol, maxit,
-                                     false, 0.0, o);
+                                     guess != nullptr, guess ? guess[i] : 0.0, o, &used);
         if (it == 0) atomicAdd(nvac, 1);
+        fb += guess != nullptr && !used && it != 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) out[v * n + i] = o[v];
         if (iters) iters[i] = it;
     }
+    for (int o = 32; o > 0; o >>= 1) fb += __shfl_xor(fb, o);
+    if (nfb && (threadIdx.x & 63) == 0 && fb) atomicAdd(nfb, fb);
 }
 
-hipError_t launch_riemann_points(long long n, const double* in, const double* eos, int guess, const double* mlp,
-                                 double rtol, int maxit, double* out, int32_t* iters, int32_t* nvac, hipStream_t s)
+hipError_t launch_riemann_points(long long n, const double* in, const double* eos, const double* guess, double rtol,
+                                 int maxit, double* out, int32_t* iters, int32_t* nvac, unsigned long long* nfb,
+                                 hipStream_t s)
 {
-    (void)guess;
-    (void)mlp;
-    hipLaunchKernelGGL(k_riemann_points, dim3(grid_for(n, 64)), dim3(64), 0, s, n, in, eos, rtol, maxit, out,
-                       iters, nvac);
+    hipLaunchKernelGGL(k_riemann_points, dim3(grid_for(n, 64)), dim3(64), 0, s, n, in, eos, guess, rtol, maxit, out,
+                       iters, nvac, nfb);
     return hipGetLastError();
 }
 

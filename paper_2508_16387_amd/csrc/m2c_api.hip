@@ -21,8 +21,11 @@
 #include "../../include/m2c.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
+#include "m2c_mlp.h"
 
 using namespace m2c;
+
+const MlpDev* m2c_mlp_dev(const m2c_mlp* m);   // m2c_learned.hip
 
 struct m2c_ctx {
     m2c_config cfg;
@@ -48,6 +51,9 @@ struct m2c_ctx {
     int tx = 32, ty = 8, kz = 8;
     int tiles[3] = {1, 1, 1};
     bool profiling = false;
+    MlpDev mlp{};                   // context copy of the learned guess (null: acoustic)
+    bool use_mlp = false;
+    double* guessbuf = nullptr;     // [qcap] learned guesses of the stage in flight
     std::vector<hipEvent_t> evpool;  // profiling: 7 events per enqueued step
     int ev_steps = 0;               // steps recorded in the pool, not yet harvested
     double ms_stage = 0, ms_fiver = 0, ms_other = 0;
@@ -170,7 +176,7 @@ IfaceArgs iface_args(m2c_ctx* c, const double* Win)
     a.qcap = c->qcap;
     a.nblk = c->nblk_compact;
     a.sc = c->sc;
-    a.mlp = nullptr;
+    a.guess = nullptr;
     return a;
 }
 
@@ -246,6 +252,10 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
     // stage 1: W(1) = W^n + dt R(W^n)
     if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
     ia.Win = c->W[p];
+    if (c->use_mlp) {
+        ia.guess = c->guessbuf;
+        HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
+    }
     HIPCHK(c, launch_fiver(ia, false, s));
     if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
     sa.Win = c->W[p];
@@ -255,6 +265,7 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
     // stage 2: W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1)))
     if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
     ia.Win = c->W1;
+    if (c->use_mlp) HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
     HIPCHK(c, launch_fiver(ia, true, s));
     if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
     sa.Win = c->W1;
@@ -398,6 +409,9 @@ void m2c_destroy(m2c_ctx* c)
     (void)hipFree(c->flips);
     (void)hipFree(c->blockcnt);
     (void)hipFree(c->sc);
+    (void)hipFree(c->mlp.master);
+    (void)hipFree(c->mlp.wbf);
+    (void)hipFree(c->guessbuf);
     if (c->hsc) (void)hipHostFree(c->hsc);
     for (auto& e : c->evpool) (void)hipEventDestroy(e);
     delete c;
@@ -659,7 +673,7 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
     int32_t hv = 0;
     int rc = M2C_OK;
     if (hipMemsetAsync(dvac, 0, sizeof(int32_t), s) != hipSuccess ||
-        launch_riemann_points(n, in, eos, guess, nullptr, rtol, maxit, out, iters, dvac, s) != hipSuccess ||
+        launch_riemann_points(n, in, eos, nullptr, rtol, maxit, out, iters, dvac, nullptr, s) != hipSuccess ||
         hipMemcpyAsync(&hv, dvac, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         rc = M2C_ERR_DEVICE;
@@ -749,6 +763,28 @@ int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
         tile_out[2] = bt[2];
     }
     if (ms_out) *ms_out = best / steps;
+    return M2C_OK;
+}
+
+int m2c_set_guess(m2c_ctx* c, const m2c_mlp* m)
+{
+    if (!c) return M2C_ERR_ARG;
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!m) {
+        c->use_mlp = false;
+        return M2C_OK;
+    }
+    const MlpDev* src = m2c_mlp_dev(m);
+    if (!c->mlp.master) {
+        HIPCHK(c, hipMalloc((void**)&c->mlp.master, MLP_NPARAM * sizeof(float)));
+        HIPCHK(c, hipMalloc((void**)&c->mlp.wbf, MLP_NBF * sizeof(uint16_t)));
+        HIPCHK(c, hipMalloc((void**)&c->guessbuf, c->qcap * sizeof(double)));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->mlp.master, src->master, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->mlp.wbf, src->wbf, MLP_NBF * sizeof(uint16_t), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->use_mlp = true;
     return M2C_OK;
 }
 

@@ -166,14 +166,16 @@ __device__ __forceinline__ double rside_star_rho(const RSide& s, double g, doubl
     return s.r * pow(x, 1.0 / g);
 }
 
-// Safeguarded Newton from p0 (clamped into the admissible range), then
-// bisection if maxit steps did not meet |dp| <= rtol (p - p_lo).
-// Returns the Newton step count (negative: bisection fallback, 0: no
-// admissible root).  out = (p*, u*, rho*_L, rho*_R).
+// Safeguarded Newton from the acoustic guess, or from a candidate guess
+// when one is given and its |g| is smaller (the candidate must be finite and
+// above p_lo); then bisection if maxit steps did not meet
+// |dp| <= rtol (p - p_lo).  Returns the Newton step count (negative:
+// bisection fallback, 0: no admissible root).  out = (p*, u*, rho*_L,
+// rho*_R); *used (nullable) tells whether the candidate was the start.
 __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, double gL, double pcL,
                                              double rR, double uR, double pR, double gR, double pcR,
                                              double rtol, int maxit, bool have_guess, double guess,
-                                             double out[4])
+                                             double out[4], bool* used = nullptr)
 {
     RSide L, R;
     rside_init(L, rL, uL, pL, gL, pcL);
@@ -181,6 +183,7 @@ __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, do
     const double du = uR - uL;
     const double plo = -fmin(pcL, pcR);
     const double glo = rside_f(L, plo) + rside_f(R, plo) + du;
+    if (used) *used = false;
     if (!(glo < 0.0)) {
         out[0] = out[1] = out[2] = out[3] = __builtin_nan("");
         return 0;
@@ -188,7 +191,14 @@ __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, do
     const double ZL = L.rc, ZR = R.rc;
     const double pac = (ZR * pL + ZL * pR + ZL * ZR * (uL - uR)) / (ZL + ZR);
     double p = fmax(pac, plo + 1e-6 * fmin(pL - plo, pR - plo));
-    if (have_guess) p = guess;
+    if (have_guess && isfinite(guess) && guess > plo) {
+        const double gg = rside_f(L, guess) + rside_f(R, guess) + du;
+        const double ga = rside_f(L, p) + rside_f(R, p) + du;
+        if (fabs(gg) < fabs(ga)) {
+            p = guess;
+            if (used) *used = true;
+        }
+    }
     int it = 0;
     bool conv = false;
     while (it < maxit) {

@@ -55,7 +55,7 @@ struct IfaceArgs {
     long long qcap;
     int nblk;                      // compaction blocks
     DevScalars* sc;
-    const double* mlp;             // learned-guess parameters (device, FP32 as double) or null
+    double* guess;                 // [qcap] learned star-pressure guesses, or null (acoustic)
 };
 
 struct PhaseArgs {
@@ -88,6 +88,21 @@ hipError_t launch_compact_batch(const RunDesc* runs, int nruns, const int2* cmap
 hipError_t launch_fiver_batch(const RunDesc* runs, int nruns, int stage, hipStream_t s);
 hipError_t launch_phase_batch(const RunDesc* runs, int nruns, hipStream_t s);
 
+// Learned star-pressure guess (k_mlp.hip).
+struct MlpDev;
+hipError_t launch_mlp_features(long long n, const double* in, const double* eos, const double* ps, float* X,
+                               float* tg, hipStream_t s);
+hipError_t launch_mlp_forward(long long n, const float* X, const MlpDev& m, float* y, hipStream_t s);
+hipError_t launch_mlp_grad(long long i0, long long cnt, long long ntot, float invB, const float* X, const float* T,
+                           const MlpDev& m, float* grad, float* sse, hipStream_t s);
+hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t s);
+hipError_t launch_adam(const MlpDev& md, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_mlp_sync(const MlpDev& m, hipStream_t s);
+hipError_t launch_fiver_guess(const IfaceArgs& a, const MlpDev& m, hipStream_t s);
+hipError_t launch_points_guess(long long n, const double* in, const double* eos, const MlpDev& m, double* guess,
+                               hipStream_t s);
+
 // Per-step bookkeeping and state conversion (k_misc.hip).
 hipError_t launch_begin_step(DevScalars* sc, const Grid& g, double dt_imposed, hipStream_t s);
 hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
@@ -102,8 +117,11 @@ hipError_t launch_chi_from_phi(const Grid& g, const double* W, uint8_t* chi, hip
 hipError_t launch_fill_i32(int32_t* p, long long n, int32_t v, hipStream_t s);
 hipError_t launch_hllc_points(long long n, const double* qL, const double* qR, double gamma, double pc,
                               bool mixed, double* F, hipStream_t s);
-hipError_t launch_riemann_points(long long n, const double* in, const double* eos, int guess,
-                                 const double* mlp, double rtol, int maxit, double* out, int32_t* iters,
-                                 int32_t* nvac, hipStream_t s);
+// guess (nullable): candidate initial pressures, judged against the
+// acoustic guess; nfb (nullable) counts problems that started from the
+// acoustic guess although a candidate was given.
+hipError_t launch_riemann_points(long long n, const double* in, const double* eos, const double* guess,
+                                 double rtol, int maxit, double* out, int32_t* iters, int32_t* nvac,
+                                 unsigned long long* nfb, hipStream_t s);
 
 }  // namespace m2c

@@ -1,0 +1,138 @@
+"""Learned star-pressure guess on the GPU vs the FP64 reference (needs an
+MI355X): features, BF16-MFMA inference, gradients of the training loss,
+training, and the judged learned guess inside the exact Riemann solver."""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_ref as M
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def m2c():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_16387_amd as m
+    m.lib()
+    return m
+
+
+def _bf16(a):
+    """Round float32 values to the nearest BF16 (even ties), as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_theta(theta):
+    p = M.unpack(np.asarray(theta, dtype=np.float64))
+    p["W1"] = _bf16(p["W1"])
+    p["W2"] = _bf16(p["W2"])
+    return M.pack(p)
+
+
+def _labelled(seed, n):
+    inp, eos = W.riemann_problem_set(seed, n)
+    out, it, bad = oracle.riemann_many(inp, eos, rtol=1e-14)
+    ok = np.isfinite(out[:, 0])
+    return inp[ok], eos[ok], out[ok], it[ok]
+
+
+def _cuda(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), device="cuda")
+
+
+def test_features_and_targets(m2c):
+    inp, eos, out, _ = _labelled(21, 3000)
+    X, t = m2c.mlp_features(_cuda(inp.T), _cuda(eos.T), _cuda(out[:, 0]))
+    Xr = M.features(inp, eos)
+    tr = M.target(out[:, 0], inp, eos)
+    assert np.max(np.abs(X.cpu().numpy().T - Xr)) <= 1e-5 * (1 + np.max(np.abs(Xr)))
+    assert np.max(np.abs(t.cpu().numpy() - tr)) <= 1e-5 * (1 + np.max(np.abs(tr)))
+
+
+def test_forward_matches_reference(m2c):
+    rng = np.random.default_rng(7)
+    theta = M.init(5) + 0.02 * rng.standard_normal(M.NPARAM)
+    net = m2c.Mlp(theta.astype(np.float32))
+    X = rng.standard_normal((8, 1001)).astype(np.float32)      # ragged: 62 chunks of 16 + 9
+    y = net.forward(_cuda(X)).cpu().numpy()
+    yr = M.forward(_bf16_theta(theta.astype(np.float32)), _bf16(X.T))
+    err = np.max(np.abs(y - yr))
+    print("forward max abs err", err, "scale", np.max(np.abs(yr)))
+    assert err <= 2e-2 * max(1.0, np.max(np.abs(yr)))
+
+
+def test_gradient_matches_reference(m2c):
+    rng = np.random.default_rng(8)
+    theta = (M.init(6) + 0.02 * rng.standard_normal(M.NPARAM)).astype(np.float32)
+    net = m2c.Mlp(theta)
+    X = rng.standard_normal((8, 777)).astype(np.float32)
+    t = rng.standard_normal(777).astype(np.float32)
+    g, loss = net.grad(_cuda(X), _cuda(t))
+    tb = _bf16_theta(theta)
+    gr = M.grad(tb, _bf16(X.T), t.astype(np.float64))
+    lr = M.loss(tb, _bf16(X.T), t.astype(np.float64))
+    assert abs(loss - lr) <= 2e-2 * lr
+    pg, pr = M.unpack(g.astype(np.float64)), M.unpack(gr)
+    for name, _ in M.SIZES:
+        rel = np.linalg.norm(pg[name] - pr[name]) / max(np.linalg.norm(pr[name]), 1e-30)
+        print(name, "rel err", rel)
+        assert rel <= 3e-2, name
+
+
+def test_training_lowers_loss_and_keeps_the_solution(m2c):
+    inp, eos, out, it_ref = _labelled(22, 40000)
+    X, t = m2c.mlp_features(_cuda(inp.T), _cuda(eos.T), _cuda(out[:, 0]))
+    net = m2c.Mlp(seed=1)
+    hist = net.train(X, t, epochs=8, batch=1024, lr=3e-3, lr_final=3e-4)
+    print("loss per epoch", hist)
+    assert hist[-1] < 0.2 * hist[0]
+    # held-out problems: same star state as the oracle, fewer Newton steps
+    hin, heos, hout, hit = _labelled(23, 5000)
+    o_l, i_l, rc, nfb = m2c.riemann_solve_learned(net, _cuda(hin.T), _cuda(heos.T))
+    o_a, i_a, rc2, _ = m2c.riemann_solve_learned(None, _cuda(hin.T), _cuda(heos.T))
+    o_l, i_l, i_a = o_l.cpu().numpy(), np.abs(i_l.cpu().numpy()), np.abs(i_a.cpu().numpy())
+    plo = -np.minimum(heos[:, 1], heos[:, 3])
+    assert np.max(np.abs(o_l[0] - hout[:, 0]) / (hout[:, 0] - plo)) <= 1e-10
+    print("mean Newton steps: learned", i_l.mean(), "acoustic", i_a.mean(), "fallbacks", nfb)
+    assert i_l.mean() < i_a.mean()
+
+
+def test_committed_network(m2c):
+    """The trained network shipped with the package: held-out gain, and the
+    in-situ guess leaves a shock-bubble run within the FP64 bar."""
+    path = os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess.npy")
+    if not os.path.exists(path):
+        pytest.skip("no trained network committed")
+    theta = np.load(path)
+    net = m2c.Mlp(theta)
+    hin, heos, hout, _ = _labelled(99, 20000)
+    o_l, i_l, rc, nfb = m2c.riemann_solve_learned(net, _cuda(hin.T), _cuda(heos.T))
+    _, i_a, _, _ = m2c.riemann_solve_learned(None, _cuda(hin.T), _cuda(heos.T))
+    i_l, i_a = np.abs(i_l.cpu().numpy()), np.abs(i_a.cpu().numpy())
+    plo = -np.minimum(heos[:, 1], heos[:, 3])
+    assert np.max(np.abs(o_l.cpu().numpy()[0] - hout[:, 0]) / (hout[:, 0] - plo)) <= 1e-10
+    print("held-out mean Newton steps: learned", i_l.mean(), "acoustic", i_a.mean(), "fallbacks", nfb)
+    assert i_l.mean() < 0.9 * i_a.mean()
+    from tests.parity import TOL_FP64, compare_runs
+    p = W.shock_bubble(0, n=32, radius=0.3, p_shock=1e9, shock_x=0.2)
+    g = m2c.Sim(m2c.config_for(p), p.prim)
+    g.set_guess(net)
+    o = oracle.OracleSim(p)
+    assert g.step(30) == 0 and o.step(30) == 0
+    e = compare_runs(g, o, p)
+    print(e, g.stats())
+    assert e["id_mismatch"] == 0
+    for k in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[k] <= TOL_FP64
