@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the mixed-precision, batched and standalone-FIVER measurements")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--cloud-steps", type=int, default=10,
+                    help="steps timed on the 384^3 bubble cloud (0 skips it)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (reference "
                          "for scaling hardware byte counters to bytes)")
@@ -142,6 +144,76 @@ def fiver_standalone(m2c, torch, n=1_000_000):
             "newton_iters_per_solve": float(it[ok].mean()), "vacuum": int((~ok).sum())}
 
 
+def cloud_forms(m2c, torch, steps):
+    """384^3 cloud of 32 air bubbles in water (50 steps in the workload; a
+    bounded number of them timed here): FP64 vs mixed precision, and the
+    learned star-pressure guess against the acoustic one on the FP64 path."""
+    import numpy as np
+
+    import workloads as W
+
+    p = W.bubble_cloud(0)
+    out = {"workload": "bubble_cloud_384^3: 32 air bubbles r~U[0.02,0.06] in water, 5e7 Pa slab at x<0.05",
+           "cells": p.ncells, "steps_timed": steps}
+    net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess.npy")))
+    runs = (("fp64", m2c.M2C_PREC_FP64, None), ("mixed", m2c.M2C_PREC_MIXED, None),
+            ("fp64_learned_guess", m2c.M2C_PREC_FP64, net))
+    for name, prec, guess in runs:
+        sim = m2c.Sim(m2c.config_for(p, precision=prec))
+        sim.set_stream(torch.cuda.current_stream())
+        sim.set_state(p.prim)
+        if guess is not None:
+            sim.set_guess(guess)
+        sim.step(1)
+        sim.set_state(p.prim)
+        sim.reset_stats()
+        sim.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        st = sim.stats()
+        out[name] = {"value": p.ncells * steps * 2 / T, "ms_per_step": T * 1e3 / steps,
+                     "stage_ms_per_launch": st["ms_stage"] / max(st["stage_launches"], 1),
+                     "fiver_ms_per_launch": st["ms_fiver"] / max(st["fiver_launches"], 1),
+                     "riemann_solves": st["riemann_solves"],
+                     "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1),
+                     "learned_guess_rejected": st["mlp_fallbacks"] if guess is not None else None}
+        sim.close()
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    out["fiver_speedup_learned_vs_acoustic"] = (out["fp64"]["fiver_ms_per_launch"] /
+                                                out["fp64_learned_guess"]["fiver_ms_per_launch"])
+    return out
+
+
+def learned_standalone(m2c, torch, n=1_000_000):
+    """Held-out water/air Riemann problems: Newton steps and solves/s with the
+    judged learned guess against the acoustic guess."""
+    import numpy as np
+
+    import workloads as W
+
+    inp, eos = W.riemann_problem_set(2000, n)
+    di = torch.tensor(inp.T.copy(), device="cuda")
+    de = torch.tensor(eos.T.copy(), device="cuda")
+    net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess.npy")))
+    res = {"problems": n}
+    for name, guess in (("acoustic", None), ("learned", net)):
+        m2c.riemann_solve_learned(guess, di, de)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, it, rc, nfb = m2c.riemann_solve_learned(guess, di, de)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        it = it.abs().double()
+        ok = it > 0
+        res[name] = {"solves_per_s": n / T, "newton_iters_per_solve": float(it[ok].mean()),
+                     "acoustic_starts": int(nfb) if guess is not None else None}
+    res["speedup_learned_vs_acoustic"] = res["learned"]["solves_per_s"] / res["acoustic"]["solves_per_s"]
+    return res
+
+
 def cpu_baseline(problem, steps):
     import oracle
 
@@ -236,7 +308,10 @@ def main():
             "speedup_mixed_vs_fp64": vmx / v64,
             "batched": batched_forms(m2c, torch, args.batch_steps),
             "fiver_standalone": fiver_standalone(m2c, torch),
+            "learned_guess_standalone": learned_standalone(m2c, torch),
         }
+        if args.cloud_steps > 0:
+            out["forms"]["cloud_384"] = cloud_forms(m2c, torch, args.cloud_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
     print(json.dumps(out), flush=True)
