@@ -50,17 +50,25 @@
 
 namespace m2c {
 
+// Threads of a stage block: the tile's cells rounded up to whole wavefronts.
+constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
+
 // One tile (TX x TY columns, a.kz planes) of one stage.  Called once per
 // block by the single-grid kernel and once per work item by the persistent
 // batched kernel; the whole block takes part.
 template <int STAGE, int TX, int TY, typename TF>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
-    constexpr int NT = TX * TY, LX = TX + 4, LY = TY + 4, PL = LX * LY;
+    // CT cells per tile; the block is CT rounded up to whole wavefronts (a
+    // 16x15 tile has 511 in-plane faces: exactly two rounds of the 256
+    // threads, where a 16x16 tile needs a third, one-wave round)
+    constexpr int CT = TX * TY, NT = stage_threads(TX, TY), LX = TX + 4, LY = TY + 4, PL = LX * LY;
     constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1), NF = NXF + NYF;
-    __shared__ TF sQ[5 * PL];              // primitives rho,u,v,w,p of the plane + halo
-    __shared__ double sPhi[PL];            // level set of the plane + halo (always FP64)
-    __shared__ uint8_t sX[PL];             // material ids
+    // plane tiles are double-buffered (even / odd planes), so the next
+    // plane can be staged while slow waves still read the current one
+    __shared__ TF sQ2[2][5 * PL];          // primitives rho,u,v,w,p of the plane + halo
+    __shared__ double sPhi2[2][PL];        // level set of the plane + halo (always FP64)
+    __shared__ uint8_t sX2[2][PL];         // material ids
     __shared__ TF sF[5 * NF];              // in-plane single-material face fluxes
     __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
@@ -90,8 +98,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     const int kz0 = bz * a.kz, kz1 = min(nz, kz0 + a.kz);
 
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const bool cellt = tid < CT;                       // thread owns a tile column
     const int gi = i0 + tx, gj = j0 + ty;
-    const bool inside = gi < nx && gj < ny;
+    const bool inside = cellt && gi < nx && gj < ny;
     bool mirx = false, miry = false;
     const int si = bc_index(gi, nx, G.bc[0], G.bc[1], mirx);
     const int sj = bc_index(gj, ny, G.bc[2], G.bc[3], miry);
@@ -210,7 +219,54 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     const double dt = sc->dt;
     double lam = 0.0;                 // stage 2: max wave-speed sum of own cells
 
+    // Halo ring of a plane (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX
+    // columns), HPT cells per thread at most; its raw state is loaded one
+    // plane ahead (during the residual of the previous plane) and turned
+    // into primitives when the plane is staged.
+    constexpr int HPT = (4 * TX + 4 * TY + NT - 1) / NT;
+    const int nxh = xact ? 4 * TY : 0, nyh = yact ? 4 * TX : 0;
+    auto halo_pos = [&](int h, int& li, int& lj) {
+        if (h < nxh) {
+            const int r = h / 4, s = h % 4;
+            lj = r + 2;
+            li = s < 2 ? s : TX + s;
+        } else {
+            const int hh = h - nxh;
+            const int r = hh / TX, s = hh % TX;
+            li = s + 2;
+            lj = r < 2 ? r : TY + r;
+        }
+    };
+    // FP64 form: the halo of the next plane is prefetched into registers;
+    // the mixed form keeps its register budget for four waves per SIMD and
+    // loads the halo when it stages the plane.
+    constexpr bool PF = sizeof(TF) == sizeof(double);
+    double hw[HPT][6];
+    uint8_t hx[HPT];
+    auto halo_load = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            const int h = tid + q * NT;
+            if (h < nxh + nyh) {
+                int li, lj;
+                halo_pos(h, li, lj);
+                bool mx, my;
+                const int hi_ = bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
+                const int hj_ = bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
+                const uint32_t c = hi_ + nx * hj_ + sxy * k;
+#pragma unroll
+                for (int v = 0; v < 6; ++v) hw[q][v] = ldf(Win + v * N, c);
+                hx[q] = chi[c];
+            }
+        }
+    };
+    if (PF) halo_load(kz0);
+
     for (int k = kz0; k < kz1; ++k) {
+        const int buf = (k - kz0) & 1;
+        TF* const sQ = sQ2[buf];
+        double* const sPhi = sPhi2[buf];
+        uint8_t* const sX = sX2[buf];
         // lead load of plane k+3 (consumed at the end of the iteration)
         double Wn[6];
         uint8_t Xn = 0;
@@ -218,45 +274,35 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         if (zact) load_raw(k + 3, Wn, Xn, mzn);
 
         // (1) own plane-k values into the LDS tile
-        {
+        if (cellt) {
             const int o = (ty + 2) * LX + tx + 2;
 #pragma unroll
             for (int v = 0; v < 5; ++v) sQ[v * PL + o] = Q0[v];
             sPhi[o] = PH[2];
             sX[o] = X0;
         }
-        // (2) halo ring of plane k (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX columns)
-        {
-            const int nxh = xact ? 4 * TY : 0, nyh = yact ? 4 * TX : 0;
-            const uint32_t plane = sxy * k;
-            for (int h = tid; h < nxh + nyh; h += NT) {
+        // (2) halo ring of plane k from the prefetched raw state
+        if (!PF) halo_load(k);
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            const int h = tid + q * NT;
+            if (h < nxh + nyh) {
                 int li, lj;
-                if (h < nxh) {
-                    const int r = h / 4, s = h % 4;
-                    lj = r + 2;
-                    li = s < 2 ? s : TX + s;
-                } else {
-                    const int hh = h - nxh;
-                    const int r = hh / TX, s = hh % TX;
-                    li = s + 2;
-                    lj = r < 2 ? r : TY + r;
-                }
-                bool mx = false, my = false;
-                const int hi_ = bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
-                const int hj_ = bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
-                const uint32_t c = hi_ + nx * hj_ + plane;
-                const uint8_t x = chi[c];
+                halo_pos(h, li, lj);
+                bool mx, my;
+                (void)bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
+                (void)bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
+                const uint8_t x = hx[q];
                 double u, vv, ww;
-                const double r0 = ldf(Win, c);
-                const double p = eos_prim(r0, ldf(Win + N, c), ldf(Win + 2 * N, c), ldf(Win + 3 * N, c), ldf(Win + 4 * N, c),
-                                          pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
+                const double p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], pick(G.gamma, x) - 1.0,
+                                          pick(G.gpc, x), u, vv, ww);
                 const int o = lj * LX + li;
-                sQ[o] = TF(r0);
+                sQ[o] = TF(hw[q][0]);
                 sQ[PL + o] = TF((mx && xact) ? -u : u);
                 sQ[2 * PL + o] = TF((my && yact) ? -vv : vv);
                 sQ[3 * PL + o] = TF(ww);
                 sQ[4 * PL + o] = TF(p);
-                sPhi[o] = ldf(Win + 5 * N, c);
+                sPhi[o] = hw[q][5];
                 sX[o] = x;
             }
         }
@@ -325,6 +371,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (inside) qzhi = zface(k, Q0, S0, X0, Q1, S1, X1, Fzhi);
         }
         __syncthreads();
+        if (PF && k + 1 < kz1) halo_load(k + 1);
 
         // (5) residual and stage update of cell (gi, gj, k)
         if (inside) {
@@ -406,7 +453,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     const int slot = atomicAdd(&sc->nflip, 1);
                     a.flips[slot] = (int)c;
                 } else if (ok) {
-                    const double cs = sqrt(pick(G.gamma, X0) * (p + pick(G.pc, X0)) / wn[0]);
+                    const double cs = sqrt_nr(pick(G.gamma, X0) * (p + pick(G.pc, X0)) * rcp_nr(wn[0]));
                     double l = 0.0;
                     if (xact) l += (fabs(u) + cs) * G.rh[0];
                     if (yact) l += (fabs(vv) + cs) * G.rh[1];
@@ -438,7 +485,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             X1 = X2;
             X2 = Xn;
         }
-        __syncthreads();
+        // no barrier here: the next plane is staged in the other buffer, and
+        // its first barrier orders this plane's reads before any reuse
     }
 
     if (STAGE == 2) {
@@ -464,7 +512,8 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk)
     return (xcd < br ? xcd * (bq + 1) : br * (bq + 1) + (xcd - br) * bq) + idx;
 }
 
-#define M2C_STAGE_BOUNDS(TX, TY, TF) __launch_bounds__(TX * TY, sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES)
+#define M2C_STAGE_BOUNDS(TX, TY, TF) \
+    __launch_bounds__(stage_threads(TX, TY), sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES)
 
 template <int STAGE, int TX, int TY, typename TF>
 __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
@@ -524,9 +573,9 @@ static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
 {
     const int nblk = a.tiles_x * a.tiles_y * a.tiles_z;
     if (stage == 1)
-        hipLaunchKernelGGL((k_stage<1, TX, TY, TF>), dim3(nblk), dim3(TX * TY), 0, s, a);
+        hipLaunchKernelGGL((k_stage<1, TX, TY, TF>), dim3(nblk), dim3(stage_threads(TX, TY)), 0, s, a);
     else
-        hipLaunchKernelGGL((k_stage<2, TX, TY, TF>), dim3(nblk), dim3(TX * TY), 0, s, a);
+        hipLaunchKernelGGL((k_stage<2, TX, TY, TF>), dim3(nblk), dim3(stage_threads(TX, TY)), 0, s, a);
     return hipGetLastError();
 }
 
@@ -537,27 +586,33 @@ static hipError_t launch_tile_batch(int stage, const RunDesc* runs, const int2* 
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<1, TX, TY, TF>, TX * TY, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<2, TX, TY, TF>, TX * TY, 0);
+        e = stage == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<1, TX, TY, TF>,
+                                                                     stage_threads(TX, TY), 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_stage_batch<2, TX, TY, TF>,
+                                                                     stage_threads(TX, TY), 0);
     if (e != hipSuccess) return e;
     long long nblk = (long long)ncu * (per > 0 ? per : 1);
     if (nblk > nitems) nblk = nitems > 0 ? nitems : 1;
     if (stage == 1)
-        hipLaunchKernelGGL((k_stage_batch<1, TX, TY, TF>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, runs, items, nitems);
+        hipLaunchKernelGGL((k_stage_batch<1, TX, TY, TF>), dim3((unsigned)nblk), dim3(stage_threads(TX, TY)), 0, s,
+                           runs, items, nitems);
     else
-        hipLaunchKernelGGL((k_stage_batch<2, TX, TY, TF>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, runs, items, nitems);
+        hipLaunchKernelGGL((k_stage_batch<2, TX, TY, TF>), dim3((unsigned)nblk), dim3(stage_threads(TX, TY)), 0, s,
+                           runs, items, nitems);
     return hipGetLastError();
 }
 
 bool stage_tile_supported(int tx, int ty)
 {
-    return (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 16 && ty == 16) || (tx == 64 && ty == 2);
+    return (tx == 16 && ty == 15) || (tx == 32 && ty == 7) || (tx == 16 && ty == 16) || (tx == 32 && ty == 8) ||
+           (tx == 64 && ty == 2);
 }
 
 #define M2C_TILES(F)                                                                    \
-    F(32, 8)                                                                            \
-    F(64, 4)                                                                            \
+    F(16, 15)                                                                           \
+    F(32, 7)                                                                            \
     F(16, 16)                                                                           \
+    F(32, 8)                                                                            \
     F(64, 2)
 
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s)

@@ -684,7 +684,7 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
 
 int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
 {
-    static const int cands[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {32, 8, 4}, {64, 4, 8}, {64, 4, 4}};
+    static const int cands[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {16, 15, 8}, {32, 7, 8}, {16, 15, 4}};
     if (!c || steps < 1) return M2C_ERR_ARG;
     if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
     HIPCHK(c, hipSetDevice(c->device));

@@ -210,7 +210,7 @@ int run_batch(m2c_batch* b, int32_t nsteps, std::vector<long long>* done_out)
     return first;
 }
 
-const int kTileCandidates[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {32, 8, 4}, {64, 4, 8}, {64, 4, 4}};
+const int kTileCandidates[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {16, 15, 8}, {32, 7, 8}, {16, 15, 4}};
 
 }  // namespace
 

@@ -28,13 +28,52 @@ __device__ __forceinline__ void stf(double* base, uint32_t c, double v)
     *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + (c << 3)) = v;
 }
 
+// ------------------------------------------------------- fast rcp / sqrt --
+// Reciprocal and square root from the hardware estimates refined by
+// Newton-Raphson (reciprocal) and Goldschmidt (square root) iterations,
+// accurate to about one ulp for the positive normal arguments of the flux
+// and EOS formulas; far shorter dependency chains than the correctly
+// rounded library sequences.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+__device__ __forceinline__ float sqrt_nr(float x)
+{
+    const float y = __builtin_amdgcn_rsqf(x);
+    float g = x * y;
+    const float h = 0.5f * y;
+    const float d = fmaf(-g, g, x);
+    return fmaf(d, h, g);
+}
+
 // ---------------------------------------------------------------- EOS ------
 // Conservative -> primitive for one cell; returns the pressure.
 __device__ __forceinline__ double eos_prim(double r, double mx, double my, double mz, double E,
                                            double gm1, double gpc,
                                            double& u, double& v, double& w)
 {
-    const double ri = 1.0 / r;
+    const double ri = rcp_nr(r);
     u = mx * ri;
     v = my * ri;
     w = mz * ri;
@@ -71,15 +110,15 @@ __device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
                                      T rR, T uR, T aR, T bR, T pR,
                                      T g, T pc, T gpc, T inv_gm1, T F[5])
 {
-    const T riL = T(1) / rL, riR = T(1) / rR;
-    const T cL = sqrt(g * (pL + pc) * riL);
-    const T cR = sqrt(g * (pR + pc) * riR);
+    const T riL = rcp_nr(rL), riR = rcp_nr(rR);
+    const T cL = sqrt_nr(g * (pL + pc) * riL);
+    const T cR = sqrt_nr(g * (pR + pc) * riR);
     const T EL = eos_energy<T>(rL, uL, aL, bL, pL, gpc, inv_gm1);
     const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
     const T SL = fmin(uL - cL, uR - cR);
     const T SR = fmax(uL + cL, uR + cR);
     const T dL = rL * (SL - uL), dR = rR * (SR - uR);
-    const T Ss = (pR - pL + uL * dL - uR * dR) / (dL - dR);
+    const T Ss = (pR - pL + uL * dL - uR * dR) * rcp_nr(dL - dR);
 
     const bool left_sup = T(0) <= SL;
     const bool useL = left_sup || (T(0) <= Ss);
@@ -96,7 +135,7 @@ __device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
     Fk[3] = mu * b;
     Fk[4] = (E + p) * u;
     if (star) {
-        const T inv = T(1) / (S - Ss);
+        const T inv = rcp_nr(S - Ss);
         const T fac = r * (S - u) * inv;
         const T Us0 = fac;
         const T Us1 = fac * Ss;
