@@ -262,6 +262,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     };
     if (PF) halo_load(kz0);
 
+    // In-plane face list: face t < NXF is the x-face left of tile column
+    // t % (TX+1) in row t / (TX+1); the others are y-faces below row
+    // (t - NXF) / TX.  Per round: LDS offset of the lower cell << 2 | x-face
+    // << 1 | face inside the grid.
+    constexpr int FR = (NF + NT - 1) / NT;
+    static_assert(FR <= 3, "at most three rounds of in-plane faces");
+    int fdesc[FR];
+#pragma unroll
+    for (int rr = 0; rr < FR; ++rr) {
+        const int t = tid + rr * NT;
+        fdesc[rr] = 0;
+        if (t < NF) {
+            const bool isx = t < NXF;
+            const int tt = isx ? t : t - NXF;
+            const int W_ = isx ? TX + 1 : TX;
+            const int fa = tt % W_, fb = tt / W_;
+            const int oA = isx ? (fb + 2) * LX + (fa + 1) : (fb + 1) * LX + (fa + 2);
+            const int gx = i0 + fa, gy = j0 + fb;
+            const bool valid = isx ? (xact && gx <= nx && gy < ny) : (yact && gx < nx && gy <= ny);
+            fdesc[rr] = (oA << 2) | (isx ? 2 : 0) | (valid ? 1 : 0);
+        }
+    }
+
     for (int k = kz0; k < kz1; ++k) {
         const int buf = (k - kz0) & 1;
         TF* const sQ = sQ2[buf];
@@ -308,19 +331,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         }
         __syncthreads();
 
-        // (3) x- and y-faces of the tile as one work list, one code path
-        for (int t = tid; t < NF; t += NT) {
-            const bool isx = t < NXF;
-            const int tt = isx ? t : t - NXF;
-            const int W_ = isx ? TX + 1 : TX;          // faces per row of the list
-            const int fa = tt % W_, fb = tt / W_;
-            // LDS offsets of the two cells (A lower, B upper) and the step
+        // (3) x- and y-faces of the tile as one work list, one code path (the
+        // list decomposition is the same for every plane, see fdesc)
+#pragma unroll 1
+        for (int rr = 0; rr < FR; ++rr) {
+            const int t = tid + rr * NT;
+            const int fd = rr == 0 ? fdesc[0] : (rr == 1 ? fdesc[1 % FR] : fdesc[2 % FR]);
+            const int oA = fd >> 2;
+            if (!(fd & 1)) continue;
+            const bool isx = fd & 2;
             const int step = isx ? 1 : LX;
-            const int oA = isx ? (fb + 2) * LX + (fa + 1) : (fb + 1) * LX + (fa + 2);
             const int oB = oA + step;
-            const int gx = i0 + fa, gy = j0 + fb;       // x: face left of cell gx; y: below gy
-            const bool valid = isx ? (xact && gx <= nx && gy < ny) : (yact && gx < nx && gy <= ny);
-            if (!valid) continue;
             const int nrm = isx ? 1 : 2, ta = isx ? 2 : 3, tb = isx ? 3 : 1;
             const uint8_t xa = sX[oA], xb = sX[oB];
             if (xa == xb) {
@@ -348,6 +369,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 sS[t] = -1;
             } else {
                 bool m;
+                const int tt = isx ? t : t - NXF;
+                const int W_ = isx ? TX + 1 : TX;
+                const int gx = i0 + tt % W_, gy = j0 + tt / W_;   // x: face left of cell gx; y: below gy
                 uint32_t lower;
                 if (isx) {
                     const int lx = bc_index(gx - 1, nx, G.bc[0], G.bc[1], m);
