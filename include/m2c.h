@@ -164,9 +164,14 @@ int m2c_step_dt(m2c_ctx* ctx, int32_t nsteps, double dt, double* t_out);
 
 int m2c_get_stats(m2c_ctx* ctx, m2c_stats* s);
 int m2c_reset_stats(m2c_ctx* ctx);
-/* 1: time kernel classes with HIP events on the context stream (adds one
- * synchronisation per step); 0: off (default). */
-int m2c_set_profiling(m2c_ctx* ctx, int on);
+/* every >= 1: time the kernel classes of one step in `every` (the first
+ * step after switching on, then every `every`-th step)
+ * with HIP events recorded on the context stream around the kernels; the
+ * events are read when m2c_step returns and summed into ms_stage, ms_fiver,
+ * ms_other and stage_launches of m2c_stats.  Each timed step carries seven
+ * event records (a few microseconds).  0: off (default).  Negative:
+ * M2C_ERR_ARG. */
+int m2c_set_profiling(m2c_ctx* ctx, int every);
 
 /* Interface faces of the current material field: ascending face ids
  * f = 3c + d (face between cell c and its +d neighbour, periodic wrap

@@ -281,8 +281,11 @@ class Sim:
     def reset_stats(self):
         return self._check(self.L.m2c_reset_stats(self.h))
 
-    def set_profiling(self, on=True):
-        return self._check(self.L.m2c_set_profiling(self.h, 1 if on else 0))
+    def set_profiling(self, every=1):
+        """Time one step in `every` with HIP events (True = every step,
+        False or 0 = off)."""
+        every = int(every) if not isinstance(every, bool) else (1 if every else 0)
+        return self._check(self.L.m2c_set_profiling(self.h, every))
 
     def interface_faces(self):
         cnt = C.c_int64(0)

@@ -24,8 +24,7 @@
 namespace m2c {
 
 // Upper neighbour of cell (i,j,k) across axis d, or -1 when the face lies on
-// a non-periodic domain boundary (no interface there: the boundary image
-// carries the boundary cell's material).
+// a non-periodic domain boundary.
 __device__ __forceinline__ long long upper_neighbour(const Grid& G, int i, int j, int k, int d, long long c)
 {
     const long long sxy = (long long)G.nx * G.ny;
@@ -41,45 +40,40 @@ __device__ __forceinline__ long long upper_neighbour(const Grid& G, int i, int j
     return G.bc[5] == BC_PERIODIC ? c - (long long)(G.nz - 1) * sxy : -1;
 }
 
-// Interface-face bits of one cell: bit d set when the +d face separates
-// two materials.
-__device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t* __restrict__ chi,
-                                                   int i, int j, int k, long long c)
+// Interface-face bits of cell c: bit d set when the face towards the +d
+// neighbour separates two materials.  A face on a non-periodic domain
+// boundary is never an interface (the boundary image carries the boundary
+// cell's material); a periodic axis wraps.  Cell indices fit in 32 bits
+// (grids are limited to 2^29 cells).
+__device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t* __restrict__ chi, uint32_t c)
 {
+    const uint32_t nx = G.nx, ny = G.ny, nz = G.nz, sxy = nx * ny;
+    const uint32_t k = c / sxy, r = c - k * sxy, j = r / nx, i = r - j * nx;
     const uint8_t x = chi[c];
     unsigned bits = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (!G.act[d]) continue;
-        const long long n = upper_neighbour(G, i, j, k, d, c);
-        if (n >= 0 && chi[n] != x) bits |= 1u << d;
+    if (G.act[0] && (i + 1 < nx || G.bc[1] == BC_PERIODIC)) {
+        const uint32_t n = i + 1 < nx ? c + 1 : c - (nx - 1);
+        if (chi[n] != x) bits |= 1u;
+    }
+    if (G.act[1] && (j + 1 < ny || G.bc[3] == BC_PERIODIC)) {
+        const uint32_t n = j + 1 < ny ? c + nx : c - (ny - 1) * nx;
+        if (chi[n] != x) bits |= 2u;
+    }
+    if (G.act[2] && (k + 1 < nz || G.bc[5] == BC_PERIODIC)) {
+        const uint32_t n = k + 1 < nz ? c + sxy : c - (nz - 1) * sxy;
+        if (chi[n] != x) bits |= 4u;
     }
     return bits;
 }
 
-// Walk the COMPACT_CELLS_PER_THREAD consecutive cells of this thread,
-// calling f(c, bits) for each cell.
-template <typename F>
-__device__ __forceinline__ void walk_cells(const Grid& G, const uint8_t* __restrict__ chi, long long c0, F f)
+// Cells of a compaction block: wave w owns the COMPACT_CELLS_PER_THREAD * 64
+// consecutive cells from blk * COMPACT_CELLS_PER_BLOCK + w * 64 *
+// COMPACT_CELLS_PER_THREAD; in round e lane l takes cell base + 64 e + l, so
+// each round reads one contiguous run of material ids.
+__device__ __forceinline__ uint32_t compact_base(int blk)
 {
-    if (c0 >= G.N) return;
-    const long long sxy = (long long)G.nx * G.ny;
-    int k = (int)(c0 / sxy);
-    const long long r = c0 - (long long)k * sxy;
-    int j = (int)(r / G.nx);
-    int i = (int)(r - (long long)j * G.nx);
-    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
-        const long long c = c0 + e;
-        if (c >= G.N) break;
-        f(c, cell_face_bits(G, chi, i, j, k, c));
-        if (++i == G.nx) {
-            i = 0;
-            if (++j == G.ny) {
-                j = 0;
-                ++k;
-            }
-        }
-    }
+    return (uint32_t)blk * COMPACT_CELLS_PER_BLOCK + (threadIdx.x >> 6) * (64 * COMPACT_CELLS_PER_THREAD) +
+           (threadIdx.x & 63);
 }
 
 __device__ __forceinline__ int block_sum(int v, int* sRed)
@@ -96,10 +90,13 @@ __device__ __forceinline__ int block_sum(int v, int* sRed)
 __device__ __forceinline__ void count_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sRed[COMPACT_THREADS / 64];
-    const long long c0 = (long long)blk * COMPACT_CELLS_PER_BLOCK +
-                         (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
+    const uint32_t N = (uint32_t)a.g.N, base = compact_base(blk);
     int cnt = 0;
-    walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
+#pragma unroll
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
+        const uint32_t c = base + 64u * e;
+        if (c < N) cnt += __popc(cell_face_bits(a.g, a.chi, c));
+    }
     const int t = block_sum(cnt, sRed);
     if (threadIdx.x == 0) a.blockcnt[blk] = t;
 }
@@ -146,46 +143,104 @@ __device__ __forceinline__ void scan_body(const IfaceArgs& a)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a) { scan_body(a); }
+// End of a step (single grid): counters and simulated time, only when no
+// kernel of the step reported an error.
+__device__ __forceinline__ void end_step_body(DevScalars* sc, int stages)
+{
+    if (sc->err != 0) return;
+    sc->steps_done += 1;
+    sc->t += sc->dt;
+    sc->dt_last = sc->dt;
+    sc->solves += (long long)sc->qlen * stages;
+    sc->flips += sc->nflip;
+}
+
+// Start of a step (single grid): dt from the CFL rule (section "Time
+// integration"; the rule itself is not printed, the reading is dt = CFL /
+// max_i sum over the axes with more than one cell of (|V_d| + c)/h_d) or
+// imposed; clear the accumulators that the step fills for the next step.
+__device__ __forceinline__ void begin_step_body(DevScalars* sc, double cfl, double dt_fixed, double dt_imposed)
+{
+    if (sc->err != 0) return;
+    double dt;
+    if (dt_imposed > 0.0) dt = dt_imposed;
+    else if (dt_fixed > 0.0) dt = dt_fixed;
+    else dt = cfl / __longlong_as_double((long long)sc->lam_bits);
+    sc->dt = dt;
+    sc->lam_bits = 0ull;
+    sc->nflip = 0;
+}
+
+// The scan kernel of a step also closes the previous step of the same
+// m2c_step call (end_prev) and opens this one (begin): both must precede
+// every kernel that reads dt, and follow the phase update of the previous
+// step, which is where the single-block scan sits in the stream.
+__global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a, int end_prev, int begin, double cfl,
+                                               double dt_fixed, double dt_imposed)
+{
+    if (threadIdx.x == 0) {
+        if (end_prev) end_step_body(a.sc, 2);
+        if (begin) begin_step_body(a.sc, cfl, dt_fixed, dt_imposed);
+    }
+    scan_body(a);
+}
+
+__global__ void k_end_step(DevScalars* sc, int stages) { end_step_body(sc, stages); }
+
+hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_end_step, dim3(1), dim3(1), 0, s, sc, stages);
+    return hipGetLastError();
+}
 
 __device__ __forceinline__ void scatter_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sW[COMPACT_THREADS / 64];
     if (a.sc->err != 0) return;
-    const long long c0 = (long long)blk * COMPACT_CELLS_PER_BLOCK +
-                         (long long)threadIdx.x * COMPACT_CELLS_PER_THREAD;
-    int cnt = 0;
-    walk_cells(a.g, a.chi, c0, [&](long long, unsigned bits) { cnt += __popc(bits); });
-    // exclusive prefix of cnt over the block, in thread order
+    const uint32_t N = (uint32_t)a.g.N, base = compact_base(blk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int incl = cnt;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(incl, o);
-        if (lane >= o) incl += y;
+    // face bits of the lane's cells, three per round
+    uint64_t packed = 0;
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
+        const uint32_t c = base + 64u * e;
+        const unsigned bits = c < N ? cell_face_bits(a.g, a.chi, c) : 0u;
+        packed |= (uint64_t)bits << (3 * e);
+        cnt += __popc(bits);
     }
-    if (lane == 63) sW[w] = incl;
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
+    if (lane == 0) sW[w] = cnt;
     __syncthreads();
+    if (cnt == 0) return;                     // wave-uniform
     int off = a.blockcnt[blk];
     for (int k = 0; k < w; ++k) off += sW[k];
-    off += incl - cnt;
-    if (cnt == 0) return;
-    walk_cells(a.g, a.chi, c0, [&](long long c, unsigned bits) {
+    // faces in ascending id order: by cell, then by axis
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
+        const unsigned bits = (unsigned)(packed >> (3 * e)) & 7u;
+        const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u), b2 = __ballot(bits & 4u);
+        if ((b0 | b1 | b2) == 0ull) continue;
+        int o = off + __popcll(b0 & below) + __popcll(b1 & below) + __popcll(b2 & below);
+        const int f0 = (int)(3u * (base + 64u * e));
+#pragma unroll
         for (int d = 0; d < 3; ++d)
             if (bits & (1u << d)) {
-                const int f = (int)(3 * c + d);
-                a.queue[off] = f;
-                a.fslot[f] = off;
-                ++off;
+                a.queue[o] = f0 + d;
+                a.fslot[f0 + d] = o;
+                ++o;
             }
-    });
+        off += __popcll(b0) + __popcll(b1) + __popcll(b2);
+    }
 }
 
 __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a) { scatter_body(a, blockIdx.x); }
 
-hipError_t launch_compact(const IfaceArgs& a, hipStream_t s)
+hipError_t launch_compact(const IfaceArgs& a, bool end_prev, bool begin, double dt_imposed, hipStream_t s)
 {
     hipLaunchKernelGGL(k_count, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a, end_prev ? 1 : 0, begin ? 1 : 0, a.g.cfl,
+                       a.g.dt_fixed, dt_imposed);
     hipLaunchKernelGGL(k_scatter, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
     return hipGetLastError();
 }
@@ -404,7 +459,7 @@ __global__ __launch_bounds__(256) void k_phase(const PhaseArgs a) { phase_body(a
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
 {
     long long nb = (a.g.N + 255) / 256;
-    if (nb > 1024) nb = 1024;
+    if (nb > 256) nb = 256;
     hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
 }

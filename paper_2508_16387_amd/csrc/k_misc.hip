@@ -15,48 +15,11 @@ static unsigned grid_for(long long n, int threads, long long cap = 65536)
 }
 
 // ---------------------------------------------------------------------------
-// Start of a step: dt from the CFL rule (section "Time integration"; the
-// rule itself is not printed, the reading is dt = CFL / max_i sum over the
-// axes with more than one cell of (|V_d| + c)/h_d) or imposed; clear the
-// accumulators that the step fills for the next step.
-__global__ void k_begin_step(DevScalars* sc, double cfl, double dt_fixed, double dt_imposed)
-{
-    if (sc->err != 0) return;
-    double dt;
-    if (dt_imposed > 0.0) dt = dt_imposed;
-    else if (dt_fixed > 0.0) dt = dt_fixed;
-    else dt = cfl / __longlong_as_double((long long)sc->lam_bits);
-    sc->dt = dt;
-    sc->lam_bits = 0ull;
-    sc->nflip = 0;
-}
-
-hipError_t launch_begin_step(DevScalars* sc, const Grid& g, double dt_imposed, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(1), 0, s, sc, g.cfl, g.dt_fixed, dt_imposed);
-    return hipGetLastError();
-}
-
-// End of a step: counters and simulated time (only when no kernel of the
-// step reported an error).
-__global__ void k_end_step(DevScalars* sc, int stages)
-{
-    if (sc->err != 0) return;
-    sc->steps_done += 1;
-    sc->t += sc->dt;
-    sc->dt_last = sc->dt;
-    sc->solves += (long long)sc->qlen * stages;
-    sc->flips += sc->nflip;
-}
-
-hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_end_step, dim3(1), dim3(1), 0, s, sc, stages);
-    return hipGetLastError();
-}
-
-// Batched begin / end of a step: one thread per run; a completed step also
-// flips the run's state parity.
+// Batched begin / end of a step: one thread per run; dt from the CFL rule
+// (section "Time integration"; the reading is dt = CFL / max_i sum over the
+// axes with more than one cell of (|V_d| + c)/h_d) or imposed, accumulators
+// cleared; a completed step advances the counters and flips the run's state
+// parity.
 __global__ void k_begin_batch(const RunDesc* __restrict__ runs, int n, double dt_imposed)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;

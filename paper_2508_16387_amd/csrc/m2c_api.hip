@@ -51,6 +51,8 @@ struct m2c_ctx {
     int tx = 32, ty = 8, kz = 8;
     int tiles[3] = {1, 1, 1};
     bool profiling = false;
+    int prof_every = 1;             // profiling: time one step in prof_every
+    long long prof_seq = 0;         // steps enqueued since profiling was switched on
     MlpDev mlp{};                   // context copy of the learned guess (null: acoustic)
     bool use_mlp = false;
     double* guessbuf = nullptr;     // [qcap] learned guesses of the stage in flight
@@ -215,14 +217,16 @@ int harvest_events(m2c_ctx* c)
     return M2C_OK;
 }
 
-// Enqueue one full time step with state parity p (reads W[p], writes W[1-p]).
-int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
+// Enqueue one full time step with state parity p (reads W[p], writes
+// W[1-p]).  end_prev: the previous step of this call is still open (its
+// counters are advanced by this step's scan kernel).
+int enqueue_step(m2c_ctx* c, int p, double dt_imposed, bool end_prev)
 {
     hipStream_t s = c->stream;
     const int q = 1 - p;
     const bool mixed = c->cfg.precision == M2C_PREC_MIXED;
     hipEvent_t* ev = nullptr;
-    if (c->profiling) {
+    if (c->profiling && c->prof_seq++ % c->prof_every == 0) {
         if ((size_t)(c->ev_steps + 1) * 7 > c->evpool.size()) {
             int rc = harvest_events(c);
             if (rc) return rc;
@@ -230,10 +234,9 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
         ev = c->evpool.data() + (size_t)c->ev_steps * 7;
     }
     if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
-    HIPCHK(c, launch_begin_step(c->sc, c->g, dt_imposed, s));
     IfaceArgs ia = iface_args(c, c->W[p]);
     ia.chi = c->chi[p];
-    HIPCHK(c, launch_compact(ia, s));
+    HIPCHK(c, launch_compact(ia, end_prev, true, dt_imposed, s));
 
     StageArgs sa;
     sa.g = c->g;
@@ -285,7 +288,6 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed)
     pa.qcap = c->qcap;
     pa.sc = c->sc;
     HIPCHK(c, launch_phase(pa, s));
-    HIPCHK(c, launch_end_step(c->sc, 2, s));
     if (ev) {
         HIPCHK(c, hipEventRecord(ev[6], s));
         ++c->ev_steps;
@@ -309,10 +311,11 @@ int run_steps(m2c_ctx* c, int32_t nsteps, double dt_imposed, double* t_out)
     const long long done0 = c->hsc->steps_done;
     int p = c->cur;
     for (int32_t k = 0; k < nsteps; ++k) {
-        rc = enqueue_step(c, p, dt_imposed);
+        rc = enqueue_step(c, p, dt_imposed, k > 0);
         if (rc) return rc;
         p = 1 - p;
     }
+    if (nsteps > 0) HIPCHK(c, launch_end_step(c->sc, 2, c->stream));
     rc = pull_scalars(c);
     if (rc) return rc;
     rc = harvest_events(c);
@@ -606,10 +609,11 @@ int m2c_reset_stats(m2c_ctx* c)
     return M2C_OK;
 }
 
-int m2c_set_profiling(m2c_ctx* c, int on)
+int m2c_set_profiling(m2c_ctx* c, int every)
 {
-    if (!c) return M2C_ERR_ARG;
+    if (!c || every < 0) return M2C_ERR_ARG;
     HIPCHK(c, hipSetDevice(c->device));
+    const int on = every;
     if (on && c->evpool.empty()) {
         c->evpool.resize(7 * 512, nullptr);
         for (auto& e : c->evpool) HIPCHK(c, hipEventCreate(&e));
@@ -619,6 +623,8 @@ int m2c_set_profiling(m2c_ctx* c, int on)
         if (rc) return rc;
     }
     c->profiling = on != 0;
+    c->prof_every = on > 0 ? on : 1;
+    c->prof_seq = 0;
     return M2C_OK;
 }
 
@@ -630,7 +636,7 @@ int m2c_interface_faces(m2c_ctx* c, int32_t* out, int64_t cap, int64_t* count)
     int rc = clear_error(c);
     if (rc) return rc;
     IfaceArgs ia = iface_args(c, c->W[c->cur]);
-    HIPCHK(c, launch_compact(ia, c->stream));
+    HIPCHK(c, launch_compact(ia, false, false, 0.0, c->stream));
     rc = pull_scalars(c);
     if (rc) return rc;
     if (c->hsc->err != 0) {

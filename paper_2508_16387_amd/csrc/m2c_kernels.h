@@ -77,10 +77,14 @@ hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDe
                               int nitems, hipStream_t s);
 
 // Interface kernels (k_interface.hip).
-constexpr int COMPACT_THREADS = 256;
-constexpr int COMPACT_CELLS_PER_THREAD = 16;
+constexpr int COMPACT_THREADS = 1024;
+constexpr int COMPACT_CELLS_PER_THREAD = 4;
 constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THREAD;
-hipError_t launch_compact(const IfaceArgs& a, hipStream_t s);
+// count / scan / scatter of the interface queue; the scan kernel also ends
+// the previous step (end_prev) and starts this one (begin: dt, cleared
+// accumulators)
+hipError_t launch_compact(const IfaceArgs& a, bool end_prev, bool begin, double dt_imposed, hipStream_t s);
+hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s);
 // Batched forms: cmap maps each compaction block to (run, block of run).
@@ -104,8 +108,6 @@ hipError_t launch_points_guess(long long n, const double* in, const double* eos,
                                hipStream_t s);
 
 // Per-step bookkeeping and state conversion (k_misc.hip).
-hipError_t launch_begin_step(DevScalars* sc, const Grid& g, double dt_imposed, hipStream_t s);
-hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
 hipError_t launch_begin_batch(const RunDesc* runs, int nruns, double dt_imposed, hipStream_t s);
 hipError_t launch_end_batch(const RunDesc* runs, int nruns, int stages, hipStream_t s);
 hipError_t launch_lambda(const Grid& g, const double* W, const uint8_t* chi, DevScalars* sc, hipStream_t s);
