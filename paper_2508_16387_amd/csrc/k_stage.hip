@@ -50,6 +50,10 @@
 
 namespace m2c {
 
+// Fields of the per-block material table (FP64): gamma, p_c, gamma p_c,
+// gamma - 1 and 1/(gamma - 1) of each material.
+enum { MAT_GAMMA = 0, MAT_PC, MAT_GPC, MAT_GM1, MAT_IGM1, MAT_FIELDS };
+
 // Threads of a stage block: the tile's cells rounded up to whole wavefronts.
 constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 
@@ -73,17 +77,42 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
+    // FP64 form: material parameters indexed by material id, so that a
+    // per-lane id costs one LDS read per parameter instead of a select
+    // between two scalar register pairs (measured faster in FP64, slower in
+    // the mixed form, which keeps the selects)
+    constexpr bool LMAT = sizeof(TF) == sizeof(double);
+    __shared__ double sMat[2][MAT_FIELDS];
 
     // Skip the tile when an earlier kernel of the step failed; the flag is
     // read once per block so that the whole block takes the same branch
     // (other blocks may raise it meanwhile).
     DevScalars* sc = a.sc;
+    const Grid& G = a.g;
     __syncthreads();
     if (threadIdx.x == 0) sErr = sc->err;
+    if (LMAT && threadIdx.x < 2) {
+        const int m = threadIdx.x;
+        sMat[m][MAT_GAMMA] = G.gamma[m];
+        sMat[m][MAT_PC] = G.pc[m];
+        sMat[m][MAT_GPC] = G.gpc[m];
+        sMat[m][MAT_GM1] = G.gamma[m] - 1.0;
+        sMat[m][MAT_IGM1] = G.inv_gm1[m];
+    }
     __syncthreads();
     if (sErr != 0) return;
+    // parameter f of material x
+    auto mat = [&](int x, int f) -> double {
+        if constexpr (LMAT) return sMat[x][f];
+        switch (f) {
+            case MAT_GAMMA: return pick(G.gamma, x);
+            case MAT_PC: return pick(G.pc, x);
+            case MAT_GPC: return pick(G.gpc, x);
+            case MAT_GM1: return pick(G.gamma, x) - 1.0;
+            default: return pick(G.inv_gm1, x);
+        }
+    };
 
-    const Grid& G = a.g;
     const int nx = G.nx, ny = G.ny, nz = G.nz;
     const long long N = G.N;
     const bool xact = G.act[0], yact = G.act[1], zact = G.act[2];
@@ -121,7 +150,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // Primitives of a raw state, velocities mirrored at wall images.
     auto to_prim = [&](const double w[6], uint8_t x, bool mz, TF q[5]) {
         double u, vv, ww;
-        const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, vv, ww);
+        const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], mat(x, MAT_GM1), mat(x, MAT_GPC), u, vv, ww);
         q[0] = TF(w[0]);
         q[1] = TF(mirx ? -u : u);
         q[2] = TF(miry ? -vv : vv);
@@ -143,8 +172,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                      uint8_t xu, TF F[5]) -> int {
         if (xl == xu) {
             TF Fr[5];
-            const TF g = TF(pick(G.gamma, xl)), pc = TF(pick(G.pc, xl)), gpc = TF(pick(G.gpc, xl)),
-                     igm1 = TF(pick(G.inv_gm1, xl));
+            const TF g = TF(mat(xl, MAT_GAMMA)), pc = TF(mat(xl, MAT_PC)), gpc = TF(mat(xl, MAT_GPC)),
+                     igm1 = TF(mat(xl, MAT_IGM1));
             // face frame: normal w, tangential u, v
             hllc<TF>(ql[0] + TF(0.5) * sl[0], ql[3] + TF(0.5) * sl[3], ql[1] + TF(0.5) * sl[1],
                      ql[2] + TF(0.5) * sl[2], ql[4] + TF(0.5) * sl[4], qu[0] - TF(0.5) * su[0],
@@ -241,19 +270,35 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // the mixed form keeps its register budget for four waves per SIMD and
     // loads the halo when it stages the plane.
     constexpr bool PF = sizeof(TF) == sizeof(double);
+    // plane-independent part of the halo elements of this thread: LDS
+    // offset (-1: none), source column in the xy-plane, wall-image flags
+    int hofs[HPT];
+    uint32_t hcol[HPT];
+    unsigned hmir = 0;
+#pragma unroll
+    for (int q = 0; q < HPT; ++q) {
+        const int h = tid + q * NT;
+        hofs[q] = -1;
+        hcol[q] = 0;
+        if (h < nxh + nyh) {
+            int li, lj;
+            halo_pos(h, li, lj);
+            bool mx, my;
+            const int hi_ = bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
+            const int hj_ = bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
+            hofs[q] = lj * LX + li;
+            hcol[q] = hi_ + (uint32_t)nx * hj_;
+            hmir |= ((mx && xact) ? 1u : 0u) << (2 * q);
+            hmir |= ((my && yact) ? 2u : 0u) << (2 * q);
+        }
+    }
     double hw[HPT][6];
     uint8_t hx[HPT];
     auto halo_load = [&](int k) {
 #pragma unroll
         for (int q = 0; q < HPT; ++q) {
-            const int h = tid + q * NT;
-            if (h < nxh + nyh) {
-                int li, lj;
-                halo_pos(h, li, lj);
-                bool mx, my;
-                const int hi_ = bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
-                const int hj_ = bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
-                const uint32_t c = hi_ + nx * hj_ + sxy * k;
+            if (hofs[q] >= 0) {
+                const uint32_t c = hcol[q] + sxy * k;
 #pragma unroll
                 for (int v = 0; v < 6; ++v) hw[q][v] = ldf(Win + v * N, c);
                 hx[q] = chi[c];
@@ -308,21 +353,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         if (!PF) halo_load(k);
 #pragma unroll
         for (int q = 0; q < HPT; ++q) {
-            const int h = tid + q * NT;
-            if (h < nxh + nyh) {
-                int li, lj;
-                halo_pos(h, li, lj);
-                bool mx, my;
-                (void)bc_index(i0 + li - 2, nx, G.bc[0], G.bc[1], mx);
-                (void)bc_index(j0 + lj - 2, ny, G.bc[2], G.bc[3], my);
+            if (hofs[q] >= 0) {
+                const bool mx = (hmir >> (2 * q)) & 1u, my = (hmir >> (2 * q)) & 2u;
                 const uint8_t x = hx[q];
                 double u, vv, ww;
-                const double p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], pick(G.gamma, x) - 1.0,
-                                          pick(G.gpc, x), u, vv, ww);
-                const int o = lj * LX + li;
+                const double p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], mat(x, MAT_GM1),
+                                          mat(x, MAT_GPC), u, vv, ww);
+                const int o = hofs[q];
                 sQ[o] = TF(hw[q][0]);
-                sQ[PL + o] = TF((mx && xact) ? -u : u);
-                sQ[2 * PL + o] = TF((my && yact) ? -vv : vv);
+                sQ[PL + o] = TF(mx ? -u : u);
+                sQ[2 * PL + o] = TF(my ? -vv : vv);
                 sQ[3 * PL + o] = TF(ww);
                 sQ[4 * PL + o] = TF(p);
                 sPhi[o] = hw[q][5];
@@ -359,8 +399,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     qb[v] = b0 - TF(0.5) * sb;
                 }
                 TF Fr[5];
-                hllc<TF>(qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], TF(pick(G.gamma, xa)),
-                         TF(pick(G.pc, xa)), TF(pick(G.gpc, xa)), TF(pick(G.inv_gm1, xa)), Fr);
+                hllc<TF>(qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], TF(mat(xa, MAT_GAMMA)),
+                         TF(mat(xa, MAT_PC)), TF(mat(xa, MAT_GPC)), TF(mat(xa, MAT_IGM1)), Fr);
                 sF[t] = Fr[0];
                 sF[nrm * NF + t] = Fr[1];
                 sF[ta * NF + t] = Fr[2];
@@ -464,8 +504,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 wn[5] = 0.5 * ldf(a.W0 + 5 * N, c) + 0.5 * (PH[2] + dt * (-Ls));
             }
             double u, vv, ww;
-            const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], pick(G.gamma, X0) - 1.0, pick(G.gpc, X0), u, vv, ww);
-            const bool ok = wn[0] > 0.0 && p + pick(G.pc, X0) > 0.0 && isfinite(p) && isfinite(u) && isfinite(vv) &&
+            const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
+            const bool ok = wn[0] > 0.0 && p + mat(X0, MAT_PC) > 0.0 && isfinite(p) && isfinite(u) && isfinite(vv) &&
                             isfinite(ww) && isfinite(wn[5]);
             if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
 #pragma unroll
@@ -477,7 +517,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     const int slot = atomicAdd(&sc->nflip, 1);
                     a.flips[slot] = (int)c;
                 } else if (ok) {
-                    const double cs = sqrt_nr(pick(G.gamma, X0) * (p + pick(G.pc, X0)) * rcp_nr(wn[0]));
+                    const double cs = sqrt_nr(mat(X0, MAT_GAMMA) * (p + mat(X0, MAT_PC)) * rcp_nr(wn[0]));
                     double l = 0.0;
                     if (xact) l += (fabs(u) + cs) * G.rh[0];
                     if (yact) l += (fabs(vv) + cs) * G.rh[1];

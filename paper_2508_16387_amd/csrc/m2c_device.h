@@ -92,10 +92,12 @@ __device__ __forceinline__ T eos_energy(T r, T u, T v, T w, T p, T gpc, T inv_gm
 // MC-limited slope: with theta = dm/dp the paper's phi(theta) dp on a uniform
 // grid equals minmod(alpha dm, (dm + dp)/2, alpha dp); this is the
 // division-free form of the same function.
+// (alpha min(|dm|, |dp|) equals min(alpha |dm|, alpha |dp|) exactly, since
+// rounding is monotone.)
 template <typename T>
 __device__ __forceinline__ T mc_slope(T dm, T dp, T alpha)
 {
-    const T a = fmin(fmin(alpha * fabs(dm), T(0.5) * fabs(dm + dp)), alpha * fabs(dp));
+    const T a = fmin(alpha * fmin(fabs(dm), fabs(dp)), T(0.5) * fabs(dm + dp));
     return (dm * dp > T(0)) ? copysign(a, dp) : T(0);
 }
 
