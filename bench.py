@@ -147,6 +147,26 @@ def fiver_standalone(m2c, torch, n=1_000_000):
             "newton_iters_per_solve": float(it[ok].mean()), "vacuum": int((~ok).sum())}
 
 
+def host_round_trip(m2c, torch, problem, steps):
+    """The same FP64 run with the state handed over in host memory: upload
+    (primitive -> conservative on the device), `steps` steps, download.  A
+    PCIe-inclusive rate beside the device-resident headline value."""
+    sim = m2c.Sim(m2c.config_for(problem, precision=m2c.M2C_PREC_FP64))
+    sim.set_stream(torch.cuda.current_stream())
+    sim.set_state(problem.prim)
+    sim.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.set_state(problem.prim)
+    t1 = time.perf_counter()
+    sim.step(steps)
+    t2 = time.perf_counter()
+    sim.get_state()
+    t3 = time.perf_counter()
+    return {"steps": steps, "upload_ms": (t1 - t0) * 1e3, "steps_ms": (t2 - t1) * 1e3,
+            "download_ms": (t3 - t2) * 1e3, "value_pcie_inclusive": problem.ncells * steps * 2 / (t3 - t0)}
+
+
 def cloud_forms(m2c, torch, steps):
     """384^3 cloud of 32 air bubbles in water (50 steps in the workload; a
     bounded number of them timed here): FP64 vs mixed precision, and the
@@ -316,6 +336,7 @@ def main():
             "batched": batched_forms(m2c, torch, args.batch_steps),
             "fiver_standalone": fiver_standalone(m2c, torch),
             "learned_guess_standalone": learned_standalone(m2c, torch),
+            "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
         }
         if args.cloud_steps > 0:
             out["forms"]["cloud_384"] = cloud_forms(m2c, torch, args.cloud_steps)

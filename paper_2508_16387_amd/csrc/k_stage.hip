@@ -59,8 +59,9 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 
 // One tile (TX x TY columns, a.kz planes) of one stage.  Called once per
 // block by the single-grid kernel and once per work item by the persistent
-// batched kernel; the whole block takes part.
-template <int STAGE, int TX, int TY, typename TF>
+// batched kernel; the whole block takes part.  LM: material parameters from
+// an LDS table (see below).
+template <int STAGE, int TX, int TY, typename TF, bool LM>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
     // CT cells per tile; the block is CT rounded up to whole wavefronts (a
@@ -77,11 +78,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
-    // FP64 form: material parameters indexed by material id, so that a
-    // per-lane id costs one LDS read per parameter instead of a select
-    // between two scalar register pairs (measured faster in FP64, slower in
-    // the mixed form, which keeps the selects)
-    constexpr bool LMAT = sizeof(TF) == sizeof(double);
+    // LM: material parameters indexed by material id, so that a per-lane
+    // id costs one LDS read per parameter instead of a select between two
+    // scalar register pairs.  Measured faster for the single-grid FP64
+    // kernel; the mixed form and the batched kernel (whose register budget
+    // it would exceed) keep the selects.
+    constexpr bool LMAT = LM;
     __shared__ double sMat[2][MAT_FIELDS];
 
     // Skip the tile when an earlier kernel of the step failed; the flag is
@@ -582,7 +584,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk)
 template <int STAGE, int TX, int TY, typename TF>
 __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
 {
-    stage_tile<STAGE, TX, TY, TF>(a, xcd_tile(blockIdx.x, gridDim.x));
+    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double)>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Persistent batched stage: the grid is sized to the resident capacity and
@@ -627,7 +629,7 @@ __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage_batch(const RunDesc* __rest
         a.tiles_y = R.tiles_y;
         a.tiles_z = R.tiles_z;
         a.kz = R.kz;
-        stage_tile<STAGE, TX, TY, TF>(a, it.y);
+        stage_tile<STAGE, TX, TY, TF, false>(a, it.y);
     }
 }
 

