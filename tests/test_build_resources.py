@@ -1,0 +1,68 @@
+"""Register and LDS budget of the stage kernels (compile-time, no GPU).
+
+The FP64 stage kernels are sized for two waves per SIMD without private-
+memory spills; the mixed-precision ones for four waves per SIMD.  A change
+that silently pushes a kernel past its budget (spills to scratch, or a drop
+in occupancy) costs far more than it saves, so the compiler's own resource
+report is checked here."""
+from __future__ import annotations
+
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2508_16387_amd import build as B
+
+HIPCC = B.hipcc()
+
+
+@pytest.fixture(scope="module")
+def stage_resources(tmp_path_factory):
+    if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    obj = tmp_path_factory.mktemp("res") / "k_stage.o"
+    src = os.path.join(B.CSRC, "k_stage.hip")
+    r = subprocess.run([HIPCC, *B.FLAGS, "-c", src, "-o", str(obj), "-Rpass-analysis=kernel-resource-usage"],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = {}
+    name = None
+    for line in r.stderr.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            out[name] = {}
+            continue
+        for key, pat in (("vgpr", r"VGPRs: (\d+)"), ("agpr", r"AGPRs: (\d+)"),
+                         ("scratch", r"ScratchSize \[bytes/lane\]: (\d+)"),
+                         ("occupancy", r"Occupancy \[waves/SIMD\]: (\d+)"),
+                         ("lds", r"LDS Size \[bytes/block\]: (\d+)")):
+            m = re.search(pat, line)
+            if m and name:
+                out[name][key] = int(m.group(1))
+    return out
+
+
+# the 64x2 tile exists for quasi-1D grids only; its budget is not tuned
+TUNED = ("Li16ELi16E", "Li32ELi8E", "Li16ELi15E", "Li32ELi7E")
+
+
+def test_fp64_stage_kernels_fit_two_waves_without_spills(stage_resources):
+    ks = {n: r for n, r in stage_resources.items() if "k_stage" in n and "Ed" in n and any(t in n for t in TUNED)}
+    assert len(ks) == 16, sorted(ks)
+    for n, r in ks.items():
+        assert r["scratch"] == 0, (n, r)
+        assert r["agpr"] == 0, (n, r)
+        assert r["occupancy"] >= 2, (n, r)
+        assert 2 * r["lds"] <= 160 * 1024, (n, r)
+
+
+def test_mixed_stage_kernels_keep_four_waves(stage_resources):
+    ks = {n: r for n, r in stage_resources.items() if "k_stage" in n and "Ef" in n and any(t in n for t in TUNED)}
+    assert len(ks) == 16, sorted(ks)
+    for n, r in ks.items():
+        assert r["occupancy"] == 4, (n, r)
+        assert r["vgpr"] <= 128, (n, r)
