@@ -56,7 +56,13 @@ def _samples(p, nrand=10, niface=10, seed=0):
     return out
 
 
-def _check_samples(p, w_gpu, dt, samples):
+# mixed form: FP32 reconstruction and single-material fluxes; the bound is
+# the one the mixed form is held to on whole grids (the measured error is
+# printed)
+TOL_MIXED = 1e-3
+
+
+def _check_samples(p, w_gpu, dt, samples, tol=TOL_FP64):
     w_all = w_gpu.reshape(6, -1)
     scale = np.maximum(np.max(np.abs(w_all), axis=1), [1.0, 1.0, 1.0, 1.0, 1.0, min(p.dx())])
     worst = np.zeros(6)
@@ -67,18 +73,18 @@ def _check_samples(p, w_gpu, dt, samples):
         wo = o.cons()[:, ck, cj, ci]
         wg = w_gpu[:, k, j, i]
         worst = np.maximum(worst, np.abs(wg - wo) / scale)
-    print("sampled max rel err per field", worst)
-    assert np.all(worst <= TOL_FP64)
+    print("sampled max rel err per field (rho, rho u, rho v, rho w, rho E, phi)", worst)
+    assert np.all(worst <= tol)
 
 
-@pytest.mark.parametrize("prec", [0])
+@pytest.mark.parametrize("prec", [0, 1])
 def test_bubble_cloud_384_sampled(m2c, prec):
     p = W.bubble_cloud(0)
     g = m2c.Sim(m2c.config_for(p, precision=prec), p.prim)
     assert g.step(1) == 0
     dt = g.stats()["dt_last"]
     assert dt > 0
-    _check_samples(p, g.get_conserved(), dt, _samples(p))
+    _check_samples(p, g.get_conserved(), dt, _samples(p), tol=TOL_FP64 if prec == 0 else TOL_MIXED)
 
 
 def test_shock_bubble_128_sampled_after_learned_guess(m2c):
