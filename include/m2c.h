@@ -124,8 +124,13 @@ void m2c_config_default(m2c_config* c);
 int m2c_validate_config(const m2c_config* c);
 
 /* Validate the configuration, select device 'current' and allocate every
- * device buffer of the context (about 160 B per cell).  *out is NULL on
- * failure. */
+ * device buffer of the context: 162 B per cell (two full states, the stage
+ * state, two material-id fields, the face -> queue-slot map, the flip list)
+ * plus 148 B per interface-queue slot (id, two one-sided fluxes, star
+ * record); the queue holds 3N slots for grids up to 65536 cells and N
+ * above, about 310 B per cell in all (17.6 GB at 384^3).  A step whose
+ * interface faces exceed the queue fails with M2C_ERR_NOMEM.  *out is NULL
+ * on failure. */
 int m2c_create(const m2c_config* c, m2c_ctx** out);
 void m2c_destroy(m2c_ctx* ctx);
 const char* m2c_last_error(const m2c_ctx* ctx);
