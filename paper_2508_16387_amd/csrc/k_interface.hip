@@ -23,23 +23,6 @@
 
 namespace m2c {
 
-// Upper neighbour of cell (i,j,k) across axis d, or -1 when the face lies on
-// a non-periodic domain boundary.
-__device__ __forceinline__ long long upper_neighbour(const Grid& G, int i, int j, int k, int d, long long c)
-{
-    const long long sxy = (long long)G.nx * G.ny;
-    if (d == 0) {
-        if (i + 1 < G.nx) return c + 1;
-        return G.bc[1] == BC_PERIODIC ? c - (G.nx - 1) : -1;
-    }
-    if (d == 1) {
-        if (j + 1 < G.ny) return c + G.nx;
-        return G.bc[3] == BC_PERIODIC ? c - (long long)(G.ny - 1) * G.nx : -1;
-    }
-    if (k + 1 < G.nz) return c + sxy;
-    return G.bc[5] == BC_PERIODIC ? c - (long long)(G.nz - 1) * sxy : -1;
-}
-
 // Interface-face bits of cell c: bit d set when the face towards the +d
 // neighbour separates two materials.  A face on a non-periodic domain
 // boundary is never an interface (the boundary image carries the boundary
@@ -252,14 +235,14 @@ hipError_t launch_compact(const IfaceArgs& a, bool end_prev, bool begin, double 
 //   F_lower = HLLC(W_L, W*_L; EOS of the lower cell)
 //   F_upper = HLLC(W*_R, W_R; EOS of the upper cell)
 // with the arguments ordered along the face normal.
-__device__ __forceinline__ void cell_prim(const Grid& G, const double* __restrict__ W, long long c, int x,
+__device__ __forceinline__ void cell_prim(const Grid& G, const double* __restrict__ W, uint32_t c, int x,
                                           double q[5])
 {
-    const long long N = G.N;
+    const uint32_t N = (uint32_t)G.N;
     double u, v, w;
-    q[4] = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], G.gamma[x] - 1.0, G.gpc[x],
-                    u, v, w);
-    q[0] = W[c];
+    q[4] = eos_prim(ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
+                    pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, v, w);
+    q[0] = ldf(W, c);
     q[1] = u;
     q[2] = v;
     q[3] = w;
@@ -267,28 +250,28 @@ __device__ __forceinline__ void cell_prim(const Grid& G, const double* __restric
 
 __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk)
 {
+    __shared__ unsigned long long sCnt[3][4];
+    __shared__ int sErr;
     DevScalars* sc = a.sc;
-    if (sc->err != 0) return;
+    // skip when an earlier kernel failed; read once so that the whole block
+    // takes the same branch (this kernel's own reports may raise the flag)
+    if (threadIdx.x == 0) sErr = sc->err;
+    __syncthreads();
+    if (sErr != 0) return;
     const Grid& G = a.g;
     const int n = sc->qlen;
-    const long long sxy = (long long)G.nx * G.ny;
     long long iters = 0, fallbacks = 0, mlp_fb = 0;
     for (int q = blk * blockDim.x + threadIdx.x; q < n; q += nblk * blockDim.x) {
-        const int f = a.queue[q];
-        const long long c = f / 3;
-        const int d = f - 3 * (int)c;
-        const int k = (int)(c / sxy);
-        const long long r = c - (long long)k * sxy;
-        const int j = (int)(r / G.nx);
-        const int i = (int)(r - (long long)j * G.nx);
-        const long long cn = upper_neighbour(G, i, j, k, d, c);
+        uint32_t c, cn;
+        int d;
+        face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], c, cn, d);
         const int xa = a.chi[c], xb = a.chi[cn];
         double qa[5], qb[5];
         cell_prim(G, a.Win, c, xa, qa);
         cell_prim(G, a.Win, cn, xb, qb);
         const int t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
         const double ua = qa[1 + d], ub = qb[1 + d];
-        const double gA = G.gamma[xa], pcA = G.pc[xa], gB = G.gamma[xb], pcB = G.pc[xb];
+        const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
         double out[4];
         bool used = false;
         const bool hg = a.guess != nullptr;
@@ -303,10 +286,10 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         fallbacks += it < 0;
         const double ps = out[0], us = out[1];
         double Fl[5], Fu[5];
-        hllc<double>(qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA, G.gpc[xa],
-                     G.inv_gm1[xa], Fl);
-        hllc<double>(out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB, G.gpc[xb],
-                     G.inv_gm1[xb], Fu);
+        hllc<double>(qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA, pick(G.gpc, xa),
+                     pick(G.inv_gm1, xa), Fl);
+        hllc<double>(out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB, pick(G.gpc, xb),
+                     pick(G.inv_gm1, xb), Fu);
         const long long Q = a.qcap;
         // face frame (mass, normal, t1, t2, energy) -> global components
         a.fluxF[0 * Q + q] = Fl[0];
@@ -330,30 +313,41 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
             a.star[7 * Q + q] = qb[t2];
         }
     }
-    // one atomic per wavefront for the counters
+    // counters: one atomic per block and counter (same-address atomics from
+    // every wavefront serialise into a measurable tail)
     for (int o = 32; o > 0; o >>= 1) {
         iters += __shfl_xor(iters, o);
         fallbacks += __shfl_xor(fallbacks, o);
         mlp_fb += __shfl_xor(mlp_fb, o);
     }
-    if ((threadIdx.x & 63) == 0 && (iters | fallbacks | mlp_fb)) {
-        atomicAdd((unsigned long long*)&sc->newton_iters, (unsigned long long)iters);
-        atomicAdd((unsigned long long*)&sc->fallbacks, (unsigned long long)fallbacks);
-        if (mlp_fb) atomicAdd((unsigned long long*)&sc->mlp_fallbacks, (unsigned long long)mlp_fb);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sCnt[0][w] = iters;
+        sCnt[1][w] = fallbacks;
+        sCnt[2][w] = mlp_fb;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int k = 0; k < nw; ++k) t += sCnt[threadIdx.x][k];
+        unsigned long long* dst = threadIdx.x == 0 ? (unsigned long long*)&sc->newton_iters
+                                 : (threadIdx.x == 1 ? (unsigned long long*)&sc->fallbacks
+                                                     : (unsigned long long*)&sc->mlp_fallbacks);
+        if (t) atomicAdd(dst, t);
     }
 }
 
-__global__ __launch_bounds__(64) void k_fiver(const IfaceArgs a, int record)
+__global__ __launch_bounds__(256) void k_fiver(const IfaceArgs a, int record)
 {
     fiver_body(a, record, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
 {
-    long long nb = (a.qcap + 63) / 64;
-    if (nb > 4096) nb = 4096;
+    long long nb = (a.qcap + 255) / 256;
+    if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(64), 0, s, a, record ? 1 : 0);
+    hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -420,14 +414,14 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk
         } else {
             double u, vv, w;
             q[4] = eos_prim(a.W[c], a.W[N + c], a.W[2 * N + c], a.W[3 * N + c], a.W[4 * N + c],
-                            G.gamma[A] - 1.0, G.gpc[A], u, vv, w);
+                            pick(G.gamma, A) - 1.0, pick(G.gpc, A), u, vv, w);
             q[0] = a.W[c];
             q[1] = u;
             q[2] = vv;
             q[3] = w;
             ++orphans;
         }
-        bool ok = q[0] > 0.0 && q[4] + G.pc[B] > 0.0;
+        bool ok = q[0] > 0.0 && q[4] + pick(G.pc, B) > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) ok = ok && isfinite(q[v]);
         if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
@@ -435,9 +429,9 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk
         a.W[N + c] = q[0] * q[1];
         a.W[2 * N + c] = q[0] * q[2];
         a.W[3 * N + c] = q[0] * q[3];
-        a.W[4 * N + c] = eos_energy<double>(q[0], q[1], q[2], q[3], q[4], G.gpc[B], G.inv_gm1[B]);
+        a.W[4 * N + c] = eos_energy<double>(q[0], q[1], q[2], q[3], q[4], pick(G.gpc, B), pick(G.inv_gm1, B));
         if (ok) {
-            const double cs = sqrt(G.gamma[B] * (q[4] + G.pc[B]) / q[0]);
+            const double cs = sqrt(pick(G.gamma, B) * (q[4] + pick(G.pc, B)) / q[0]);
             double l = 0.0;
             for (int d = 0; d < 3; ++d)
                 if (G.act[d]) l += (fabs(q[1 + d]) + cs) * G.rh[d];

@@ -75,9 +75,9 @@ __global__ __launch_bounds__(256) void k_lambda(const Grid G, const double* __re
         const int x = chi[c];
         double u, v, w;
         const double r = W[c];
-        const double p = eos_prim(r, W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], G.gamma[x] - 1.0,
-                                  G.gpc[x], u, v, w);
-        const double cs = sqrt(G.gamma[x] * (p + G.pc[x]) / r);
+        const double p = eos_prim(r, W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
+                                  pick(G.gpc, x), u, v, w);
+        const double cs = sqrt(pick(G.gamma, x) * (p + pick(G.pc, x)) / r);
         double l = 0.0;
         if (G.act[0]) l += (fabs(u) + cs) * G.rh[0];
         if (G.act[1]) l += (fabs(v) + cs) * G.rh[1];
@@ -118,13 +118,13 @@ __global__ __launch_bounds__(256) void k_prim_to_cons(const Grid G, const double
         const double phi = P[5 * N + c];
         const int x = phi < 0.0 ? 1 : 0;
         const bool ok = isfinite(r) && isfinite(u) && isfinite(v) && isfinite(w) && isfinite(p) &&
-                        isfinite(phi) && r > 0.0 && p + G.pc[x] > 0.0;
+                        isfinite(phi) && r > 0.0 && p + pick(G.pc, x) > 0.0;
         if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
         W[c] = r;
         W[N + c] = r * u;
         W[2 * N + c] = r * v;
         W[3 * N + c] = r * w;
-        W[4 * N + c] = eos_energy<double>(r, u, v, w, p, G.gpc[x], G.inv_gm1[x]);
+        W[4 * N + c] = eos_energy<double>(r, u, v, w, p, pick(G.gpc, x), pick(G.inv_gm1, x));
         W[5 * N + c] = phi;
         chi[c] = (uint8_t)x;
     }
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_cons_to_prim(const Grid G, const double
          c += (long long)gridDim.x * blockDim.x) {
         const int x = chi[c];
         double u, v, w;
-        const double p = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], G.gamma[x] - 1.0,
-                                  G.gpc[x], u, v, w);
+        const double p = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
+                                  pick(G.gpc, x), u, v, w);
         P[c] = W[c];
         P[N + c] = u;
         P[2 * N + c] = v;

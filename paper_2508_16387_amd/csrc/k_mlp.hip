@@ -398,46 +398,151 @@ hipError_t launch_mlp_sync(const MlpDev& m, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Learned guesses for the FIVER work queue of one stage: 16 queued faces per
-// wave, features from the two cells' own states, guess[q] = p_lo + P exp(y)
-// (non-finite when the network output is).
+// Inference for the guess kernels.  A wave keeps the weights in registers
+// (the A operands of layers 1 and 2, and its lanes' biases and output
+// weights in the D layout) and evaluates 64 samples per pass: each lane
+// computes the features of one sample once, and the four 16-sample MFMA
+// tiles take their B operands from the owning lanes by shuffles.
+struct MlpRegs {
+    bf16x4 a1[4], a2[4][4];
+    float b1[4][4], b2[4][4], w3[4][4], b3;
+};
+
+__device__ __forceinline__ void mlp_load_regs(const float* __restrict__ P, const uint16_t* __restrict__ wbf,
+                                              MlpRegs& w)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int k = 4 * g + e, h = 16 * t + 4 * g + e;
+            w.a1[t][e] = k < MLP_IN ? (short)wbf[MLP_OFF_W1 + (16 * t + r) * MLP_IN + k] : (short)0;
+            w.b1[t][e] = P[MLP_OFF_B1 + h];
+            w.b2[t][e] = P[MLP_OFF_B2 + h];
+            w.w3[t][e] = P[MLP_OFF_W3 + h];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w.a2[t][c][e] = (short)wbf[512 + (16 * t + r) * MLP_H + 16 * c + 4 * g + e];
+    }
+    w.b3 = P[MLP_OFF_B3];
+}
+
+// tanh through the hardware exponential and reciprocal: 1 - 2/(e^{2x} + 1)
+// (about 1e-7 absolute error, far below the BF16 rounding of the operands;
+// saturates correctly for large |x|).
+__device__ __forceinline__ float tanh_fast(float x)
+{
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
+}
+
+// y of the 16 samples whose layer-1 B operand is xb (sample l%16 in every
+// lane of that sample).
+__device__ __forceinline__ float mlp_infer16(const MlpRegs& w, bf16x4 xb)
+{
+    bf16x4 hb[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const f32x4 z = mfma(w.a1[t], xb, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int e = 0; e < 4; ++e) hb[t][e] = to_bf16(tanh_fast(z[e] + w.b1[t][e]));
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z = mfma(w.a2[u][c], hb[c], z);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part += w.w3[u][e] * tanh_fast(z[e] + w.b2[u][e]);
+    }
+    part += __shfl_xor(part, 16);
+    part += __shfl_xor(part, 32);
+    return part + w.b3;
+}
+
+// A problem whose two states differ by less than 1e-3 in pressure (relative
+// to the smaller p + p_c) and in normal velocity (relative to the smaller
+// sound speed): the acoustic guess is then exact to about 1e-6, far closer
+// than the network's, and is taken directly (the guess is left non-finite,
+// which the solver reads as "no candidate").
+__device__ __forceinline__ bool acoustic_suffices(double rL, double uL, double pL, double gL, double pcL, double rR,
+                                                  double uR, double pR, double gR, double pcR)
+{
+    const double aL = pL + pcL, aR = pR + pcR, du = uL - uR;
+    const double c2 = fmin(gL * aL / rL, gR * aR / rR);
+    return fabs(pL - pR) <= 1e-3 * fmin(aL, aR) && du * du <= 1e-6 * c2;
+}
+
+// Guesses of the wave's 64 samples (one per lane): features x, p_lo, P and
+// `skip` (no network: invalid lane or acoustic_suffices).  Tiles whose 16
+// samples all skip are not evaluated.
+__device__ __forceinline__ double guess64(const MlpRegs& w, const float x[8], double plo, double P, bool skip)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
+    const uint64_t need = __ballot(!skip);
+    float y = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if (((need >> (16 * t)) & 0xffffull) == 0ull) continue;     // wave-uniform
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = __shfl(x[k], 16 * t + r);
+        bf16x4 xb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xb[e] = g == 0 ? to_bf16(v[e]) : (g == 1 ? to_bf16(v[4 + e]) : (short)0);
+        const float yt = mlp_infer16(w, xb);
+        const float mine = __shfl(yt, r);
+        if (g == t) y = mine;
+    }
+    return skip ? __builtin_nan("") : plo + P * exp((double)y);
+}
+
+// Learned guesses for the FIVER work queue of one stage: features from the
+// two cells' own states, guess[q] = p_lo + P exp(y) (non-finite when the
+// network output is, or when the acoustic guess suffices).
 __device__ __forceinline__ void guess_body(const IfaceArgs& a, const MlpDev m, int blk, int nblk)
 {
     DevScalars* sc = a.sc;
     if (sc->err != 0) return;
     const Grid& G = a.g;
     const int n = sc->qlen;
-    const int l = threadIdx.x & 63, r = l & 15;
+    const int l = threadIdx.x & 63;
     const int wave = (blk * blockDim.x + threadIdx.x) >> 6, nw = (nblk * blockDim.x) >> 6;
-    const long long N = G.N, sxy = (long long)G.nx * G.ny;
-    for (int c = wave; c * 16 < n; c += nw) {
-        const int q = c * 16 + r;
+    if (wave * 64 >= n) return;                                   // wave-uniform
+    MlpRegs w;
+    bool loaded = false;                                          // weights fetched on first use
+    const uint32_t N = (uint32_t)G.N;
+    for (int c = wave; c * 64 < n; c += nw) {
+        const int q = c * 64 + l;
         float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         double plo = 0.0, P = 1.0;
+        bool skip = true;
         if (q < n) {
-            const int f = a.queue[q];
-            const long long cc = f / 3;
-            const int d = f - 3 * (int)cc;
-            const int k = (int)(cc / sxy);
-            const long long rr = cc - (long long)k * sxy;
-            const int j = (int)(rr / G.nx), i = (int)(rr - (long long)j * G.nx);
-            long long cn;
-            if (d == 0) cn = i + 1 < G.nx ? cc + 1 : cc - (G.nx - 1);
-            else if (d == 1) cn = j + 1 < G.ny ? cc + G.nx : cc - (long long)(G.ny - 1) * G.nx;
-            else cn = k + 1 < G.nz ? cc + sxy : cc - (long long)(G.nz - 1) * sxy;
+            uint32_t cc, cn;
+            int d;
+            face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], cc, cn, d);
             const int xa = a.chi[cc], xb = a.chi[cn];
             double ua, va, wa, ub, vb, wb;
-            const double pa = eos_prim(a.Win[cc], a.Win[N + cc], a.Win[2 * N + cc], a.Win[3 * N + cc],
-                                       a.Win[4 * N + cc], pick(G.gamma, xa) - 1.0, pick(G.gpc, xa), ua, va, wa);
-            const double pb = eos_prim(a.Win[cn], a.Win[N + cn], a.Win[2 * N + cn], a.Win[3 * N + cn],
-                                       a.Win[4 * N + cn], pick(G.gamma, xb) - 1.0, pick(G.gpc, xb), ub, vb, wb);
+            const double* W = a.Win;
+            const double pa = eos_prim(ldf(W, cc), ldf(W + N, cc), ldf(W + 2 * N, cc), ldf(W + 3 * N, cc),
+                                       ldf(W + 4 * N, cc), pick(G.gamma, xa) - 1.0, pick(G.gpc, xa), ua, va, wa);
+            const double pb = eos_prim(ldf(W, cn), ldf(W + N, cn), ldf(W + 2 * N, cn), ldf(W + 3 * N, cn),
+                                       ldf(W + 4 * N, cn), pick(G.gamma, xb) - 1.0, pick(G.gpc, xb), ub, vb, wb);
             const double una = d == 0 ? ua : (d == 1 ? va : wa), unb = d == 0 ? ub : (d == 1 ? vb : wb);
-            mlp_features(a.Win[cc], una, pa, pick(G.gamma, xa), pick(G.pc, xa), a.Win[cn], unb, pb,
-                         pick(G.gamma, xb), pick(G.pc, xb), x, plo, P);
+            const double ra = ldf(W, cc), rb = ldf(W, cn);
+            const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
+            skip = acoustic_suffices(ra, una, pa, gA, pcA, rb, unb, pb, gB, pcB);
+            if (!skip) mlp_features(ra, una, pa, gA, pcA, rb, unb, pb, gB, pcB, x, plo, P);
         }
-        Fwd fw;
-        mlp_fwd16(m.master, m.wbf, xb_of(x), fw);
-        if (l < 16 && q < n) a.guess[q] = plo + P * exp((double)fw.y);
+        if (!loaded && __ballot(!skip) != 0ull) {                 // wave-uniform
+            mlp_load_regs(m.master, m.wbf, w);
+            loaded = true;
+        }
+        const double gs = guess64(w, x, plo, P, skip);
+        if (q < n) a.guess[q] = gs;
     }
 }
 
@@ -448,8 +553,8 @@ __global__ __launch_bounds__(256) void k_fiver_guess(const IfaceArgs a, const Ml
 
 hipError_t launch_fiver_guess(const IfaceArgs& a, const MlpDev& m, hipStream_t s)
 {
-    long long nb = (a.qcap + 63) / 64;
-    if (nb > 2048) nb = 2048;
+    long long nb = (a.qcap + 255) / 256;
+    if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_fiver_guess, dim3((unsigned)nb), dim3(256), 0, s, a, m);
     return hipGetLastError();
@@ -461,27 +566,34 @@ __global__ __launch_bounds__(256) void k_points_guess(long long n, const double*
                                                       const double* __restrict__ eos, const MlpDev m,
                                                       double* __restrict__ guess)
 {
-    const int l = threadIdx.x & 63, r = l & 15;
+    const int l = threadIdx.x & 63;
     const long long wave = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
     const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
-    for (long long c = wave; c * 16 < n; c += nw) {
-        const long long i = c * 16 + r;
+    if (wave * 64 >= n) return;                                   // wave-uniform
+    MlpRegs w;
+    mlp_load_regs(m.master, m.wbf, w);
+    for (long long c = wave; c * 64 < n; c += nw) {
+        const long long i = c * 64 + l;
         float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         double plo = 0.0, P = 1.0;
-        if (i < n)
-            mlp_features(in[i], in[n + i], in[2 * n + i], eos[i], eos[n + i], in[3 * n + i], in[4 * n + i],
-                         in[5 * n + i], eos[2 * n + i], eos[3 * n + i], x, plo, P);
-        Fwd fw;
-        mlp_fwd16(m.master, m.wbf, xb_of(x), fw);
-        if (l < 16 && i < n) guess[i] = plo + P * exp((double)fw.y);
+        bool skip = true;
+        if (i < n) {
+            const double rL = in[i], uL = in[n + i], pL = in[2 * n + i], rR = in[3 * n + i], uR = in[4 * n + i],
+                         pR = in[5 * n + i];
+            const double gL = eos[i], pcL = eos[n + i], gR = eos[2 * n + i], pcR = eos[3 * n + i];
+            skip = acoustic_suffices(rL, uL, pL, gL, pcL, rR, uR, pR, gR, pcR);
+            if (!skip) mlp_features(rL, uL, pL, gL, pcL, rR, uR, pR, gR, pcR, x, plo, P);
+        }
+        const double gs = guess64(w, x, plo, P, skip);
+        if (i < n) guess[i] = gs;
     }
 }
 
 hipError_t launch_points_guess(long long n, const double* in, const double* eos, const MlpDev& m, double* guess,
                                hipStream_t s)
 {
-    long long nb = (n + 63) / 64;
-    if (nb > 8192) nb = 8192;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_points_guess, dim3((unsigned)nb), dim3(256), 0, s, n, in, eos, m, guess);
     return hipGetLastError();

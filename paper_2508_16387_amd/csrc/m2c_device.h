@@ -232,20 +232,38 @@ __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, do
     const double ZL = L.rc, ZR = R.rc;
     const double pac = (ZR * pL + ZL * pR + ZL * ZR * (uL - uR)) / (ZL + ZR);
     double p = fmax(pac, plo + 1e-6 * fmin(pL - plo, pR - plo));
+    // judged start: g and g' of both candidates; the chosen pair is the
+    // first Newton step's (the same values the loop would compute)
+    bool first = false;
+    double g0 = 0.0, d0 = 1.0;
     if (have_guess && isfinite(guess) && guess > plo) {
-        const double gg = rside_f(L, guess) + rside_f(R, guess) + du;
-        const double ga = rside_f(L, p) + rside_f(R, p) + du;
+        double dgL, dgR, daL, daR;
+        const double gg = rside_f(L, guess, dgL) + rside_f(R, guess, dgR) + du;
+        const double ga = rside_f(L, p, daL) + rside_f(R, p, daR) + du;
+        first = true;
         if (fabs(gg) < fabs(ga)) {
             p = guess;
+            g0 = gg;
+            d0 = dgL + dgR;
             if (used) *used = true;
+        } else {
+            g0 = ga;
+            d0 = daL + daR;
         }
     }
     int it = 0;
     bool conv = false;
     while (it < maxit) {
-        double dLf, dRf;
-        const double gv = rside_f(L, p, dLf) + rside_f(R, p, dRf) + du;
-        double pn = p - gv / (dLf + dRf);
+        double gv, dv;
+        if (first && it == 0) {
+            gv = g0;
+            dv = d0;
+        } else {
+            double dLf, dRf;
+            gv = rside_f(L, p, dLf) + rside_f(R, p, dRf) + du;
+            dv = dLf + dRf;
+        }
+        double pn = p - gv / dv;
         if (pn <= plo) pn = plo + 0.5 * (p - plo);
         ++it;
         conv = fabs(pn - p) <= rtol * (pn - plo);
@@ -291,6 +309,20 @@ __device__ __forceinline__ void report_error(int* err, long long* err_cell, int 
 {
     atomicCAS(err, 0, code);
     atomicMin(err_cell, cell);
+}
+
+// Lower cell c, upper cell cn and axis d of an interface face f = 3c + d
+// (32-bit index arithmetic: grids hold at most 2^29 cells).  The face is an
+// interface face, so a face on the upper domain boundary is periodic.
+__device__ __forceinline__ void face_cells(int gnx, int gny, int gnz, uint32_t f, uint32_t& c, uint32_t& cn, int& d)
+{
+    const uint32_t nx = gnx, ny = gny, nz = gnz, sxy = nx * ny;
+    c = f / 3u;
+    d = (int)(f - 3u * c);
+    const uint32_t k = c / sxy, r = c - k * sxy, j = r / nx, i = r - j * nx;
+    if (d == 0) cn = i + 1 < nx ? c + 1 : c - (nx - 1);
+    else if (d == 1) cn = j + 1 < ny ? c + nx : c - (ny - 1) * nx;
+    else cn = k + 1 < nz ? c + sxy : c - (nz - 1) * sxy;
 }
 
 // Source index along one axis for a (possibly ghost) index i in [-2, n+1]
