@@ -70,6 +70,40 @@ def measured_traffic(precision):
     return rec["bytes_per_launch_mean"]
 
 
+# VALU issue peak: one wave64 VALU instruction per CU per clock (a SIMD
+# takes four clocks per wave64 FP64 or unpacked FP32 instruction), 256 CUs
+# at 2.4 GHz, in lane-instructions per second
+VALU_PEAK = 256 * 2.4e9 * 64
+
+
+def valu_line(instr_per_cell, cells, launch_ms):
+    """The stage kernel against the VALU issue roof (the bound it meets
+    first in FP64): instructions per cell from the counters, rate from the
+    live launch time."""
+    if instr_per_cell is None:
+        return None
+    rate = instr_per_cell * cells / (launch_ms * 1e-3)
+    return {"instr_per_cell": instr_per_cell, "achieved": rate, "peak": VALU_PEAK,
+            "unit": "lane-instructions/s", "frac": rate / VALU_PEAK}
+
+
+def measured_valu(precision):
+    """VALU lane-instructions per cell-update of the stage kernel from the
+    committed SQ counter summary, if it was taken on the current sources."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "k_stage_valu.json")
+    if precision != "fp64" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    m = hashlib.sha256()
+    for src in rec["sources"]:
+        m.update(open(os.path.join(ROOT, src), "rb").read())
+    if m.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["valu_instr_per_cell_mean"]
+
+
 def time_sim(m2c, torch, problem, precision, steps, warmup, tile=None):
     """Cell-updates/s per RK stage of one context over `steps` steps."""
     sim = m2c.Sim(m2c.config_for(problem, precision=precision, tile=tile))
@@ -317,6 +351,7 @@ def main():
                    "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
+                     "valu": valu_line(measured_valu(args.precision), N, stage_ms),
                      "kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
         "fiver": {"solves": st["riemann_solves"], "ms_per_launch": fiver_ms,

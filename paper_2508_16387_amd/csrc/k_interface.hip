@@ -28,10 +28,40 @@ namespace m2c {
 // boundary is never an interface (the boundary image carries the boundary
 // cell's material); a periodic axis wraps.  Cell indices fit in 32 bits
 // (grids are limited to 2^29 cells).
-__device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t* __restrict__ chi, uint32_t c)
+// A lane walks its cells c, c + 64, c + 128, ... with their coordinates
+// (i, j, k) advanced incrementally (no division per cell).
+struct CellWalk {
+    uint32_t c, i, j, k;
+};
+
+__device__ __forceinline__ void walk_start(const Grid& G, uint32_t c, CellWalk& w)
+{
+    const uint32_t nx = G.nx, sxy = nx * (uint32_t)G.ny;
+    w.c = c;
+    w.k = c / sxy;
+    const uint32_t r = c - w.k * sxy;
+    w.j = r / nx;
+    w.i = r - w.j * nx;
+}
+
+__device__ __forceinline__ void walk_advance(const Grid& G, CellWalk& w, uint32_t step = 64u)
+{
+    const uint32_t nx = G.nx, ny = G.ny;
+    w.c += step;
+    w.i += step;
+    while (w.i >= nx) {
+        w.i -= nx;
+        if (++w.j == ny) {
+            w.j = 0;
+            ++w.k;
+        }
+    }
+}
+
+__device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t* __restrict__ chi, const CellWalk& w)
 {
     const uint32_t nx = G.nx, ny = G.ny, nz = G.nz, sxy = nx * ny;
-    const uint32_t k = c / sxy, r = c - k * sxy, j = r / nx, i = r - j * nx;
+    const uint32_t c = w.c, i = w.i, j = w.j, k = w.k;
     const uint8_t x = chi[c];
     unsigned bits = 0;
     if (G.act[0] && (i + 1 < nx || G.bc[1] == BC_PERIODIC)) {
@@ -49,14 +79,13 @@ __device__ __forceinline__ unsigned cell_face_bits(const Grid& G, const uint8_t*
     return bits;
 }
 
-// Cells of a compaction block: wave w owns the COMPACT_CELLS_PER_THREAD * 64
+// Cells of a compaction block: wave w owns the 64 * COMPACT_CELLS_PER_THREAD
 // consecutive cells from blk * COMPACT_CELLS_PER_BLOCK + w * 64 *
-// COMPACT_CELLS_PER_THREAD; in round e lane l takes cell base + 64 e + l, so
-// each round reads one contiguous run of material ids.
-__device__ __forceinline__ uint32_t compact_base(int blk)
+// COMPACT_CELLS_PER_THREAD (how its lanes share them: lane_bits_* below), so
+// the queue order over waves and blocks is ascending cell order.
+__device__ __forceinline__ uint32_t compact_wave_base(int blk)
 {
-    return (uint32_t)blk * COMPACT_CELLS_PER_BLOCK + (threadIdx.x >> 6) * (64 * COMPACT_CELLS_PER_THREAD) +
-           (threadIdx.x & 63);
+    return (uint32_t)blk * COMPACT_CELLS_PER_BLOCK + (threadIdx.x >> 6) * (64 * COMPACT_CELLS_PER_THREAD);
 }
 
 __device__ __forceinline__ int block_sum(int v, int* sRed)
@@ -70,16 +99,85 @@ __device__ __forceinline__ int block_sum(int v, int* sRed)
     return t;
 }
 
+// Face bits of the lane's cells.  Byte path (any grid): in round e the lane
+// takes cell wbase + 64 e + l, packed at bits 3e..3e+2.  Word path (nx a
+// multiple of 4, ids 4-byte aligned): in round e the lane takes the four
+// cells wbase + 256 e + 4 l + b (b = 0..3) with one aligned 32-bit load of
+// their ids and one per neighbouring row, plane and (for b = 3) the next
+// word, packed at bits 3(4e + b)...; a quarter of the memory instructions.
+__device__ __forceinline__ bool compact_words(const Grid& G, const uint8_t* chi)
+{
+    return G.nx % 4 == 0 && ((uintptr_t)chi & 3u) == 0;
+}
+
+__device__ __forceinline__ uint64_t lane_bits_bytes(const Grid& G, const uint8_t* __restrict__ chi, uint32_t wbase,
+                                                    int& cnt)
+{
+    const uint32_t N = (uint32_t)G.N;
+    uint64_t packed = 0;
+    cnt = 0;
+    CellWalk cw;
+    walk_start(G, wbase + (threadIdx.x & 63), cw);
+#pragma unroll
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
+        const unsigned bits = cw.c < N ? cell_face_bits(G, chi, cw) : 0u;
+        walk_advance(G, cw);
+        packed |= (uint64_t)bits << (3 * e);
+        cnt += __popc(bits);
+    }
+    return packed;
+}
+
+__device__ __forceinline__ uint32_t ld_word(const uint8_t* __restrict__ chi, uint32_t c)
+{
+    return *reinterpret_cast<const uint32_t*>(chi + c);
+}
+
+__device__ __forceinline__ uint64_t lane_bits_words(const Grid& G, const uint8_t* __restrict__ chi, uint32_t wbase,
+                                                    int& cnt)
+{
+    const uint32_t N = (uint32_t)G.N, nx = G.nx, ny = G.ny, nz = G.nz, sxy = nx * ny;
+    const bool py = G.bc[3] == BC_PERIODIC, pz = G.bc[5] == BC_PERIODIC, px = G.bc[1] == BC_PERIODIC;
+    uint64_t packed = 0;
+    cnt = 0;
+    CellWalk cw;
+    walk_start(G, wbase + 4u * (threadIdx.x & 63), cw);
+#pragma unroll
+    for (int e = 0; e < COMPACT_CELLS_PER_THREAD / 4; ++e) {
+        if (cw.c < N) {
+            const uint32_t c = cw.c;
+            const uint32_t d0 = ld_word(chi, c);
+            // neighbour words (all 4-byte aligned since nx % 4 == 0)
+            const bool hx = cw.i + 4 < nx || px;
+            const bool hy = G.act[1] && (cw.j + 1 < ny || py);
+            const bool hz = G.act[2] && (cw.k + 1 < nz || pz);
+            const uint32_t dx = hx ? ld_word(chi, cw.i + 4 < nx ? c + 4 : c + 4 - nx) : 0u;
+            const uint32_t dy = hy ? ld_word(chi, cw.j + 1 < ny ? c + nx : c - (ny - 1) * nx) : 0u;
+            const uint32_t dz = hz ? ld_word(chi, cw.k + 1 < nz ? c + sxy : c - (nz - 1) * sxy) : 0u;
+            const uint32_t nxw = (d0 >> 8) | (dx << 24);     // +x neighbour of each byte
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const uint32_t x = (d0 >> (8 * b)) & 0xffu;
+                unsigned bits = 0;
+                if ((b < 3 || hx) && ((nxw >> (8 * b)) & 0xffu) != x) bits |= 1u;
+                if (hy && ((dy >> (8 * b)) & 0xffu) != x) bits |= 2u;
+                if (hz && ((dz >> (8 * b)) & 0xffu) != x) bits |= 4u;
+                packed |= (uint64_t)bits << (3 * (4 * e + b));
+                cnt += __popc(bits);
+            }
+        }
+        walk_advance(G, cw, 256u);
+    }
+    return packed;
+}
+
 __device__ __forceinline__ void count_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sRed[COMPACT_THREADS / 64];
-    const uint32_t N = (uint32_t)a.g.N, base = compact_base(blk);
+    const uint32_t wbase = compact_wave_base(blk);
     int cnt = 0;
-#pragma unroll
-    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
-        const uint32_t c = base + 64u * e;
-        if (c < N) cnt += __popc(cell_face_bits(a.g, a.chi, c));
-    }
+    if (compact_words(a.g, a.chi)) (void)lane_bits_words(a.g, a.chi, wbase, cnt);
+    else (void)lane_bits_bytes(a.g, a.chi, wbase, cnt);
     const int t = block_sum(cnt, sRed);
     if (threadIdx.x == 0) a.blockcnt[blk] = t;
 }
@@ -180,32 +278,50 @@ __device__ __forceinline__ void scatter_body(const IfaceArgs& a, int blk)
 {
     __shared__ int sW[COMPACT_THREADS / 64];
     if (a.sc->err != 0) return;
-    const uint32_t N = (uint32_t)a.g.N, base = compact_base(blk);
+    const uint32_t wbase = compact_wave_base(blk);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    // face bits of the lane's cells, three per round
-    uint64_t packed = 0;
+    const bool words = compact_words(a.g, a.chi);
     int cnt = 0;
-#pragma unroll
-    for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
-        const uint32_t c = base + 64u * e;
-        const unsigned bits = c < N ? cell_face_bits(a.g, a.chi, c) : 0u;
-        packed |= (uint64_t)bits << (3 * e);
-        cnt += __popc(bits);
-    }
+    const uint64_t packed = words ? lane_bits_words(a.g, a.chi, wbase, cnt) : lane_bits_bytes(a.g, a.chi, wbase, cnt);
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o);
     if (lane == 0) sW[w] = cnt;
     __syncthreads();
     if (cnt == 0) return;                     // wave-uniform
     int off = a.blockcnt[blk];
     for (int k = 0; k < w; ++k) off += sW[k];
-    // faces in ascending id order: by cell, then by axis
+    if (words) {
+        // the lane's 16 cells are 4 runs of 4 consecutive cells; faces in
+        // ascending id order within a round: by lane, cell, axis
+        for (int e = 0; e < COMPACT_CELLS_PER_THREAD / 4; ++e) {
+            const unsigned bits12 = (unsigned)(packed >> (12 * e)) & 0xfffu;
+            const int n = __popc(bits12);
+            int incl = n;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(incl, o);
+                if (lane >= o) incl += y;
+            }
+            const int tot = __shfl(incl, 63);
+            if (tot == 0) continue;                               // wave-uniform
+            int o = off + incl - n;
+            const int f0 = (int)(3u * (wbase + 256u * e + 4u * lane));
+            for (int q = 0; q < 12; ++q)
+                if (bits12 & (1u << q)) {
+                    a.queue[o] = f0 + q;                          // 3 (c0 + b) + d = f0 + 3b + d
+                    a.fslot[f0 + q] = o;
+                    ++o;
+                }
+            off += tot;
+        }
+        return;
+    }
+    // byte path: faces in ascending id order: by cell, then by axis
     const uint64_t below = (1ull << lane) - 1ull;
     for (int e = 0; e < COMPACT_CELLS_PER_THREAD; ++e) {
         const unsigned bits = (unsigned)(packed >> (3 * e)) & 7u;
         const uint64_t b0 = __ballot(bits & 1u), b1 = __ballot(bits & 2u), b2 = __ballot(bits & 4u);
         if ((b0 | b1 | b2) == 0ull) continue;
         int o = off + __popcll(b0 & below) + __popcll(b1 & below) + __popcll(b2 & below);
-        const int f0 = (int)(3u * (base + 64u * e));
+        const int f0 = (int)(3u * (wbase + lane + 64u * e));
 #pragma unroll
         for (int d = 0; d < 3; ++d)
             if (bits & (1u << d)) {

@@ -77,8 +77,8 @@ hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDe
                               int nitems, hipStream_t s);
 
 // Interface kernels (k_interface.hip).
-constexpr int COMPACT_THREADS = 1024;
-constexpr int COMPACT_CELLS_PER_THREAD = 4;
+constexpr int COMPACT_THREADS = 256;
+constexpr int COMPACT_CELLS_PER_THREAD = 16;
 constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THREAD;
 // count / scan / scatter of the interface queue; the scan kernel also ends
 // the previous step (end_prev) and starts this one (begin: dt, cleared

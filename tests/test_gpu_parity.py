@@ -106,8 +106,12 @@ def test_queue_shock_bubble(m2c):
     assert np.array_equal(q, ref)
 
 
-def test_queue_checkerboard_periodic(m2c):
-    p = W.periodic_box(3, n=(9, 7, 5))
+# (9,7,5): byte path of the compaction; (8,6,5), (4,3,3), (12,1,7): 32-bit
+# word path (nx a multiple of 4), with the periodic wrap of the last word of
+# a row, a 4-cell row and an inactive axis
+@pytest.mark.parametrize("dims", [(9, 7, 5), (8, 6, 5), (4, 3, 3), (12, 1, 7)])
+def test_queue_checkerboard_periodic(m2c, dims):
+    p = W.periodic_box(3, n=dims)
     nx, ny, nz = p.n
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     p.prim[5] = np.where((i + j + k) % 2 == 0, 1.0, -1.0)
@@ -115,6 +119,22 @@ def test_queue_checkerboard_periodic(m2c):
     p.prim[0] = np.where(p.prim[5] < 0, 1000.0, 1.0)
     g, o = _pair(m2c, p)
     assert np.array_equal(g.interface_faces(), o.interface_faces())
+
+
+@pytest.mark.parametrize("dims", [(20, 12, 10), (21, 12, 10), (64, 3, 2)])
+def test_queue_random_materials(m2c, dims):
+    """Random material ids (transmissive boundaries): every face class."""
+    p = W.shock_bubble(5, nxyz=dims, radius=0.3)
+    rng = np.random.default_rng(sum(dims))
+    phi = np.where(rng.random(p.prim[5].shape) < 0.35, -1.0, 1.0)
+    p.prim[5] = phi
+    p.prim[0] = np.where(phi < 0, 1.0, 1000.0)
+    p.prim[1:4] = 0.0
+    p.prim[4] = 1e5
+    g, o = _pair(m2c, p)
+    q = g.interface_faces()
+    assert q.size > 0
+    assert np.array_equal(q, o.interface_faces())
 
 
 def test_queue_empty(m2c):
