@@ -5,6 +5,8 @@ from __future__ import annotations
 import os
 import re
 
+import ctypes as C
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -56,3 +58,47 @@ def test_create_rejects_bad_config_without_gpu():
     c = m.config_default()
     c.bc[0] = m.M2C_BC_PERIODIC        # unpaired periodic side
     assert m.lib().m2c_create(C.byref(c), C.byref(h)) == m.M2C_ERR_ARG
+
+
+@pytest.mark.parametrize("field,value,ok", [
+    ("nx", 1 << 29, True),                  # 2^29 cells: the largest grid (32-bit byte offsets)
+    ("nx", (1 << 29) + 1, False),
+    ("ny", 0, False),
+    ("gamma", (1.0, 1.4), False),           # gamma must exceed 1
+    ("pc", (-1.0, 0.0), False),
+    ("limiter_alpha", 2.5, False),
+    ("limiter_alpha", 1.0, True),           # MC with alpha = 1 is minmod
+    ("rk_order", 3, False),
+    ("cfl", 0.0, False),
+    ("precision", 7, False),
+    ("riemann_rtol", 0.0, False),
+    ("riemann_maxit", 0, False),
+    ("tile", (16, 16), True),
+    ("tile", (8, 8), False),
+    ("tile", (32, 7), True),
+    ("tile_z", -1, False),
+    ("bc", (2, 2, 0, 1, 1, 1), True),       # periodic x, mixed others
+    ("bc", (3, 0, 0, 0, 0, 0), False),
+    ("box", 0, False),                      # hi == lo
+])
+def test_validate_config_without_gpu(field, value, ok):
+    """m2c_validate_config: the limits and the argument checks of m2c_create,
+    usable without a GPU."""
+    import paper_2508_16387_amd as m
+    c = m.config_default()
+    if field == "nx" and value > 1000:
+        c.nx = value
+    elif field in ("gamma", "pc"):
+        for k in range(2):
+            getattr(c, field)[k] = value[k]
+    elif field == "tile":
+        c.tile_x, c.tile_y = value
+    elif field == "bc":
+        for k in range(6):
+            c.bc[k] = value[k]
+    elif field == "box":
+        c.hi[0] = c.lo[0]
+    else:
+        setattr(c, field, value)
+    rc = m.lib().m2c_validate_config(C.byref(c))
+    assert (rc == m.M2C_OK) == ok, (field, value, rc)
