@@ -191,6 +191,24 @@ def test_shock_bubble_small(m2c, tile):
     assert g.stats()["riemann_solves"] == o.stats()["riemann_solves"]
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_bubble_next_to_rigid_wall(m2c, prec):
+    """The paper's shock-induced collapse of a bubble near a rigid wall:
+    walls on every side, bubble 0.04 from the +x wall, a 1 GPa shock; FIVER
+    faces meet wall images.  FP64 at the oracle bar, mixed at its bound."""
+    p = W.shock_bubble(6, nxyz=(40, 24, 22), radius=0.2, p_shock=1e9, shock_x=0.52, centre_x=0.76,
+                       bc=(W.BC_WALL,) * 6)
+    g, o = _pair(m2c, p, precision=prec)
+    assert g.step(80) == 0 and o.step(80) == 0
+    assert o.stats()["flips"] > 0                    # the shock has reached the bubble
+    e = compare_runs(g, o, p)
+    print("wall", prec, e)
+    assert e["id_mismatch"] == 0
+    tol = TOL_FP64 if prec == 0 else 1e-3
+    for k in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[k] <= tol, (k, e[k])
+
+
 def test_shock_bubble_interaction_flips(m2c):
     """Shock reaches the bubble: cells change material (phase update)."""
     p = W.shock_bubble(0, n=32, radius=0.3, p_shock=1e9, shock_x=0.2)
@@ -210,6 +228,21 @@ def test_shock_bubble_128_one_step(m2c):
     g, o = _pair(m2c, p)
     assert g.step(2) == 0 and o.step(2) == 0
     _assert_close(compare_runs(g, o, p))
+
+
+def test_profiling_samples_steps(m2c):
+    """m2c_set_profiling(every): kernel classes timed on one step in `every`."""
+    p = W.shock_bubble(2, nxyz=(24, 20, 18))
+    s = m2c.Sim(m2c.config_for(p), p.prim)
+    s.set_profiling(3)
+    s.step(10)                                   # steps 0, 3, 6, 9 are timed
+    st = s.stats()
+    assert st["stage_launches"] == 8 and st["fiver_launches"] == 8
+    assert st["ms_stage"] > 0.0 and st["ms_fiver"] > 0.0
+    s.set_profiling(0)
+    s.reset_stats()
+    s.step(2)
+    assert s.stats()["stage_launches"] == 0
 
 
 def test_determinism(m2c):

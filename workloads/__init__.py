@@ -206,22 +206,27 @@ _AMBIENT = {"rho_air": 1.0, "rho_water": 1000.0, "p": 1e5}
 
 def shock_bubble(seed: int, n: int = 128, steps: int = 100, cfl: float = 0.4,
                  radius: float = 0.15, p_shock: float = 1e8, shock_x: float = 0.1,
-                 nxyz=None) -> Problem:
-    """Air bubble in water hit by a planar shock, unit box, transmissive.
+                 nxyz=None, centre_x=None, bc=(0, 0, 0, 0, 0, 0)) -> Problem:
+    """Air bubble in water hit by a planar shock, unit box, transmissive
+    unless ``bc`` says otherwise.
 
-    Bubble (material 1) of the given radius at (0.5,0.5,0.5) + U(-0.05,0.05)^3;
-    water (material 0) at 1e5 Pa elsewhere; for x < shock_x the water takes
-    the post-shock state of pressure p_shock moving in +x.
-    Draw order: three draws, jitter of the centre along x, y, z.
+    Bubble (material 1) of the given radius at (0.5,0.5,0.5) + U(-0.05,0.05)^3
+    (x of the centre = ``centre_x`` when given, e.g. a bubble next to a rigid
+    wall); water (material 0) at 1e5 Pa elsewhere; for x < shock_x the water
+    takes the post-shock state of pressure p_shock moving in +x.
+    Draw order: three draws, jitter of the centre along x, y, z (drawn also
+    when centre_x replaces the first).
     """
     rng = SplitMix64(seed)
     c = tuple(0.5 + rng.uniform(-0.05, 0.05) for _ in range(3))
+    if centre_x is not None:
+        c = (float(centre_x), c[1], c[2])
     dims = tuple(nxyz) if nxyz is not None else (n, n, n)
     lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
     rho1, u1 = post_shock_state(1000.0, 1e5, p_shock, *WATER)
     prim = _fill_bubble_field(dims, lo, hi, [c], [radius], _AMBIENT, shock_x, (rho1, u1, p_shock))
     return Problem("shock_bubble", dims, lo, hi, gamma=(WATER[0], AIR[0]), pc=(WATER[1], AIR[1]),
-                   cfl=cfl, steps=steps, prim=prim,
+                   bc=tuple(bc), cfl=cfl, steps=steps, prim=prim,
                    meta={"seed": seed, "centre": c, "radius": radius, "p_shock": p_shock,
                          "post_shock": (rho1, u1)})
 
