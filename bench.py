@@ -333,6 +333,7 @@ def main():
     stage_ms = st["ms_stage"] / max(st["stage_launches"], 1)
     fiver_ms = st["ms_fiver"] / max(st["fiver_launches"], 1)
     bytes_per_launch = N * (BYTES_STAGE1 + BYTES_STAGE2) / 2
+    traffic = measured_traffic(args.precision)
     achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
     out = {
         "metric": "cell-updates/s per RK stage",
@@ -350,7 +351,9 @@ def main():
         "config": {"workload": f"shock_bubble_{args.n}^3", "grid": [args.n] * 3, "steps": args.steps,
                    "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl, "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.precision),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_frac": (None if traffic is None
+                                      else traffic / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
                      "valu": valu_line(measured_valu(args.precision), N, stage_ms),
                      "kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
                      "algorithmic_bytes_per_launch": bytes_per_launch},
