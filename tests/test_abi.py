@@ -102,3 +102,16 @@ def test_validate_config_without_gpu(field, value, ok):
         setattr(c, field, value)
     rc = m.lib().m2c_validate_config(C.byref(c))
     assert (rc == m.M2C_OK) == ok, (field, value, rc)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the package raises instead of falling
+    back to anything else (checked in a fresh interpreter)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import paper_2508_16387_amd as m\n"
+            "try:\n    m.config_default()\nexcept RuntimeError as e:\n    print('raised', 'no CPU fallback' in str(e))\n")
+    env = dict(os.environ, M2C_LIBRARY=str(tmp_path / "libm2c_absent.so"), PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root, timeout=120)
+    assert r.stdout.strip() == "raised True", (r.stdout, r.stderr[-2000:])
