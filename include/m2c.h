@@ -79,11 +79,14 @@ typedef struct m2c_config {
     double gamma[2], pc[2];     /* stiffened gas of material 0 and 1           */
     int32_t bc[6];              /* -x,+x,-y,+y,-z,+z; periodic must pair up    */
     double limiter_alpha;       /* MC parameter alpha (paper default 1.2)      */
-    int32_t rk_order;           /* 2 (TVD-RK2); other orders: M2C_ERR_UNIMPLEMENTED */
+    int32_t rk_order;           /* 2 (TVD-RK2, the only order built); others:
+                                   M2C_ERR_ARG                                   */
     double cfl;                 /* dt = cfl / max_i sum_d (|V_d|+c)/h_d        */
     double dt_fixed;            /* > 0: constant dt instead of the CFL rule    */
     int32_t precision;          /* M2C_PREC_*                                  */
-    int32_t guess;              /* M2C_GUESS_*                                 */
+    int32_t guess;              /* M2C_GUESS_ACOUSTIC; a learned guess is
+                                   attached with m2c_set_guess (M2C_GUESS_MLP
+                                   here: M2C_ERR_ARG)                            */
     double riemann_rtol;        /* Newton stop: |dp| <= rtol (p - p_lo)        */
     int32_t riemann_maxit;      /* Newton steps before the bisection fallback  */
     int32_t tile_x, tile_y, tile_z;  /* stage-kernel tile; 0 = library choice  */
@@ -102,7 +105,9 @@ typedef struct m2c_stats {
     int64_t flips;              /* cells whose material changed                 */
     int64_t orphans;            /* flipped cells without a neighbour of their
                                    new material (state kept, re-encoded)        */
-    int64_t mlp_fallbacks;      /* learned guesses rejected by the judge        */
+    int64_t mlp_fallbacks;      /* with a learned guess: solves that started from
+                                   the acoustic guess (judged better, unusable
+                                   network output, or near-equilibrium face)    */
     int32_t err_code;           /* m2c_status of the failing step, 0 if none    */
     int32_t pad0;
     int64_t err_cell;           /* first cell (or face/3) found failing, -1     */
@@ -229,7 +234,8 @@ int m2c_eval_hllc(int64_t n, const double* qL, const double* qR, double gamma, d
  * eos = [gamma_L,pc_L,gamma_R,pc_R][n], out = [p*,u*,rho*_L,rho*_R][n],
  * iters (nullable) = Newton steps per problem (negative: bisection fallback;
  * 0: no admissible star pressure, out = NaN).  Always-FP64 safeguarded Newton
- * from the acoustic guess (or the loaded MLP guess, judged by |g|).
+ * from the acoustic guess; guess must be M2C_GUESS_ACOUSTIC (other values:
+ * M2C_ERR_UNIMPLEMENTED; the learned guess: m2c_riemann_solve_learned).
  * Returns M2C_ERR_RIEMANN if any problem had no admissible star pressure. */
 int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t guess,
                       double rtol, int32_t maxit, double* out, int32_t* iters,
@@ -279,7 +285,10 @@ int m2c_mlp_train(m2c_mlp* m, int64_t n, const float* X8, const float* t, const 
                   float* loss_per_epoch, void* hip_stream);
 /* As m2c_riemann_solve with the learned guess (m NULL: acoustic guess);
  * *n_fallback (nullable) counts problems that started from the acoustic
- * guess because it was better or the network output was unusable. */
+ * guess: it was better, the network output was unusable, or the two states
+ * differ by less than 1e-3 in pressure (relative to the smaller p + p_c) and
+ * in velocity (relative to the smaller sound speed), where the acoustic
+ * guess is taken without consulting the network. */
 int m2c_riemann_solve_learned(const m2c_mlp* m, int64_t n, const double* in, const double* eos, double rtol,
                               int32_t maxit, double* out, int32_t* iters, int64_t* n_fallback, void* hip_stream);
 /* Use a copy of the network for every interface Riemann problem of later
