@@ -335,14 +335,6 @@ __device__ __forceinline__ void scatter_body(const IfaceArgs& a, int blk)
 
 __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a) { scatter_body(a, blockIdx.x); }
 
-hipError_t launch_compact(const IfaceArgs& a, bool end_prev, bool begin, double dt_imposed, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_count, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a, end_prev ? 1 : 0, begin ? 1 : 0, a.g.cfl,
-                       a.g.dt_fixed, dt_imposed);
-    hipLaunchKernelGGL(k_scatter, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
-    return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // FIVER: one thread per queued face.  The Riemann data are the two cells'
@@ -571,6 +563,29 @@ hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
     long long nb = (a.g.N + 255) / 256;
     if (nb > 256) nb = 256;
     hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// The phase update of the previous step run by the count kernel of the next
+// one: the phase update writes the state at flipped cells, the CFL maximum
+// and error reports; the count reads only material ids, and the scan that
+// forms dt from that maximum and closes the previous step comes after.
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count_phase(const IfaceArgs a, const PhaseArgs pa)
+{
+    phase_body(pa, blockIdx.x, gridDim.x);
+    count_body(a, blockIdx.x);
+}
+
+hipError_t launch_compact(const IfaceArgs& a, const PhaseArgs* prev_phase, bool end_prev, bool begin,
+                          double dt_imposed, hipStream_t s)
+{
+    if (prev_phase)
+        hipLaunchKernelGGL(k_count_phase, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a, *prev_phase);
+    else
+        hipLaunchKernelGGL(k_count, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a, end_prev ? 1 : 0, begin ? 1 : 0, a.g.cfl,
+                       a.g.dt_fixed, dt_imposed);
+    hipLaunchKernelGGL(k_scatter, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
     return hipGetLastError();
 }
 

@@ -218,9 +218,11 @@ int harvest_events(m2c_ctx* c)
 }
 
 // Enqueue one full time step with state parity p (reads W[p], writes
-// W[1-p]).  end_prev: the previous step of this call is still open (its
-// counters are advanced by this step's scan kernel).
-int enqueue_step(m2c_ctx* c, int p, double dt_imposed, bool end_prev)
+// W[1-p]).  prev (nullable): the phase update of the previous step of this
+// call, still pending; it runs in this step's count kernel, and this step's
+// scan kernel closes that step.  The step's own phase update is returned in
+// *phase, pending.
+int enqueue_step(m2c_ctx* c, int p, double dt_imposed, const PhaseArgs* prev, PhaseArgs* phase)
 {
     hipStream_t s = c->stream;
     const int q = 1 - p;
@@ -236,7 +238,7 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, bool end_prev)
     if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
     IfaceArgs ia = iface_args(c, c->W[p]);
     ia.chi = c->chi[p];
-    HIPCHK(c, launch_compact(ia, end_prev, true, dt_imposed, s));
+    HIPCHK(c, launch_compact(ia, prev, prev != nullptr, true, dt_imposed, s));
 
     StageArgs sa;
     sa.g = c->g;
@@ -277,7 +279,7 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, bool end_prev)
     HIPCHK(c, launch_stage(2, mixed, c->tx, c->ty, sa, s));
     if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
 
-    PhaseArgs pa;
+    PhaseArgs& pa = *phase;
     pa.g = c->g;
     pa.W = c->W[q];
     pa.chi_old = c->chi[p];
@@ -287,7 +289,6 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, bool end_prev)
     pa.star = c->star;
     pa.qcap = c->qcap;
     pa.sc = c->sc;
-    HIPCHK(c, launch_phase(pa, s));
     if (ev) {
         HIPCHK(c, hipEventRecord(ev[6], s));
         ++c->ev_steps;
@@ -310,12 +311,16 @@ int run_steps(m2c_ctx* c, int32_t nsteps, double dt_imposed, double* t_out)
     if (rc) return rc;
     const long long done0 = c->hsc->steps_done;
     int p = c->cur;
+    PhaseArgs pend[2];
     for (int32_t k = 0; k < nsteps; ++k) {
-        rc = enqueue_step(c, p, dt_imposed, k > 0);
+        rc = enqueue_step(c, p, dt_imposed, k > 0 ? &pend[(k - 1) & 1] : nullptr, &pend[k & 1]);
         if (rc) return rc;
         p = 1 - p;
     }
-    if (nsteps > 0) HIPCHK(c, launch_end_step(c->sc, 2, c->stream));
+    if (nsteps > 0) {
+        HIPCHK(c, launch_phase(pend[(nsteps - 1) & 1], c->stream));
+        HIPCHK(c, launch_end_step(c->sc, 2, c->stream));
+    }
     rc = pull_scalars(c);
     if (rc) return rc;
     rc = harvest_events(c);
@@ -636,7 +641,7 @@ int m2c_interface_faces(m2c_ctx* c, int32_t* out, int64_t cap, int64_t* count)
     int rc = clear_error(c);
     if (rc) return rc;
     IfaceArgs ia = iface_args(c, c->W[c->cur]);
-    HIPCHK(c, launch_compact(ia, false, false, 0.0, c->stream));
+    HIPCHK(c, launch_compact(ia, nullptr, false, false, 0.0, c->stream));
     rc = pull_scalars(c);
     if (rc) return rc;
     if (c->hsc->err != 0) {

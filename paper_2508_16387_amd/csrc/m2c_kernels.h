@@ -80,10 +80,12 @@ hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDe
 constexpr int COMPACT_THREADS = 256;
 constexpr int COMPACT_CELLS_PER_THREAD = 16;
 constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THREAD;
-// count / scan / scatter of the interface queue; the scan kernel also ends
-// the previous step (end_prev) and starts this one (begin: dt, cleared
+// count / scan / scatter of the interface queue; the count kernel also runs
+// the previous step's phase update (prev_phase, nullable), the scan kernel
+// ends the previous step (end_prev) and starts this one (begin: dt, cleared
 // accumulators)
-hipError_t launch_compact(const IfaceArgs& a, bool end_prev, bool begin, double dt_imposed, hipStream_t s);
+hipError_t launch_compact(const IfaceArgs& a, const PhaseArgs* prev_phase, bool end_prev, bool begin,
+                          double dt_imposed, hipStream_t s);
 hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s);
