@@ -342,6 +342,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         uint8_t Xn = 0;
         bool mzn = false;
         if (zact) load_raw(k + 3, Wn, Xn, mzn);
+        // stage 2: the step-start state of the cell, fetched early
+        constexpr bool W0E = STAGE == 2 && sizeof(TF) == sizeof(double);
+        double w0[6];
+        if (W0E && inside) {
+            const uint32_t c0 = col + sxy * k;
+#pragma unroll
+            for (int v = 0; v < 6; ++v) w0[v] = ldf(a.W0 + v * N, c0);
+        }
 
         // (1) own plane-k values into the LDS tile
         if (cellt) {
@@ -502,8 +510,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 wn[5] = PH[2] + dt * (-Ls);
             } else {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) wn[v] = 0.5 * ldf(a.W0 + v * N, c) + 0.5 * (wi[v] + dt * (-acc[v]));
-                wn[5] = 0.5 * ldf(a.W0 + 5 * N, c) + 0.5 * (PH[2] + dt * (-Ls));
+                for (int v = 0; v < 5; ++v)
+                    wn[v] = 0.5 * (W0E ? w0[v] : ldf(a.W0 + v * N, c)) + 0.5 * (wi[v] + dt * (-acc[v]));
+                wn[5] = 0.5 * (W0E ? w0[5] : ldf(a.W0 + 5 * N, c)) + 0.5 * (PH[2] + dt * (-Ls));
             }
             double u, vv, ww;
             const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
