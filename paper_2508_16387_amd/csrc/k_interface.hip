@@ -185,36 +185,35 @@ __device__ __forceinline__ void count_body(const IfaceArgs& a, int blk)
 __global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a) { count_body(a, blockIdx.x); }
 
 // One block: exclusive scan of the block counts (in place), total -> qlen.
+// Each thread sums a contiguous segment of the counts, the block scans the
+// segment sums, and each thread rewrites its segment from its offset.
 __device__ __forceinline__ void scan_body(const IfaceArgs& a)
 {
-    __shared__ int sW[16];
-    __shared__ long long sCarry;
-    if (threadIdx.x == 0) sCarry = 0;
-    __syncthreads();
+    __shared__ long long sW[16];
     const int nb = a.nblk;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int base = 0; base < nb; base += 1024) {
-        const int b = base + threadIdx.x;
-        const int v = b < nb ? a.blockcnt[b] : 0;
-        int incl = v;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        if (lane == 63) sW[w] = incl;
-        __syncthreads();
-        int woff = 0;
-        for (int k = 0; k < w; ++k) woff += sW[k];
-        int tot = 0;
-        for (int k = 0; k < 16; ++k) tot += sW[k];
-        const long long carry = sCarry;
-        if (b < nb) a.blockcnt[b] = (int)(carry + woff + incl - v);
-        __syncthreads();
-        if (threadIdx.x == 0) sCarry = carry + tot;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int b0 = min(nb, (int)threadIdx.x * per), b1 = min(nb, b0 + per);
+    long long sum = 0;
+    for (int b = b0; b < b1; ++b) sum += a.blockcnt[b];
+    long long incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) sW[w] = incl;
+    __syncthreads();
+    long long run = incl - sum, total = 0;
+    for (int k = 0; k < nw; ++k) {
+        if (k < w) run += sW[k];
+        total += sW[k];
+    }
+    for (int b = b0; b < b1; ++b) {
+        const int v = a.blockcnt[b];
+        a.blockcnt[b] = (int)run;
+        run += v;
     }
     if (threadIdx.x == 0) {
-        const long long total = sCarry;
         if (total > a.qcap) {
             atomicCAS(&a.sc->err, 0, ST_OVERFLOW);
             a.sc->qlen = 0;
