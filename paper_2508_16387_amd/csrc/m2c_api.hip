@@ -2,12 +2,13 @@
 //
 // One context owns one grid's device buffers and stream.  A time step is
 // enqueued as a fixed kernel sequence with no host round trip:
-//   begin_step (dt) -> interface compaction -> [FIVER, stage] x 2 -> phase
-//   update -> end_step
-// and every kernel returns at once when an earlier one has reported an
-// error, so the last good state is the start-of-step buffer of the failing
-// step (the two full states alternate between W[0] and W[1]).  The host
-// reads the device scalars once per m2c_step call.
+//   count (+ previous step's phase update) -> scan (+ close the previous
+//   step, open this one: dt) -> scatter -> [FIVER, stage] x 2
+// with the last step's phase update and closing after the loop.  Every
+// kernel returns at once when an earlier one has reported an error, so the
+// last good state is the start-of-step buffer of the failing step (the two
+// full states alternate between W[0] and W[1]).  The host reads the device
+// scalars once per m2c_step call.
 #include <hip/hip_runtime.h>
 
 #include <climits>
