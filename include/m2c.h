@@ -79,8 +79,9 @@ typedef struct m2c_config {
     double gamma[2], pc[2];     /* stiffened gas of material 0 and 1           */
     int32_t bc[6];              /* -x,+x,-y,+y,-z,+z; periodic must pair up    */
     double limiter_alpha;       /* MC parameter alpha (paper default 1.2)      */
-    int32_t rk_order;           /* 2 (TVD-RK2, the only order built); others:
-                                   M2C_ERR_ARG                                   */
+    int32_t rk_order;           /* 1 forward Euler, 2 TVD-RK2 (default), 3
+                                   TVD-RK3 (Shu-Osher); batches: 2 only; other
+                                   values: M2C_ERR_ARG                           */
     double cfl;                 /* dt = cfl / max_i sum_d (|V_d|+c)/h_d        */
     double dt_fixed;            /* > 0: constant dt instead of the CFL rule    */
     int32_t precision;          /* M2C_PREC_*                                  */
@@ -208,6 +209,8 @@ int m2c_get_tile(const m2c_ctx* ctx, int32_t tile[3]);
  * a step stops advancing (its last good state is kept) while the others go
  * on; m2c_batch_step then returns the first failing run's status. */
 typedef struct m2c_batch m2c_batch;
+/* cfgs: n valid configurations with one precision and rk_order 2; otherwise
+ * M2C_ERR_ARG. */
 int m2c_batch_create(int32_t n, const m2c_config* cfgs, m2c_batch** out);
 void m2c_batch_destroy(m2c_batch* b);
 const char* m2c_batch_last_error(const m2c_batch* b);

@@ -163,7 +163,8 @@ def config_default() -> Config:
     return c
 
 
-def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None) -> Config:
+def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None,
+               rk_order=2) -> Config:
     """Configuration for a problem description with attributes n, lo, hi,
     gamma, pc, bc, cfl, dt_fixed (as built by the ``workloads`` module)."""
     c = config_default()
@@ -180,6 +181,7 @@ def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2
     c.precision = precision
     c.riemann_rtol = rtol
     c.riemann_maxit = maxit
+    c.rk_order = rk_order
     if tile is not None:
         c.tile_x, c.tile_y, c.tile_z = tile
     return c

@@ -259,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a, int end_prev, 
                                                double dt_fixed, double dt_imposed)
 {
     if (threadIdx.x == 0) {
-        if (end_prev) end_step_body(a.sc, 2);
+        if (end_prev) end_step_body(a.sc, a.g.rk_stages);
         if (begin) begin_step_body(a.sc, cfl, dt_fixed, dt_imposed);
     }
     scan_body(a);

@@ -2,9 +2,12 @@
 //
 // One launch evaluates, for every cell, the finite-volume residual of eq.
 // NS_discretized (inviscid, no source) and of the level-set equation, and
-// applies the TVD-RK2 stage update (section "Time integration"):
-//   stage 1: W(1) = W^n + dt R(W^n)
-//   stage 2: W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1)))
+// applies one stage of a TVD Runge-Kutta scheme (section "Time
+// integration"), W_out = c0 W^n + c1 (W_in + dt R(W_in)):
+//   TVD-RK2: W(1) = W^n + dt R(W^n); W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1)))
+//   TVD-RK3: the same first stage; W(2) = 3/4 W^n + 1/4 (W(1) + dt R(W(1)));
+//            W^{n+1} = 1/3 W^n + 2/3 (W(2) + dt R(W(2)))
+//   forward Euler: W^{n+1} = W^n + dt R(W^n)
 // with R_i = -sum_d (F_{i,d+} - F_{i,d-}) / h_d and L_i = -sum_d V_d D_d phi.
 //
 // Layout on the device: SoA FP64 fields [rho, rho u, rho v, rho w, rho E, phi],
@@ -64,6 +67,13 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 template <int STAGE, int TX, int TY, typename TF, bool LM>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
+    // Stage kinds: 1 first stage of RK2 / RK3 (W_out = W_in + dt R); 2 last
+    // stage of RK2 / RK3 (blend with W^n, then the next step's CFL maximum,
+    // new material ids and flipped cells); 3 middle stage of RK3 (blend
+    // only); 4 forward Euler (first and last).
+    static_assert(STAGE >= 1 && STAGE <= 4, "stage kind");
+    constexpr bool BLEND = STAGE == 2 || STAGE == 3;
+    constexpr bool LAST = STAGE == 2 || STAGE == 4;
     // CT cells per tile; the block is CT rounded up to whole wavefronts (a
     // 16x15 tile has 511 in-plane faces: exactly two rounds of the 256
     // threads, where a 16x16 tile needs a third, one-wave round)
@@ -248,7 +258,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     }
 
     const double dt = sc->dt;
-    double lam = 0.0;                 // stage 2: max wave-speed sum of own cells
+    double lam = 0.0;                 // last stage: max wave-speed sum of own cells
 
     // Halo ring of a plane (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX
     // columns), HPT cells per thread at most; its raw state is loaded one
@@ -343,7 +353,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         bool mzn = false;
         if (zact) load_raw(k + 3, Wn, Xn, mzn);
         // stage 2: the step-start state of the cell, fetched early
-        constexpr bool W0E = STAGE == 2 && sizeof(TF) == sizeof(double);
+        constexpr bool W0E = BLEND && sizeof(TF) == sizeof(double);
         double w0[6];
         if (W0E && inside) {
             const uint32_t c0 = col + sxy * k;
@@ -504,15 +514,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (zact) Ls += ls_term(Vc[2], PH[0], PH[1], PH[2], PH[3], PH[4], G.rh6[2]);
 
             double wn[6];
-            if (STAGE == 1) {
+            if (!BLEND) {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) wn[v] = wi[v] + dt * (-acc[v]);
                 wn[5] = PH[2] + dt * (-Ls);
             } else {
+                const double c0 = a.c0, c1 = a.c1;
 #pragma unroll
                 for (int v = 0; v < 5; ++v)
-                    wn[v] = 0.5 * (W0E ? w0[v] : ldf(a.W0 + v * N, c)) + 0.5 * (wi[v] + dt * (-acc[v]));
-                wn[5] = 0.5 * (W0E ? w0[5] : ldf(a.W0 + 5 * N, c)) + 0.5 * (PH[2] + dt * (-Ls));
+                    wn[v] = c0 * (W0E ? w0[v] : ldf(a.W0 + v * N, c)) + c1 * (wi[v] + dt * (-acc[v]));
+                wn[5] = c0 * (W0E ? w0[5] : ldf(a.W0 + 5 * N, c)) + c1 * (PH[2] + dt * (-Ls));
             }
             double u, vv, ww;
             const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
@@ -521,7 +532,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
 #pragma unroll
             for (int v = 0; v < 6; ++v) stf(a.Wout + v * N, c, wn[v]);
-            if (STAGE == 2) {
+            if (LAST) {
                 const uint8_t xn = wn[5] < 0.0 ? 1 : 0;
                 a.chi_next[c] = xn;
                 if (xn != X0) {
@@ -564,7 +575,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         // its first barrier orders this plane's reads before any reuse
     }
 
-    if (STAGE == 2) {
+    if (LAST) {
         // block max of the wave-speed sums -> one atomic per block
         for (int o = 32; o > 0; o >>= 1) lam = fmax(lam, __shfl_xor(lam, o));
         if ((tid & 63) == 0) sRed[tid >> 6] = lam;
@@ -638,6 +649,8 @@ __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage_batch(const RunDesc* __rest
         a.tiles_y = R.tiles_y;
         a.tiles_z = R.tiles_z;
         a.kz = R.kz;
+        a.c0 = 0.5;
+        a.c1 = 0.5;
         stage_tile<STAGE, TX, TY, TF, false>(a, it.y);
     }
 }
@@ -647,10 +660,14 @@ template <int TX, int TY, typename TF>
 static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
 {
     const int nblk = a.tiles_x * a.tiles_y * a.tiles_z;
-    if (stage == 1)
-        hipLaunchKernelGGL((k_stage<1, TX, TY, TF>), dim3(nblk), dim3(stage_threads(TX, TY)), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_stage<2, TX, TY, TF>), dim3(nblk), dim3(stage_threads(TX, TY)), 0, s, a);
+    const dim3 g(nblk), b(stage_threads(TX, TY));
+    switch (stage) {
+        case 1: hipLaunchKernelGGL((k_stage<1, TX, TY, TF>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_stage<2, TX, TY, TF>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_stage<3, TX, TY, TF>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_stage<4, TX, TY, TF>), g, b, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

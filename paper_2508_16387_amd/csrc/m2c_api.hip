@@ -28,6 +28,8 @@ using namespace m2c;
 
 const MlpDev* m2c_mlp_dev(const m2c_mlp* m);   // m2c_learned.hip
 
+constexpr int EV_STRIDE = 8;        // events per timed step (up to three RK stages)
+
 struct m2c_ctx {
     m2c_config cfg;
     Grid g;
@@ -57,7 +59,7 @@ struct m2c_ctx {
     MlpDev mlp{};                   // context copy of the learned guess (null: acoustic)
     bool use_mlp = false;
     double* guessbuf = nullptr;     // [qcap] learned guesses of the stage in flight
-    std::vector<hipEvent_t> evpool;  // profiling: 7 events per enqueued step
+    std::vector<hipEvent_t> evpool;  // profiling: EV_STRIDE events per timed step
     int ev_steps = 0;               // steps recorded in the pool, not yet harvested
     double ms_stage = 0, ms_fiver = 0, ms_other = 0;
     long long stage_launches = 0, fiver_launches = 0;
@@ -106,7 +108,8 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
             return snprintf(why, n, "material %d needs gamma > 1 and p_c >= 0", m), false;
     if (!(c->limiter_alpha >= 1.0 && c->limiter_alpha <= 2.0))
         return snprintf(why, n, "limiter alpha must lie in [1, 2]"), false;
-    if (c->rk_order != 2) return snprintf(why, n, "only TVD-RK2 is built"), false;
+    if (c->rk_order < 1 || c->rk_order > 3)
+        return snprintf(why, n, "rk_order must be 1 (forward Euler), 2 or 3 (TVD-RK)"), false;
     if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0)) return snprintf(why, n, "cfl must be > 0"), false;
     if (c->precision != M2C_PREC_FP64 && c->precision != M2C_PREC_MIXED)
         return snprintf(why, n, "bad precision"), false;
@@ -145,6 +148,7 @@ void fill_grid(Grid& g, const m2c_config& c)
     g.rtol = c.riemann_rtol;
     g.maxit = c.riemann_maxit;
     g.guess = c.guess;
+    g.rk_stages = c.rk_order;
 }
 
 // Reset the error state of the device scalars (host mirror -> device).
@@ -203,16 +207,24 @@ const char* status_name(int s)
 int harvest_events(m2c_ctx* c)
 {
     if (c->ev_steps == 0) return M2C_OK;
-    HIPCHK(c, hipEventSynchronize(c->evpool[(size_t)c->ev_steps * 7 - 1]));
+    // per timed step: e[0] before the compaction, e[1 + 2k] before the
+    // FIVER launch of stage k, e[2 + 2k] before its stage kernel, e[1 + 2S]
+    // after the last stage kernel
+    const int S = c->cfg.rk_order;
+    HIPCHK(c, hipEventSynchronize(c->evpool[(size_t)(c->ev_steps - 1) * EV_STRIDE + 1 + 2 * S]));
     for (int k = 0; k < c->ev_steps; ++k) {
-        hipEvent_t* e = c->evpool.data() + (size_t)k * 7;
-        float t[6];
-        for (int j = 0; j < 6; ++j) HIPCHK(c, hipEventElapsedTime(&t[j], e[j], e[j + 1]));
-        c->ms_other += t[0] + t[5];
-        c->ms_fiver += t[1] + t[3];
-        c->ms_stage += t[2] + t[4];
-        c->stage_launches += 2;
-        c->fiver_launches += 2;
+        hipEvent_t* e = c->evpool.data() + (size_t)k * EV_STRIDE;
+        float t;
+        HIPCHK(c, hipEventElapsedTime(&t, e[0], e[1]));
+        c->ms_other += t;
+        for (int j = 0; j < S; ++j) {
+            HIPCHK(c, hipEventElapsedTime(&t, e[1 + 2 * j], e[2 + 2 * j]));
+            c->ms_fiver += t;
+            HIPCHK(c, hipEventElapsedTime(&t, e[2 + 2 * j], e[3 + 2 * j]));
+            c->ms_stage += t;
+        }
+        c->stage_launches += S;
+        c->fiver_launches += S;
     }
     c->ev_steps = 0;
     return M2C_OK;
@@ -230,11 +242,11 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, const PhaseArgs* prev, Ph
     const bool mixed = c->cfg.precision == M2C_PREC_MIXED;
     hipEvent_t* ev = nullptr;
     if (c->profiling && c->prof_seq++ % c->prof_every == 0) {
-        if ((size_t)(c->ev_steps + 1) * 7 > c->evpool.size()) {
+        if ((size_t)(c->ev_steps + 1) * EV_STRIDE > c->evpool.size()) {
             int rc = harvest_events(c);
             if (rc) return rc;
         }
-        ev = c->evpool.data() + (size_t)c->ev_steps * 7;
+        ev = c->evpool.data() + (size_t)c->ev_steps * EV_STRIDE;
     }
     if (ev) HIPCHK(c, hipEventRecord(ev[0], s));
     IfaceArgs ia = iface_args(c, c->W[p]);
@@ -255,30 +267,46 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, const PhaseArgs* prev, Ph
     sa.tiles_z = c->tiles[2];
     sa.kz = c->kz;
 
-    // stage 1: W(1) = W^n + dt R(W^n)
-    if (ev) HIPCHK(c, hipEventRecord(ev[1], s));
-    ia.Win = c->W[p];
-    if (c->use_mlp) {
-        ia.guess = c->guessbuf;
-        HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
+    // Runge-Kutta stages (section "Time integration"): stage s reads Win,
+    // writes Wout = c0 W^n + c1 (Win + dt R(Win)); the FIVER fluxes of each
+    // stage come from its own input state, and the last stage keeps the
+    // star states for the phase update.  Buffers: W[p] = W^n, W[q] = W^{n+1},
+    // W1 = the intermediate state (RK3 passes its first stage through W[q]).
+    struct Stage {
+        int kind;
+        const double* win;
+        double* wout;
+        double c0, c1;
+    };
+    Stage st[3];
+    const int S = c->cfg.rk_order;
+    if (S == 1) {
+        st[0] = {4, c->W[p], c->W[q], 0.0, 1.0};                 // forward Euler
+    } else if (S == 2) {
+        st[0] = {1, c->W[p], c->W1, 0.0, 1.0};                   // W(1) = W^n + dt R(W^n)
+        st[1] = {2, c->W1, c->W[q], 0.5, 0.5};                   // 1/2 W^n + 1/2 (W(1) + dt R)
+    } else {
+        st[0] = {1, c->W[p], c->W[q], 0.0, 1.0};
+        st[1] = {3, c->W[q], c->W1, 0.75, 0.25};                 // 3/4 W^n + 1/4 (W(1) + dt R)
+        st[2] = {2, c->W1, c->W[q], 1.0 / 3.0, 2.0 / 3.0};       // 1/3 W^n + 2/3 (W(2) + dt R)
     }
-    HIPCHK(c, launch_fiver(ia, false, s));
-    if (ev) HIPCHK(c, hipEventRecord(ev[2], s));
-    sa.Win = c->W[p];
-    sa.W0 = c->W[p];
-    sa.Wout = c->W1;
-    HIPCHK(c, launch_stage(1, mixed, c->tx, c->ty, sa, s));
-    // stage 2: W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1)))
-    if (ev) HIPCHK(c, hipEventRecord(ev[3], s));
-    ia.Win = c->W1;
-    if (c->use_mlp) HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
-    HIPCHK(c, launch_fiver(ia, true, s));
-    if (ev) HIPCHK(c, hipEventRecord(ev[4], s));
-    sa.Win = c->W1;
-    sa.W0 = c->W[p];
-    sa.Wout = c->W[q];
-    HIPCHK(c, launch_stage(2, mixed, c->tx, c->ty, sa, s));
-    if (ev) HIPCHK(c, hipEventRecord(ev[5], s));
+    for (int k = 0; k < S; ++k) {
+        if (ev) HIPCHK(c, hipEventRecord(ev[1 + 2 * k], s));
+        ia.Win = st[k].win;
+        if (c->use_mlp) {
+            ia.guess = c->guessbuf;
+            HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
+        }
+        HIPCHK(c, launch_fiver(ia, k == S - 1, s));
+        if (ev) HIPCHK(c, hipEventRecord(ev[2 + 2 * k], s));
+        sa.Win = st[k].win;
+        sa.W0 = c->W[p];
+        sa.Wout = st[k].wout;
+        sa.c0 = st[k].c0;
+        sa.c1 = st[k].c1;
+        HIPCHK(c, launch_stage(st[k].kind, mixed, c->tx, c->ty, sa, s));
+    }
+    if (ev) HIPCHK(c, hipEventRecord(ev[1 + 2 * S], s));
 
     PhaseArgs& pa = *phase;
     pa.g = c->g;
@@ -290,10 +318,7 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, const PhaseArgs* prev, Ph
     pa.star = c->star;
     pa.qcap = c->qcap;
     pa.sc = c->sc;
-    if (ev) {
-        HIPCHK(c, hipEventRecord(ev[6], s));
-        ++c->ev_steps;
-    }
+    if (ev) ++c->ev_steps;
     return M2C_OK;
 }
 
@@ -320,7 +345,7 @@ int run_steps(m2c_ctx* c, int32_t nsteps, double dt_imposed, double* t_out)
     }
     if (nsteps > 0) {
         HIPCHK(c, launch_phase(pend[(nsteps - 1) & 1], c->stream));
-        HIPCHK(c, launch_end_step(c->sc, 2, c->stream));
+        HIPCHK(c, launch_end_step(c->sc, c->g.rk_stages, c->stream));
     }
     rc = pull_scalars(c);
     if (rc) return rc;
@@ -621,7 +646,7 @@ int m2c_set_profiling(m2c_ctx* c, int every)
     HIPCHK(c, hipSetDevice(c->device));
     const int on = every;
     if (on && c->evpool.empty()) {
-        c->evpool.resize(7 * 512, nullptr);
+        c->evpool.resize(EV_STRIDE * 512, nullptr);
         for (auto& e : c->evpool) HIPCHK(c, hipEventCreate(&e));
     }
     if (!on) {

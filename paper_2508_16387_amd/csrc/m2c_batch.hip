@@ -251,6 +251,7 @@ int m2c_batch_create(int32_t n, const m2c_config* cfgs, m2c_batch** out)
     for (int r = 0; r < n; ++r) {
         if (m2c_validate_config(&cfgs[r]) != M2C_OK) return M2C_ERR_ARG;
         if (cfgs[r].precision != cfgs[0].precision) return M2C_ERR_ARG;
+        if (cfgs[r].rk_order != 2) return M2C_ERR_ARG;         // the batched kernels are TVD-RK2
     }
     m2c_batch* b = new (std::nothrow) m2c_batch();
     if (!b) return M2C_ERR_NOMEM;

@@ -41,6 +41,7 @@ struct Grid {
     double rtol;
     int maxit;
     int guess;
+    int rk_stages;                 // Runge-Kutta stages per step (1, 2 or 3)
 };
 
 // Device buffers of one simulation.

@@ -30,16 +30,17 @@ struct RunDesc {
 struct StageArgs {
     Grid g;
     const double* Win;             // stage input state [6][N]
-    const double* W0;              // start-of-step state [6][N] (stage 2)
+    const double* W0;              // start-of-step state [6][N] (blended stages)
     double* Wout;                  // stage output [6][N]
     const uint8_t* chi;            // material ids frozen for the step
-    uint8_t* chi_next;             // stage 2: ids of the new level set
-    int32_t* flips;                // stage 2: flipped cells (append)
+    uint8_t* chi_next;             // last stage: ids of the new level set
+    int32_t* flips;                // last stage: flipped cells (append)
     const int32_t* fslot;          // [3N] face -> queue slot or -1
     const double* fluxF;           // [10][qcap] one-sided interface fluxes
     long long qcap;
     DevScalars* sc;
     int tiles_x, tiles_y, tiles_z, kz;
+    double c0, c1;                 // blend of the stage: c0 W0 + c1 (Win + dt R)
 };
 
 // Interface work-queue arguments (compaction, FIVER, phase update).
@@ -71,6 +72,8 @@ struct PhaseArgs {
 };
 
 bool stage_tile_supported(int tx, int ty);
+// stage: kind 1 (first), 2 (last, blended), 3 (middle of RK3), 4 (forward
+// Euler); the batched kernel has kinds 1 and 2 (TVD-RK2)
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
 // items: (run, tile) pairs over all runs of a batch
 hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDesc* runs, const int2* items,

@@ -68,7 +68,10 @@ def test_create_rejects_bad_config_without_gpu():
     ("pc", (-1.0, 0.0), False),
     ("limiter_alpha", 2.5, False),
     ("limiter_alpha", 1.0, True),           # MC with alpha = 1 is minmod
-    ("rk_order", 3, False),
+    ("rk_order", 3, True),                  # TVD-RK3
+    ("rk_order", 1, True),                  # forward Euler
+    ("rk_order", 4, False),
+    ("rk_order", 0, False),
     ("cfl", 0.0, False),
     ("precision", 7, False),
     ("riemann_rtol", 0.0, False),

@@ -191,6 +191,25 @@ def test_shock_bubble_small(m2c, tile):
     assert g.stats()["riemann_solves"] == o.stats()["riemann_solves"]
 
 
+# forward Euler and TVD-RK3 (section "Time integration"): the stage kernels
+# of the first, middle and last kinds with their blend weights
+@pytest.mark.parametrize("order,steps,cfl", [(1, 8, 0.15), (3, 25, 0.4)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rk_orders(m2c, order, steps, cfl, prec):
+    p = W.shock_bubble(7, nxyz=(24, 20, 18), radius=0.22, p_shock=1e9, shock_x=0.25, cfl=cfl)
+    o = oracle.OracleSim(p, rk_order=order)
+    g = m2c.Sim(m2c.config_for(p, precision=prec, rk_order=order), p.prim)
+    assert g.step(steps) == 0 and o.step(steps) == 0
+    e = compare_runs(g, o, p)
+    print("rk", order, prec, e)
+    assert e["id_mismatch"] == 0
+    tol = TOL_FP64 if prec == 0 else 1e-3
+    for k in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[k] <= tol, (k, e[k])
+    st = g.stats()
+    assert st["steps"] == steps and st["riemann_solves"] == o.stats()["riemann_solves"]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_bubble_next_to_rigid_wall(m2c, prec):
     """The paper's shock-induced collapse of a bubble near a rigid wall:

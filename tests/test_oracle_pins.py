@@ -292,9 +292,9 @@ def check_dt_uniform(lib):
 
 
 def check_conservation_periodic(lib):
-    for seed, mat in [(0, 0), (1, 1)]:
+    for seed, mat, order in [(0, 0, 2), (1, 1, 2), (3, 0, 3)]:
         p = W.periodic_box(seed, material=mat, n=(12, 10, 8))
-        s = _sim(p, lib)
+        s = _sim(p, lib, rk_order=order)
         c0 = s.cons().reshape(6, -1)
         assert s.step(15) == 0
         c1 = s.cons().reshape(6, -1)
@@ -302,6 +302,33 @@ def check_conservation_periodic(lib):
             tot0, tot1 = c0[v].sum(), c1[v].sum()
             scale = np.abs(c0[v]).sum()
             assert abs(tot1 - tot0) <= 64 * 15 * np.finfo(float).eps * scale, v
+
+
+def check_rk_temporal_order(lib):
+    """Forward Euler, TVD-RK2 and TVD-RK3 (section "Time integration")
+    converge at orders 1, 2 and 3 in dt on a linear semi-discrete system: a
+    uniform flow carrying a smooth level set (every face sees the same two
+    states, so the fluid residual is exactly zero, and the level-set
+    operator is linear in phi)."""
+    n = 32
+    p = W.periodic_box(0, n=(n, 1, 1))
+    x = (np.arange(n) + 0.5) / n
+    p.prim[0], p.prim[1], p.prim[2], p.prim[3], p.prim[4] = 1000.0, 1.0, 0.0, 0.0, 1e5
+    p.prim[5] = (2.0 + np.sin(2.0 * np.pi * x)).reshape(1, 1, n)
+    T = 0.5 / n                                  # half a cell at u = 1
+
+    def run(order, steps):
+        s = _sim(p, lib, rk_order=order)
+        assert s.step_dt(steps, T / steps) == 0
+        out = s.cons()
+        assert np.all(out[1] == out[1].ravel()[0])   # the flow stays exactly uniform
+        return out[5].ravel()
+
+    ref = run(3, 1280)
+    for order in (1, 2, 3):
+        e = [np.max(np.abs(run(order, m) - ref)) for m in (10, 20, 40)]
+        rates = [math.log2(e[0] / e[1]), math.log2(e[1] / e[2])]
+        assert all(abs(r - order) < 0.25 for r in rates), (order, e, rates)
 
 
 def check_conservation_wall(lib):
@@ -412,6 +439,7 @@ CHECKS = {
     "dt_uniform": check_dt_uniform,
     "conservation_periodic": check_conservation_periodic,
     "conservation_wall": check_conservation_wall,
+    "rk_temporal_order": check_rk_temporal_order,
     "uniform_translation": check_uniform_translation,
     "axis_permutation": check_axis_permutation,
     "shock_tube_exact": check_shock_tube_exact,
@@ -439,6 +467,9 @@ MUTANTS = [
     ("level-set stencil", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + f[0])", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + 2.0 * f[0])"),
     ("flux difference order", "R[v][c] += (FL[i + 1][v] - FU[i][v]) / s->h[d];", "R[v][c] += (FU[i + 1][v] - FL[i][v]) / s->h[d];"),
     ("RK2 weight", "0.5 * W0[v][c] + 0.5 * (W1[v][c] + dt * R[v][c])", "0.5 * W0[v][c] + 0.5 * (W1[v][c] + 0.9 * dt * R[v][c])"),
+    ("RK3 middle weight", "0.75 * W0[v][c] + 0.25 * W1[v][c]", "0.75 * W0[v][c] + 0.26 * W1[v][c]"),
+    ("RK3 level-set last weight", "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 2.0 / 3.0 * dt * L[c]",
+     "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 0.6 * dt * L[c]"),
     ("EOS gamma p_c term", "q[4] = (gamma - 1.0) * rho * e - gamma * pc;", "q[4] = (gamma - 1.0) * rho * e - pc;"),
 ]
 
