@@ -60,7 +60,12 @@ class Cfg(C.Structure):
                 ("gamma", C.c_double * 2), ("pc", C.c_double * 2),
                 ("bc", C.c_int32 * 6), ("alpha", C.c_double), ("rk_order", C.c_int32),
                 ("cfl", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double),
-                ("maxit", C.c_int32)]
+                ("maxit", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_int32),
+                ("flux", C.c_int32)]
+
+
+LIM_MC, LIM_VA, LIM_VA_MOD = 0, 1, 2
+FLUX_HLLC, FLUX_LLF = 0, 1
 
 
 class Stats(C.Structure):
@@ -105,6 +110,9 @@ def load(path: str | None = None):
     lib.ora_mc_slope.restype = C.c_double
     lib.ora_mc_slope.argtypes = [C.c_double, C.c_double, C.c_double]
     lib.ora_hllc.argtypes = [_D, _D, C.c_double, C.c_double, _D]
+    lib.ora_llf.argtypes = [_D, _D, C.c_double, C.c_double, _D]
+    lib.ora_va_slope.restype = C.c_double
+    lib.ora_va_slope.argtypes = [C.c_double, C.c_double, C.c_int32, C.c_int32]
     lib.ora_riemann.restype = C.c_int
     lib.ora_riemann.argtypes = [_D, _D, C.c_double, C.c_int32, _D, C.POINTER(C.c_int32)]
     lib.ora_riemann_many.restype = C.c_int64
@@ -124,7 +132,8 @@ def lib():
     return _lib
 
 
-def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50):
+def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_MC, limiter_k=2,
+             flux=FLUX_HLLC):
     c = Cfg()
     c.nx, c.ny, c.nz = problem.n
     for d in range(3):
@@ -141,6 +150,9 @@ def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50):
     c.dt_fixed = problem.dt_fixed
     c.rtol = rtol
     c.maxit = maxit
+    c.limiter = limiter
+    c.limiter_k = limiter_k
+    c.flux = flux
     return c
 
 
@@ -212,6 +224,16 @@ def hllc(qL, qR, gamma, pc):
     lib().ora_hllc(np.asarray(qL, dtype=np.float64), np.asarray(qR, dtype=np.float64),
                    gamma, pc, F)
     return F
+
+
+def llf(qL, qR, gamma, pc):
+    F = np.empty(5)
+    lib().ora_llf(np.asarray(qL, dtype=np.float64), np.asarray(qR, dtype=np.float64), gamma, pc, F)
+    return F
+
+
+def va_slope(dm, dp, k=2, modified=False):
+    return lib().ora_va_slope(dm, dp, k, 1 if modified else 0)
 
 
 def riemann(inp, eos, rtol=1e-12, maxit=50):

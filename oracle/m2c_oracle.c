@@ -79,6 +79,31 @@ double ora_mc_slope(double dminus, double dplus, double alpha)
     return lim * dplus;
 }
 
+/* Van Albada limiter, appendix "Slope limiters", eq. vanalbada on a uniform
+ * grid (A = B = 1): phi(theta) = B (theta^k + theta) / (theta^k + A); the
+ * modified limiter (eq. vanalbada_mod) sets phi = 0 where it is negative.
+ * The limited slope is phi(theta) (w_{i+1} - w_i), 0 when w_{i+1} = w_i;
+ * where theta^k overflows, phi takes its limit B.                         */
+double ora_va_slope(double dminus, double dplus, int32_t k, int32_t modified)
+{
+    if (dplus == 0.0) return 0.0;
+    const double h = 1.0;
+    const double A = (h + h) / (h + h);
+    const double B = 2.0 * h / (h + h);
+    double theta = dminus / dplus;
+    double tk = 1.0;
+    for (int32_t e = 0; e < k; ++e) tk *= theta;
+    double lim = isfinite(tk) ? B * (tk + theta) / (tk + A) : B;
+    if (modified && lim < 0.0) lim = 0.0;
+    return lim * dplus;
+}
+
+static double limited_slope(const ora_cfg* c, double dminus, double dplus)
+{
+    if (c->limiter == ORA_LIM_MC) return ora_mc_slope(dminus, dplus, c->alpha);
+    return ora_va_slope(dminus, dplus, c->limiter_k, c->limiter == ORA_LIM_VA_MOD);
+}
+
 /* ------------------------------------------------------------------------ */
 /* HLLC, appendix "HLLC flux".  States in the face frame: q = (rho, u, v, w, p)
  * with u the component along n_ij.  Davis wave-speed estimates S_ij, S_ji
@@ -142,6 +167,34 @@ void ora_hllc(const double* qL, const double* qR, double gamma, double pc, doubl
     } else {
         euler_flux(qR, ER, F);
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local Lax-Friedrichs, appendix "Local Lax-Friedrichs flux" (eq.
+ * Lax-Friedrichs): the mean of the two physical fluxes minus half the
+ * fastest wave speed max(|u_L| + c_L, |u_R| + c_R) times the jump of the
+ * conservative state.                                                     */
+void ora_llf(const double* qL, const double* qR, double gamma, double pc, double* F)
+{
+    double EL = specific_total_energy(qL, gamma, pc);
+    double ER = specific_total_energy(qR, gamma, pc);
+    double FL[5], FR[5], UL[5], UR[5];
+    euler_flux(qL, EL, FL);
+    euler_flux(qR, ER, FR);
+    UL[0] = qL[0]; UL[1] = qL[0] * qL[1]; UL[2] = qL[0] * qL[2]; UL[3] = qL[0] * qL[3]; UL[4] = qL[0] * EL;
+    UR[0] = qR[0]; UR[1] = qR[0] * qR[1]; UR[2] = qR[0] * qR[2]; UR[3] = qR[0] * qR[3]; UR[4] = qR[0] * ER;
+    double lmax = fmax(fabs(qL[1]) + sound_speed(qL[0], qL[4], gamma, pc),
+                       fabs(qR[1]) + sound_speed(qR[0], qR[4], gamma, pc));
+    for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lmax * (UR[v] - UL[v]);
+}
+
+/* The numerical flux of the configuration (section "Spatial discretization
+ * of governing equations": one flux function Phi for every face, the
+ * one-sided FIVER fluxes included).                                       */
+static void num_flux(const ora_cfg* c, const double* qL, const double* qR, double gamma, double pc, double* F)
+{
+    if (c->flux == ORA_FLUX_LLF) ora_llf(qL, qR, gamma, pc, F);
+    else ora_hllc(qL, qR, gamma, pc, F);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -487,7 +540,6 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                     double* R[5], double* L, int record)
 {
     int n[3] = {s->c.nx, s->c.ny, s->c.nz};
-    const double alpha = s->c.alpha;
     int rc = ORA_OK;
 
     /* primitives of every interior cell, then ghosts */
@@ -552,15 +604,15 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                         for (int v = 0; v < 5; ++v) {
                             int V = comp[v];
                             double sa = flat_a ? 0.0 :
-                                ora_mc_slope(s->P[V][pa] - s->P[V][pa - stride],
-                                             s->P[V][pa + stride] - s->P[V][pa], alpha);
+                                limited_slope(&s->c, s->P[V][pa] - s->P[V][pa - stride],
+                                              s->P[V][pa + stride] - s->P[V][pa]);
                             double sb = flat_b ? 0.0 :
-                                ora_mc_slope(s->P[V][pb] - s->P[V][pb - stride],
-                                             s->P[V][pb + stride] - s->P[V][pb], alpha);
+                                limited_slope(&s->c, s->P[V][pb] - s->P[V][pb - stride],
+                                              s->P[V][pb + stride] - s->P[V][pb]);
                             la[v] = qa[v] + 0.5 * sa;
                             rb[v] = qb[v] - 0.5 * sb;
                         }
-                        ora_hllc(la, rb, s->c.gamma[xa], s->c.pc[xa], Fr_l);
+                        num_flux(&s->c, la, rb, s->c.gamma[xa], s->c.pc[xa], Fr_l);
                         for (int v = 0; v < 5; ++v) Fr_u[v] = Fr_l[v];
                     } else {
                         /* FIVER: exact two-material Riemann problem along the
@@ -588,8 +640,8 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                         } else {
                             double sa[5] = {out[2], out[1], qa[2], qa[3], out[0]};
                             double sb[5] = {out[3], out[1], qb[2], qb[3], out[0]};
-                            ora_hllc(qa, sa, s->c.gamma[xa], s->c.pc[xa], Fr_l);
-                            ora_hllc(sb, qb, s->c.gamma[xb], s->c.pc[xb], Fr_u);
+                            num_flux(&s->c, qa, sa, s->c.gamma[xa], s->c.pc[xa], Fr_l);
+                            num_flux(&s->c, sb, qb, s->c.gamma[xb], s->c.pc[xb], Fr_u);
                             if (record && m >= 1) {
                                 ora_star r;
                                 r.pstar = out[0]; r.ustar = out[1]; r.rhoL = out[2]; r.rhoR = out[3];

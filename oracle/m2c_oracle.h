@@ -46,7 +46,13 @@ typedef struct {
     double cfl, dt_fixed;     /* dt_fixed > 0 overrides the CFL rule             */
     double rtol;              /* Newton stopping tolerance on p*                 */
     int32_t maxit;            /* Newton iterations before bisection              */
+    int32_t limiter;          /* ORA_LIM_MC, ORA_LIM_VA, ORA_LIM_VA_MOD            */
+    int32_t limiter_k;        /* Van Albada exponent k                           */
+    int32_t flux;             /* ORA_FLUX_HLLC, ORA_FLUX_LLF                     */
 } ora_cfg;
+
+enum { ORA_LIM_MC = 0, ORA_LIM_VA = 1, ORA_LIM_VA_MOD = 2 };
+enum { ORA_FLUX_HLLC = 0, ORA_FLUX_LLF = 1 };
 
 typedef struct {
     int64_t steps;
@@ -87,8 +93,12 @@ void ora_cons_to_prim(const double* w5, double gamma, double pc, double* q5);
 double ora_sound_speed(double rho, double p, double gamma, double pc);
 /* MC-limited slope from the backward and forward differences. */
 double ora_mc_slope(double dminus, double dplus, double alpha);
+/* Van Albada slope (modified: clamped at 0) with exponent k. */
+double ora_va_slope(double dminus, double dplus, int32_t k, int32_t modified);
 /* HLLC flux along +x in the face frame: q = (rho, u_n, v_t1, v_t2, p). */
 void ora_hllc(const double* qL, const double* qR, double gamma, double pc, double* F5);
+/* Local Lax-Friedrichs flux, same conventions. */
+void ora_llf(const double* qL, const double* qR, double gamma, double pc, double* F5);
 /* Exact two-material stiffened-gas Riemann problem.
  * in = (rho_L, u_L, p_L, rho_R, u_R, p_R), eos = (gamma_L, pc_L, gamma_R, pc_R)
  * out = (p*, u*, rho*_L, rho*_R); returns ORA_OK or ORA_ERR_RIEMANN (vacuum). */

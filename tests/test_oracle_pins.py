@@ -171,6 +171,67 @@ def check_hllc_properties(lib):
     assert np.allclose(_hllc(lib, qL, qR, g, pc), euler_flux_def(qR, g, pc), rtol=1e-14)
 
 
+def _llf(lib, qL, qR, g, pc):
+    F = np.empty(5)
+    lib.ora_llf(np.asarray(qL, float), np.asarray(qR, float), g, pc, F)
+    return F
+
+
+def check_van_albada(lib):
+    """Van Albada slopes (appendix "Slope limiters"): for k = 2 the textbook
+    symmetric form d- d+ (d- + d+) / (d-^2 + d+^2); symmetric in (d-, d+)
+    for every k; exact on linear data; a hand-evaluated value for k = 4; the
+    modified limiter keeps the slope where phi >= 0 and zeroes it elsewhere."""
+    rng = np.random.default_rng(21)
+    for _ in range(2000):
+        a, b = rng.normal(size=2) * 10.0 ** rng.uniform(-3, 3, size=2)
+        s2 = lib.ora_va_slope(a, b, 2, 0)
+        ref = a * b * (a + b) / (a * a + b * b)
+        assert abs(s2 - ref) <= 1e-14 * (abs(a) + abs(b))
+        for k in (2, 4):
+            assert abs(lib.ora_va_slope(a, b, k, 0) - lib.ora_va_slope(b, a, k, 0)) <= 1e-14 * (abs(a) + abs(b))
+            sk, sm = lib.ora_va_slope(a, b, k, 0), lib.ora_va_slope(a, b, k, 1)
+            assert sm == (sk if sk * b >= 0 else 0.0)
+    for d in (1e-3, 2.5, -7.0):
+        for k in (2, 4):
+            assert lib.ora_va_slope(d, d, k, 0) == pytest.approx(d, rel=1e-15)
+    # theta = 2, k = 4: phi = (16 + 2) / (16 + 1)
+    assert lib.ora_va_slope(2.0, 1.0, 4, 0) == pytest.approx(18.0 / 17.0, rel=1e-15)
+    assert lib.ora_va_slope(1.0, 0.0, 2, 0) == 0.0
+
+
+def check_llf_properties(lib):
+    """Local Lax-Friedrichs (appendix "Local Lax-Friedrichs flux"):
+    consistency, mirror symmetry, and the stationary contact, where the two
+    physical fluxes are (0, p, 0, 0, 0) and only the dissipation acts:
+    mass flux -max(c_L, c_R) (rho_R - rho_L) / 2."""
+    rng = np.random.default_rng(5)
+    for mat, (g, pc) in enumerate([AIR, WATER]):
+        for _ in range(300):
+            q = _rand_state(rng, mat)
+            F = _llf(lib, q, q, g, pc)
+            Fd = euler_flux_def(q, g, pc)
+            assert np.all(np.abs(F - Fd) <= 1e-13 * np.abs(Fd).max())
+            qa, qb = _rand_state(rng, mat), _rand_state(rng, mat)
+            F1 = _llf(lib, qa, qb, g, pc)
+            ma, mb = qa.copy(), qb.copy()
+            ma[1] *= -1
+            mb[1] *= -1
+            F2 = _llf(lib, mb, ma, g, pc)
+            sgn = np.array([-1, 1, -1, -1, -1])
+            assert np.all(np.abs(F2 - sgn * F1) <= 1e-12 * (np.abs(F1).max() + max(qa[4], qb[4])))
+            # stationary contact
+            qL, qR = _rand_state(rng, mat), _rand_state(rng, mat)
+            qL[1:4] = 0.0
+            qR[1:4] = 0.0
+            qR[4] = qL[4]
+            F = _llf(lib, qL, qR, g, pc)
+            cmax = max(math.sqrt(g * (qL[4] + pc) / qL[0]), math.sqrt(g * (qR[4] + pc) / qR[0]))
+            assert F[0] == pytest.approx(-0.5 * cmax * (qR[0] - qL[0]), rel=1e-13, abs=1e-12 * cmax * qR[0])
+            assert F[1] == pytest.approx(qL[4], rel=1e-14)
+            assert F[2] == 0.0 and F[3] == 0.0
+
+
 def check_riemann_vs_independent(lib, nprob=150, seed=11):
     inp, eos = W.riemann_problem_set(seed, nprob)
     nvac = 0
@@ -391,7 +452,7 @@ def _run_to_time(s, T, max_steps=5000):
     raise AssertionError("time target not reached")
 
 
-def check_shock_tube_exact(lib, seeds=(0, 1, 2), Ns=(250, 1000)):
+def check_shock_tube_exact(lib, seeds=(0, 1, 2), Ns=(250, 1000), **opts):
     """The scheme converges to the exact two-material solution (section
     "One-dimensional Riemann problems"): L1 errors of u and p against exact
     cell averages shrink with the grid and are small at 1000 cells."""
@@ -400,7 +461,7 @@ def check_shock_tube_exact(lib, seeds=(0, 1, 2), Ns=(250, 1000)):
         errs = []
         for N in Ns:
             p = W.shock_tube_1d(seed, nx=N)
-            s = _sim(p, lib)
+            s = _sim(p, lib, **opts)
             _run_to_time(s, T)
             q, _ = s.prim()
             inp = [1000.0, 0.0, p.meta["pL"], 1.0, 0.0, 1e5]
@@ -443,6 +504,12 @@ CHECKS = {
     "uniform_translation": check_uniform_translation,
     "axis_permutation": check_axis_permutation,
     "shock_tube_exact": check_shock_tube_exact,
+    "shock_tube_exact_llf_van_albada": lambda lib: check_shock_tube_exact(
+        lib, seeds=(0, 2), limiter=oracle.LIM_VA, limiter_k=2, flux=oracle.FLUX_LLF),
+    "shock_tube_exact_modified_van_albada": lambda lib: check_shock_tube_exact(
+        lib, seeds=(1,), limiter=oracle.LIM_VA_MOD, limiter_k=4),
+    "van_albada": check_van_albada,
+    "llf_properties": check_llf_properties,
     "interface_faces_listing": check_interface_faces_listing,
 }
 
@@ -460,13 +527,17 @@ MUTANTS = [
     ("Davis speed", "double SR = fmax(uL + cL, uR + cR);", "double SR = fmax(uL + cL, uR);"),
     ("shock wave function", "return (p - s->p) * q;", "return (p - s->p) * q * 1.0001;"),
     ("rarefaction exponent", "(pow(r, (g - 1.0) / (2.0 * g)) - 1.0)", "(pow(r, (g - 1.0) / (g)) - 1.0)"),
-    ("FIVER argument order", "ora_hllc(sb, qb, s->c.gamma[xb]", "ora_hllc(qb, sb, s->c.gamma[xb]"),
-    ("FIVER EOS side", "ora_hllc(qa, sa, s->c.gamma[xa], s->c.pc[xa]", "ora_hllc(qa, sa, s->c.gamma[xb], s->c.pc[xb]"),
+    ("FIVER argument order", "num_flux(&s->c, sb, qb, s->c.gamma[xb]", "num_flux(&s->c, qb, sb, s->c.gamma[xb]"),
+    ("FIVER EOS side", "num_flux(&s->c, qa, sa, s->c.gamma[xa], s->c.pc[xa]",
+     "num_flux(&s->c, qa, sa, s->c.gamma[xb], s->c.pc[xb]"),
     ("MC limiter middle term", "B / (A + 1.0) * (theta + 1.0)", "B / A * (theta + 1.0)"),
     ("face value half slope", "la[v] = qa[v] + 0.5 * sa;", "la[v] = qa[v] + sa;"),
     ("level-set stencil", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + f[0])", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + 2.0 * f[0])"),
     ("flux difference order", "R[v][c] += (FL[i + 1][v] - FU[i][v]) / s->h[d];", "R[v][c] += (FU[i + 1][v] - FL[i][v]) / s->h[d];"),
     ("RK2 weight", "0.5 * W0[v][c] + 0.5 * (W1[v][c] + dt * R[v][c])", "0.5 * W0[v][c] + 0.5 * (W1[v][c] + 0.9 * dt * R[v][c])"),
+    ("Van Albada numerator", "B * (tk + theta) / (tk + A)", "B * (tk - theta) / (tk + A)"),
+    ("LLF dissipation sign", "- 0.5 * lmax * (UR[v] - UL[v])", "+ 0.5 * lmax * (UR[v] - UL[v])"),
+    ("LLF state jump", "UL[1] = qL[0] * qL[1];", "UL[1] = qL[1];"),
     ("RK3 middle weight", "0.75 * W0[v][c] + 0.25 * W1[v][c]", "0.75 * W0[v][c] + 0.26 * W1[v][c]"),
     ("RK3 level-set last weight", "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 2.0 / 3.0 * dt * L[c]",
      "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 0.6 * dt * L[c]"),
