@@ -68,6 +68,13 @@ enum { M2C_PREC_FP64 = 0,        /* everything in FP64                          
                                     accumulation, level set and time step      */
 enum { M2C_GUESS_ACOUSTIC = 0,   /* linearised (acoustic) star-pressure guess   */
        M2C_GUESS_MLP = 1 };      /* learned guess, judged against the acoustic  */
+/* Slope limiters, appendix "Slope limiters" (uniform grid, A = B = 1). */
+enum { M2C_LIM_MC = 0,           /* monotonized central, parameter limiter_alpha */
+       M2C_LIM_VAN_ALBADA = 1,   /* (theta^k + theta) / (theta^k + 1)           */
+       M2C_LIM_VAN_ALBADA_MOD = 2 }; /* the same, 0 where negative             */
+/* Numerical flux at single-material faces and for the one-sided FIVER
+ * fluxes (appendix "Numerical flux functions"). */
+enum { M2C_FLUX_HLLC = 0, M2C_FLUX_LLF = 1 };
 
 /* Problem and method parameters (the "Mesh", "Equations", "BoundaryCondition",
  * "Space", "Time" and "ExactRiemannSolution" input classes of the paper's
@@ -78,7 +85,8 @@ typedef struct m2c_config {
     double lo[3], hi[3];        /* domain box                                  */
     double gamma[2], pc[2];     /* stiffened gas of material 0 and 1           */
     int32_t bc[6];              /* -x,+x,-y,+y,-z,+z; periodic must pair up    */
-    double limiter_alpha;       /* MC parameter alpha (paper default 1.2)      */
+    double limiter_alpha;       /* MC parameter alpha in [0, 2] (paper default
+                                   1.2; 0: constant reconstruction)             */
     int32_t rk_order;           /* 1 forward Euler, 2 TVD-RK2 (default), 3
                                    TVD-RK3 (Shu-Osher); batches: 2 only; other
                                    values: M2C_ERR_ARG                           */
@@ -91,6 +99,10 @@ typedef struct m2c_config {
     double riemann_rtol;        /* Newton stop: |dp| <= rtol (p - p_lo)        */
     int32_t riemann_maxit;      /* Newton steps before the bisection fallback  */
     int32_t tile_x, tile_y, tile_z;  /* stage-kernel tile; 0 = library choice  */
+    int32_t limiter;            /* M2C_LIM_* (default MC; batches: MC only)     */
+    int32_t limiter_k;          /* Van Albada exponent: even, 2..8 (default 2;
+                                   odd k has a pole at theta = -1)              */
+    int32_t flux;               /* M2C_FLUX_* (default HLLC; batches: HLLC only) */
 } m2c_config;
 
 /* Counters and timings since m2c_create (or the last m2c_reset_stats). */
@@ -122,8 +134,8 @@ typedef struct m2c_stats {
 typedef struct m2c_ctx m2c_ctx;
 
 /* Fill a configuration with the defaults: 1 cell, unit box, air/water,
- * transmissive, alpha 1.2, RK2, CFL 0.5, FP64, acoustic guess, rtol 1e-12,
- * maxit 50, library-chosen tiles. */
+ * transmissive, MC limiter with alpha 1.2 (Van Albada k 2), HLLC, RK2, CFL
+ * 0.5, FP64, acoustic guess, rtol 1e-12, maxit 50, library-chosen tiles. */
 void m2c_config_default(m2c_config* c);
 /* M2C_OK if m2c_create would accept the configuration, else M2C_ERR_ARG
  * (no device work, usable without a GPU). */
@@ -209,8 +221,8 @@ int m2c_get_tile(const m2c_ctx* ctx, int32_t tile[3]);
  * a step stops advancing (its last good state is kept) while the others go
  * on; m2c_batch_step then returns the first failing run's status. */
 typedef struct m2c_batch m2c_batch;
-/* cfgs: n valid configurations with one precision and rk_order 2; otherwise
- * M2C_ERR_ARG. */
+/* cfgs: n valid configurations with one precision, rk_order 2, the MC
+ * limiter and the HLLC flux; otherwise M2C_ERR_ARG. */
 int m2c_batch_create(int32_t n, const m2c_config* cfgs, m2c_batch** out);
 void m2c_batch_destroy(m2c_batch* b);
 const char* m2c_batch_last_error(const m2c_batch* b);

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     M2C_OK, M2C_ERR_ARG, M2C_ERR_NONPHYSICAL, M2C_ERR_RIEMANN, M2C_ERR_DEVICE, M2C_ERR_STATE,
     M2C_ERR_UNIMPLEMENTED, M2C_ERR_NOMEM, M2C_BC_TRANSMISSIVE, M2C_BC_WALL, M2C_BC_PERIODIC,
     M2C_PREC_FP64, M2C_PREC_MIXED, M2C_GUESS_ACOUSTIC, M2C_GUESS_MLP,
+    M2C_LIM_MC, M2C_LIM_VAN_ALBADA, M2C_LIM_VAN_ALBADA_MOD, M2C_FLUX_HLLC, M2C_FLUX_LLF,
     Config, Stats, M2CError, lib, lib_path, exported_symbols, config_default, config_for, Sim, Batch,
     eval_hllc, riemann_solve, Mlp, TrainOpts, mlp_features, riemann_solve_learned, NPARAM,
 )

@@ -18,6 +18,8 @@ M2C_ERR_DEVICE, M2C_ERR_STATE, M2C_ERR_UNIMPLEMENTED, M2C_ERR_NOMEM = -4, -5, -6
 M2C_BC_TRANSMISSIVE, M2C_BC_WALL, M2C_BC_PERIODIC = 0, 1, 2
 M2C_PREC_FP64, M2C_PREC_MIXED = 0, 1
 M2C_GUESS_ACOUSTIC, M2C_GUESS_MLP = 0, 1
+M2C_LIM_MC, M2C_LIM_VAN_ALBADA, M2C_LIM_VAN_ALBADA_MOD = 0, 1, 2
+M2C_FLUX_HLLC, M2C_FLUX_LLF = 0, 1
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -44,7 +46,8 @@ class Config(C.Structure):
                 ("limiter_alpha", C.c_double), ("rk_order", C.c_int32), ("cfl", C.c_double),
                 ("dt_fixed", C.c_double), ("precision", C.c_int32), ("guess", C.c_int32),
                 ("riemann_rtol", C.c_double), ("riemann_maxit", C.c_int32),
-                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32)]
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
+                ("limiter", C.c_int32), ("limiter_k", C.c_int32), ("flux", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -164,7 +167,7 @@ def config_default() -> Config:
 
 
 def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None,
-               rk_order=2) -> Config:
+               rk_order=2, limiter=M2C_LIM_MC, limiter_k=2, flux=M2C_FLUX_HLLC) -> Config:
     """Configuration for a problem description with attributes n, lo, hi,
     gamma, pc, bc, cfl, dt_fixed (as built by the ``workloads`` module)."""
     c = config_default()
@@ -182,6 +185,9 @@ def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2
     c.riemann_rtol = rtol
     c.riemann_maxit = maxit
     c.rk_order = rk_order
+    c.limiter = limiter
+    c.limiter_k = limiter_k
+    c.flux = flux
     if tile is not None:
         c.tile_x, c.tile_y, c.tile_z = tile
     return c

@@ -393,10 +393,10 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         fallbacks += it < 0;
         const double ps = out[0], us = out[1];
         double Fl[5], Fu[5];
-        hllc<double>(qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA, pick(G.gpc, xa),
-                     pick(G.inv_gm1, xa), Fl);
-        hllc<double>(out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB, pick(G.gpc, xb),
-                     pick(G.inv_gm1, xb), Fu);
+        num_flux<double>(G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA,
+                         pick(G.gpc, xa), pick(G.inv_gm1, xa), Fl);
+        num_flux<double>(G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB,
+                         pick(G.gpc, xb), pick(G.inv_gm1, xb), Fu);
         const long long Q = a.qcap;
         // face frame (mass, normal, t1, t2, energy) -> global components
         a.fluxF[0 * Q + q] = Fl[0];

@@ -28,6 +28,10 @@ using namespace m2c;
 
 const MlpDev* m2c_mlp_dev(const m2c_mlp* m);   // m2c_learned.hip
 
+static_assert(M2C_LIM_MC == LIM_MC && M2C_LIM_VAN_ALBADA == LIM_VA && M2C_LIM_VAN_ALBADA_MOD == LIM_VA_MOD &&
+                  M2C_FLUX_HLLC == FLUX_HLLC && M2C_FLUX_LLF == FLUX_LLF,
+              "option values shared by the ABI and the kernels");
+
 constexpr int EV_STRIDE = 8;        // events per timed step (up to three RK stages)
 
 struct m2c_ctx {
@@ -106,8 +110,12 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
     for (int m = 0; m < 2; ++m)
         if (!(c->gamma[m] > 1.0) || !(c->pc[m] >= 0.0) || !std::isfinite(c->pc[m]))
             return snprintf(why, n, "material %d needs gamma > 1 and p_c >= 0", m), false;
-    if (!(c->limiter_alpha >= 1.0 && c->limiter_alpha <= 2.0))
-        return snprintf(why, n, "limiter alpha must lie in [1, 2]"), false;
+    if (!(c->limiter_alpha >= 0.0 && c->limiter_alpha <= 2.0))
+        return snprintf(why, n, "limiter alpha must lie in [0, 2]"), false;
+    if (c->limiter < M2C_LIM_MC || c->limiter > M2C_LIM_VAN_ALBADA_MOD) return snprintf(why, n, "bad limiter"), false;
+    if (c->limiter != M2C_LIM_MC && (c->limiter_k < 2 || c->limiter_k > 8 || c->limiter_k % 2 != 0))
+        return snprintf(why, n, "Van Albada exponent k must be even, 2..8"), false;
+    if (c->flux != M2C_FLUX_HLLC && c->flux != M2C_FLUX_LLF) return snprintf(why, n, "bad flux"), false;
     if (c->rk_order < 1 || c->rk_order > 3)
         return snprintf(why, n, "rk_order must be 1 (forward Euler), 2 or 3 (TVD-RK)"), false;
     if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0)) return snprintf(why, n, "cfl must be > 0"), false;
@@ -149,6 +157,9 @@ void fill_grid(Grid& g, const m2c_config& c)
     g.maxit = c.riemann_maxit;
     g.guess = c.guess;
     g.rk_stages = c.rk_order;
+    g.limiter = c.limiter;
+    g.limk = c.limiter_k;
+    g.flux = c.flux;
 }
 
 // Reset the error state of the device scalars (host mirror -> device).
@@ -420,6 +431,9 @@ void m2c_config_default(m2c_config* c)
     c->guess = M2C_GUESS_ACOUSTIC;
     c->riemann_rtol = 1e-12;
     c->riemann_maxit = 50;
+    c->limiter = M2C_LIM_MC;
+    c->limiter_k = 2;
+    c->flux = M2C_FLUX_HLLC;
 }
 
 const char* m2c_strerror(int status) { return status_name(status); }

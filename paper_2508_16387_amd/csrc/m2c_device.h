@@ -9,6 +9,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "m2c_internal.h"
+
 namespace m2c {
 
 // Material parameter of material x (0 or 1) as a select rather than an
@@ -101,6 +103,31 @@ __device__ __forceinline__ T mc_slope(T dm, T dp, T alpha)
     return (dm * dp > T(0)) ? copysign(a, dp) : T(0);
 }
 
+// Van Albada slope (appendix "Slope limiters", eq. vanalbada with A = B = 1
+// on a uniform grid): phi(theta) = (theta^k + theta) / (theta^k + 1) with
+// theta = dm / dp, times dp; the modified limiter (eq. vanalbada_mod) takes
+// phi = 0 where it is negative; where theta^k overflows, phi takes its
+// limit 1; dp = 0 gives 0.
+template <typename T>
+__device__ __forceinline__ T va_slope(T dm, T dp, int k, bool modified)
+{
+    if (dp == T(0)) return T(0);
+    const T theta = dm / dp;
+    T tk = T(1);
+    for (int e = 0; e < k; ++e) tk *= theta;
+    T lim = isfinite(tk) ? (tk + theta) / (tk + T(1)) : T(1);
+    if (modified && lim < T(0)) lim = T(0);
+    return lim * dp;
+}
+
+// Limited slope of the configured limiter (limiter uniform over a launch).
+template <typename T>
+__device__ __forceinline__ T lim_slope(int limiter, int k, T dm, T dp, T alpha)
+{
+    if (limiter == LIM_MC) return mc_slope<T>(dm, dp, alpha);
+    return va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
+}
+
 // --------------------------------------------------------------- HLLC ------
 // Flux through a face with normal +n in the face frame: state = (rho, u_n,
 // v_t1, v_t2, p).  Davis wave speeds, contact speed S_*, and the star state
@@ -152,6 +179,37 @@ __device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
     } else {
         for (int v = 0; v < 5; ++v) F[v] = Fk[v];
     }
+}
+
+// ------------------------------------------------ local Lax-Friedrichs ----
+// Appendix "Local Lax-Friedrichs flux" (eq. Lax-Friedrichs), face frame as
+// for hllc: the mean of the physical fluxes minus half the fastest wave
+// speed max(|u_L| + c_L, |u_R| + c_R) times the jump of the conservative
+// state.
+template <typename T>
+__device__ __forceinline__ void llf(T rL, T uL, T aL, T bL, T pL, T rR, T uR, T aR, T bR, T pR, T g, T pc,
+                                    T gpc, T inv_gm1, T F[5])
+{
+    const T EL = eos_energy<T>(rL, uL, aL, bL, pL, gpc, inv_gm1);
+    const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
+    const T cL = sqrt_nr(g * (pL + pc) * rcp_nr(rL));
+    const T cR = sqrt_nr(g * (pR + pc) * rcp_nr(rR));
+    const T lm = fmax(fabs(uL) + cL, fabs(uR) + cR);
+    const T mL = rL * uL, mR = rR * uR;
+    F[0] = T(0.5) * (mL + mR) - T(0.5) * lm * (rR - rL);
+    F[1] = T(0.5) * (mL * uL + pL + (mR * uR + pR)) - T(0.5) * lm * (mR - mL);
+    F[2] = T(0.5) * (mL * aL + mR * aR) - T(0.5) * lm * (rR * aR - rL * aL);
+    F[3] = T(0.5) * (mL * bL + mR * bR) - T(0.5) * lm * (rR * bR - rL * bL);
+    F[4] = T(0.5) * ((EL + pL) * uL + (ER + pR) * uR) - T(0.5) * lm * (ER - EL);
+}
+
+// Numerical flux of the configuration (flux uniform over a launch).
+template <typename T>
+__device__ __forceinline__ void num_flux(int flux, T rL, T uL, T aL, T bL, T pL, T rR, T uR, T aR, T bR, T pR,
+                                         T g, T pc, T gpc, T inv_gm1, T F[5])
+{
+    if (flux == FLUX_LLF) llf<T>(rL, uL, aL, bL, pL, rR, uR, aR, bR, pR, g, pc, gpc, inv_gm1, F);
+    else hllc<T>(rL, uL, aL, bL, pL, rR, uR, aR, bR, pR, g, pc, gpc, inv_gm1, F);
 }
 
 // ----------------------------------------------- two-material Riemann ------

@@ -7,6 +7,8 @@ namespace m2c {
 
 enum { BC_TRANSMISSIVE = 0, BC_WALL = 1, BC_PERIODIC = 2 };
 enum { ST_OK = 0, ST_NONPHYSICAL = -2, ST_RIEMANN = -3, ST_OVERFLOW = -7 };
+enum { LIM_MC = 0, LIM_VA = 1, LIM_VA_MOD = 2 };       // the values of M2C_LIM_*
+enum { FLUX_HLLC = 0, FLUX_LLF = 1 };                  // the values of M2C_FLUX_*
 
 // Device-resident scalars of one simulation.  Everything a step needs from
 // the previous step (dt, error state) stays on the device so a whole step
@@ -42,6 +44,8 @@ struct Grid {
     int maxit;
     int guess;
     int rk_stages;                 // Runge-Kutta stages per step (1, 2 or 3)
+    int limiter, limk;             // slope limiter (M2C_LIM_*) and Van Albada exponent
+    int flux;                      // numerical flux (M2C_FLUX_*)
 };
 
 // Device buffers of one simulation.

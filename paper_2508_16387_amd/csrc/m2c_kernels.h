@@ -75,6 +75,8 @@ bool stage_tile_supported(int tx, int ty);
 // stage: kind 1 (first), 2 (last, blended), 3 (middle of RK3), 4 (forward
 // Euler); the batched kernel has kinds 1 and 2 (TVD-RK2)
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
+// the same with the configured limiter and flux (any, including MC + HLLC)
+hipError_t launch_stage_opts(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
 // items: (run, tile) pairs over all runs of a batch
 hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDesc* runs, const int2* items,
                               int nitems, hipStream_t s);

@@ -72,6 +72,16 @@ def test_create_rejects_bad_config_without_gpu():
     ("rk_order", 1, True),                  # forward Euler
     ("rk_order", 4, False),
     ("rk_order", 0, False),
+    ("limiter", 1, True),                   # Van Albada
+    ("limiter", 2, True),                   # modified Van Albada
+    ("limiter", 3, False),
+    ("limiter", -1, False),
+    ("limiter_k", 3, True),                 # ignored by MC
+    ("va_k", 4, True),
+    ("va_k", 3, False),                     # odd: pole at theta = -1
+    ("va_k", 10, False),
+    ("flux", 1, True),                      # local Lax-Friedrichs
+    ("flux", 2, False),
     ("cfl", 0.0, False),
     ("precision", 7, False),
     ("riemann_rtol", 0.0, False),
@@ -101,10 +111,27 @@ def test_validate_config_without_gpu(field, value, ok):
             c.bc[k] = value[k]
     elif field == "box":
         c.hi[0] = c.lo[0]
+    elif field == "va_k":
+        c.limiter, c.limiter_k = m.M2C_LIM_VAN_ALBADA, value
     else:
         setattr(c, field, value)
     rc = m.lib().m2c_validate_config(C.byref(c))
     assert (rc == m.M2C_OK) == ok, (field, value, rc)
+
+
+@pytest.mark.parametrize("field,value", [("rk_order", 3), ("limiter", 1), ("flux", 1), ("precision", None)])
+def test_batch_create_rejects_unsupported_without_gpu(field, value):
+    """The batched kernels are TVD-RK2 with MC and HLLC and one precision;
+    anything else is refused before any device call."""
+    import paper_2508_16387_amd as m
+    cfgs = (m.Config * 2)(m.config_default(), m.config_default())
+    if field == "precision":
+        cfgs[1].precision = m.M2C_PREC_MIXED
+    else:
+        setattr(cfgs[1], field, value)
+    h = C.c_void_p()
+    assert m.lib().m2c_batch_create(2, cfgs, C.byref(h)) == m.M2C_ERR_ARG
+    assert not h.value
 
 
 def test_missing_library_fails_loudly(tmp_path):

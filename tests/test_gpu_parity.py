@@ -210,6 +210,32 @@ def test_rk_orders(m2c, order, steps, cfl, prec):
     assert st["steps"] == steps and st["riemann_solves"] == o.stats()["riemann_solves"]
 
 
+# limiters and numerical fluxes other than MC + HLLC: the option kernels
+# (run-time choice), with the same choice in the FIVER one-sided fluxes; a
+# zero MC parameter gives constant reconstruction in the default kernels
+@pytest.mark.parametrize("lim,k,flux,alpha,order,tile", [
+    (oracle.LIM_VA, 2, oracle.FLUX_HLLC, 1.2, 2, None),
+    (oracle.LIM_VA_MOD, 4, oracle.FLUX_HLLC, 1.2, 2, (32, 7, 4)),
+    (oracle.LIM_MC, 2, oracle.FLUX_LLF, 1.2, 2, None),
+    (oracle.LIM_VA, 6, oracle.FLUX_LLF, 1.2, 3, (16, 15, 3)),
+    (oracle.LIM_MC, 2, oracle.FLUX_HLLC, 0.0, 2, None),
+])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_limiter_and_flux_options(m2c, lim, k, flux, alpha, order, tile, prec):
+    p = W.shock_bubble(8, nxyz=(26, 21, 17), radius=0.22, p_shock=1e9, shock_x=0.3)
+    o = oracle.OracleSim(p, limiter=lim, limiter_k=k, flux=flux, alpha=alpha, rk_order=order)
+    g = m2c.Sim(m2c.config_for(p, precision=prec, limiter=lim, limiter_k=k, flux=flux, alpha=alpha,
+                               rk_order=order, tile=tile), p.prim)
+    assert g.step(20) == 0 and o.step(20) == 0
+    e = compare_runs(g, o, p)
+    print("opts", lim, k, flux, alpha, order, prec, e)
+    assert e["id_mismatch"] == 0
+    tol = TOL_FP64 if prec == 0 else 1e-3
+    for name in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[name] <= tol, (name, e[name])
+    assert g.stats()["riemann_solves"] == o.stats()["riemann_solves"]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_bubble_next_to_rigid_wall(m2c, prec):
     """The paper's shock-induced collapse of a bubble near a rigid wall:
