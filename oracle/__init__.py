@@ -13,6 +13,9 @@ Contents
   self-similar exact solution used to pin the scheme.
 * ``mlp_ref.py`` -- FP64 features, forward, backward and Adam of the learned
   star-pressure guess.
+* ``riemann_eos.py`` -- the two-material Riemann problem with a general EOS
+  on each side (Noble-Abel stiffened gas, Mie-Grueneisen, JWL): bracketed
+  roots and a DOP853 integration of the isentropes.
 
 Parity status: the phase-update rule is a reading of an under-specified step
 and is "parity unpinned" beyond the translation and self-consistency tests;
