@@ -33,6 +33,7 @@ EXPORTS = [
     "m2c_batch_get_stats", "m2c_batch_set_tile", "m2c_batch_get_tile", "m2c_batch_autotune",
     "m2c_train_opts_default", "m2c_mlp_create", "m2c_mlp_destroy", "m2c_mlp_get_params", "m2c_mlp_features",
     "m2c_mlp_forward", "m2c_mlp_grad", "m2c_mlp_train", "m2c_riemann_solve_learned", "m2c_set_guess",
+    "m2c_riemann_solve_eos", "m2c_eos_eval",
 ]
 _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
               "m2c_batch_last_error", "m2c_train_opts_default", "m2c_mlp_destroy")
@@ -67,6 +68,27 @@ class TrainOpts(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("epochs", C.c_int32), ("batch", C.c_int32),
                 ("lr", C.c_float), ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
                 ("eps", C.c_float)]
+
+
+M2C_EOS_NASG, M2C_EOS_MG, M2C_EOS_JWL = 0, 1, 2
+M2C_EOS_MAX = 8
+
+
+class Eos(C.Structure):
+    """One material of the general-EOS entry points: family and up to seven
+    parameters (NASG: gamma, p_c, b, e_c; MG: rho_0, c_0, Gamma_0, s, e_0,
+    eta_min; JWL: omega, A_1, A_2, R_1, R_2, rho_0)."""
+    _fields_ = [("family", C.c_int32), ("reserved", C.c_int32), ("prm", C.c_double * 7)]
+
+
+def eos_table(materials):
+    """ctypes array of Eos from [(family, [params])]."""
+    arr = (Eos * len(materials))()
+    for i, (fam, prm) in enumerate(materials):
+        arr[i].family = int(fam)
+        for j, v in enumerate(prm):
+            arr[i].prm[j] = float(v)
+    return arr
 
 
 class M2CError(RuntimeError):
@@ -137,6 +159,8 @@ def _declare(L):
     L.m2c_mlp_train.argtypes = [vp, i64, vp, vp, C.POINTER(TrainOpts), vp, vp]
     L.m2c_riemann_solve_learned.argtypes = [vp, i64, vp, vp, d, i32, vp, vp, C.POINTER(i64), vp]
     L.m2c_set_guess.argtypes = [vp, vp]
+    L.m2c_riemann_solve_eos.argtypes = [i64, vp, vp, i32, vp, d, i32, d, vp, vp, vp]
+    L.m2c_eos_eval.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(L, name).restype = C.c_int
@@ -449,6 +473,34 @@ def riemann_solve(inp, eos, guess=M2C_GUESS_ACOUSTIC, rtol=1e-12, maxit=50, stre
     if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
         raise M2CError(rc, lib().m2c_strerror(rc).decode())
     return out, iters, rc
+
+
+def riemann_solve_eos(inp, mat, materials, rtol=1e-12, maxit=50, ds=0.0, stream=None, check=True):
+    """General-EOS two-material Riemann problems: inp [6, n] float64 and mat
+    [2, n] int32 cuda tensors, materials [(family, [params])].  Returns
+    (out [4, n], iters [n], rc)."""
+    import torch
+    n = inp.shape[1]
+    out = torch.empty((4, n), dtype=torch.float64, device=inp.device)
+    iters = torch.empty((n,), dtype=torch.int32, device=inp.device)
+    tab = eos_table(materials)
+    rc = lib().m2c_riemann_solve_eos(n, _ptr(inp), _ptr(mat), len(materials), tab, rtol, maxit, ds, _ptr(out),
+                                     _ptr(iters), _stream_of(inp, stream))
+    if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return out, iters, rc
+
+
+def eos_eval(rho, e, mat, materials, stream=None):
+    """Pressure and sound speed of states (rho, e) (float64 cuda tensors)
+    of materials mat (int32)."""
+    import torch
+    p, c = torch.empty_like(rho), torch.empty_like(rho)
+    rc = lib().m2c_eos_eval(rho.numel(), _ptr(rho), _ptr(e), _ptr(mat), len(materials), eos_table(materials),
+                            _ptr(p), _ptr(c), _stream_of(rho, stream))
+    if rc != M2C_OK:
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return p, c
 
 
 def _stream_of(t, stream):

@@ -1,0 +1,538 @@
+// m2c_eos.h -- general equations of state and the exact two-material
+// Riemann solve for one problem (internal; device code, and plain C++ when
+// M2C_HD is defined empty before inclusion).
+//
+// The interface fluxes of FIVER come from the exact solution of the 1D
+// bimaterial Riemann problem (eq. 1DRiemannProblem); with EOS other than the
+// stiffened gas the wave curves have no closed form, and the solve is the
+// nested iteration the paper points to as the expensive part ("Spatial
+// discretization", FIVER): an outer Newton iteration on the star pressure
+// p*, and for each side and each trial pressure either a Hugoniot solve
+// (shock) or an integration along the isentrope (rarefaction).
+//
+// Families (section "Equations of state" and its appendix): Noble-Abel
+// stiffened gas (eq. NASG_EOS), Mie-Grueneisen with its compression, small
+// tension and tensile-cutoff reference curves, JWL (eq. JWL_EOS, both
+// exponentials decaying in the specific volume).
+//
+// For each side K and trial pressure p, the velocity change f_K(p)
+// (u*_L = u_L - f_L, u*_R = u_R + f_R, F(p) = f_L + f_R + u_R - u_L = 0):
+//   shock (p > p_K): the Hugoniot energy relation
+//     H(v) = e(v, p) - e_K - (p + p_K)(v_K - v)/2 = 0
+//   solved by safeguarded Newton in the specific volume v (linear in v for
+//   NASG, so one step there), f = sqrt((p - p_K)(v_K - v));
+//   rarefaction (p <= p_K): the isentrope with y = ln(p - floor) as the
+//   independent variable, carrying s = ln(rho/rho_K) and f:
+//   ds/dy = (p - floor)/(rho c^2), df/dy = c ds/dy, by classical RK4 at
+//   steps of at most ds in y, straight to the trial pressure (no inner
+//   iteration).  Along y the stiffened-gas isentrope is exactly linear
+//   (ds/dy = 1/gamma), and the curves stay smooth where p approaches the
+//   floor at a finite density (JWL states below the reference isentrope),
+//   where a march in s would meet a logarithmic singularity.  The
+//   Mie-Grueneisen branch points (eta = 0, eta_min) are stepped onto
+//   exactly and each RK4 step stays on one branch.  The walk along each
+//   isentrope is kept between outer iterations and continued from where it
+//   stopped, so a solve integrates each rarefaction path about once.
+// Sound speeds and the derivatives the Newton steps need are written per
+// family in closed form of (rho, p): c^2 = dp/drho|_e + p dp/de|_rho / rho^2
+// reduces to gamma (p + p_c) v^2 / (v - b) (NASG), rho_0 v^2 (p_R' -
+// rho_0 Gamma_0 e_R' + Gamma_0 p) (MG) and ((1 + omega) p - T) v + T'
+// (JWL, T the exponential terms), with no subtraction of large energies.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "m2c.h"
+
+#ifndef M2C_HD
+#define M2C_HD __device__
+#endif
+
+namespace m2c {
+namespace eos {
+
+// Prepared constants of one material (host-computed from m2c_eos).
+//   NASG: k0 gamma, k1 p_c, k2 b, k3 e_c, k4 1/(gamma - 1), k5 gamma p_c
+//   MG:   k0 rho_0, k1 Gamma_0, k2 s, k3 e_0, k4 eta_min, k5 K_0 = rho_0 c_0^2,
+//         k6 rho_0 Gamma_0, k7 e_R(eta_min), k8 1/(rho_0 Gamma_0)
+//   JWL:  k0 omega, k1 A_1, k2 A_2, k3 R_1 rho_0, k4 R_2 rho_0,
+//         k5 omega/(R_1 rho_0), k6 omega/(R_2 rho_0), k7 1/omega
+//   all:  k10 smallest specific volume (b, (1 - 1/s)/rho_0 or 0), k11 floor
+struct EosK {
+    int fam;
+    int pad;
+    double k[12];
+};
+struct EosTable {
+    int n;
+    int pad;
+    EosK m[M2C_EOS_MAX];
+};
+constexpr int KVMIN = 10, KFLOOR = 11;
+
+// Mie-Grueneisen reference curves and their eta-derivatives.
+struct Ref {
+    double pR, eR, dpR, deR;
+};
+// Branch of the reference curves at eta: 0 compression, 1 small tension,
+// 2 tensile cutoff.
+M2C_HD inline int mg_branch(const EosK& m, double eta)
+{
+    return eta >= 0.0 ? 0 : (eta >= m.k[4] ? 1 : 2);
+}
+
+// Reference curves on a given branch (extended smoothly past its ends).
+M2C_HD inline Ref mg_ref_on(const EosK& m, double eta, int br)
+{
+    const double r0 = m.k[0], s = m.k[2], e0 = m.k[3], em = m.k[4], K0 = m.k[5];
+    Ref r;
+    if (br == 0) {
+        const double a = 1.0 / (1.0 - s * eta);
+        r.pR = K0 * eta * a * a;
+        r.dpR = K0 * (1.0 + s * eta) * a * a * a;
+        r.eR = 0.5 * r.pR * eta / r0 + e0;
+        r.deR = 0.5 * (r.dpR * eta + r.pR) / r0;
+    } else if (br == 1) {
+        r.pR = K0 * eta;
+        r.dpR = K0;
+        r.eR = 0.5 * K0 * eta * eta / r0 + e0;
+        r.deR = K0 * eta / r0;
+    } else {
+        const double pmin = m.k[KFLOOR];
+        r.pR = pmin;
+        r.dpR = 0.0;
+        r.eR = m.k[7] + pmin / r0 * (eta - em);
+        r.deR = pmin / r0;
+    }
+    return r;
+}
+
+M2C_HD inline Ref mg_ref(const EosK& m, double eta)
+{
+    return mg_ref_on(m, eta, mg_branch(m, eta));
+}
+
+// JWL exponential terms T(rho) = sum_i A_i (1 - omega rho/(R_i rho_0))
+// exp(-R_i rho_0 v) and dT/drho.
+M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
+{
+    const double rho = 1.0 / v;
+    const double x1 = exp(-m.k[3] * v), x2 = exp(-m.k[4] * v);
+    const double a1 = 1.0 - m.k[5] * rho, a2 = 1.0 - m.k[6] * rho;
+    const double v2 = v * v;
+    T = m.k[1] * a1 * x1 + m.k[2] * a2 * x2;
+    dT = m.k[1] * x1 * (a1 * m.k[3] * v2 - m.k[5]) + m.k[2] * x2 * (a2 * m.k[4] * v2 - m.k[6]);
+}
+
+// e(v, p)
+M2C_HD double eos_e(const EosK& m, double v, double p)
+{
+    if (m.fam == M2C_EOS_NASG) return (p + m.k[5]) * (v - m.k[2]) * m.k[4] + m.k[3];
+    if (m.fam == M2C_EOS_MG) {
+        const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
+        return r.eR + (p - r.pR) * m.k[8];
+    }
+    double T, dT;
+    jwl_terms(m, v, T, dT);
+    return (p - T) * v * m.k[7];
+}
+
+// p(v, e)
+M2C_HD double eos_p(const EosK& m, double v, double e)
+{
+    if (m.fam == M2C_EOS_NASG) return (e - m.k[3]) / ((v - m.k[2]) * m.k[4]) - m.k[5];
+    if (m.fam == M2C_EOS_MG) {
+        const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
+        return r.pR + m.k[6] * (e - r.eR);
+    }
+    double T, dT;
+    jwl_terms(m, v, T, dT);
+    return m.k[0] * e / v + T;
+}
+
+// c^2(v, p)
+M2C_HD double eos_c2(const EosK& m, double v, double p)
+{
+    if (m.fam == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v / (v - m.k[2]);
+    if (m.fam == M2C_EOS_MG) {
+        const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
+        return m.k[0] * v * v * (r.dpR - m.k[6] * r.deR + m.k[1] * p);
+    }
+    double T, dT;
+    jwl_terms(m, v, T, dT);
+    return ((1.0 + m.k[0]) * p - T) * v + dT;
+}
+
+// c^2(v, p) with the Mie-Grueneisen branch given (other families: eos_c2).
+M2C_HD double eos_c2_on(const EosK& m, double v, double p, int br)
+{
+    if (m.fam == M2C_EOS_MG) {
+        const Ref r = mg_ref_on(m, 1.0 - m.k[0] * v, br);
+        return m.k[0] * v * v * (r.dpR - m.k[6] * r.deR + m.k[1] * p);
+    }
+    return eos_c2(m, v, p);
+}
+
+// de/dv at constant p, and de/dp at constant v.
+M2C_HD void eos_ederiv(const EosK& m, double v, double p, double& ev, double& ep)
+{
+    if (m.fam == M2C_EOS_NASG) {
+        ev = (p + m.k[5]) * m.k[4];
+        ep = (v - m.k[2]) * m.k[4];
+    } else if (m.fam == M2C_EOS_MG) {
+        const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
+        ev = r.dpR / m.k[1] - m.k[0] * r.deR;
+        ep = m.k[8];
+    } else {
+        double T, dT;
+        jwl_terms(m, v, T, dT);
+        ev = (p - T + dT / v) * m.k[7];
+        ep = v * m.k[7];
+    }
+}
+
+// One side of the problem and its wave-curve state between outer iterations.
+struct Side {
+    double rho, v, p, e, c;        // state K
+    double fl;                     // pressure floor of the material
+    double s, y, f;                // current point of the isentrope walk
+    double vh;                     // last Hugoniot volume (0: none yet)
+};
+
+struct Wave {
+    double f, df, rho;
+};
+
+// One classical RK4 step of the isentrope over y = ln(p - floor), from
+// (y, s, f) to y + h: ds/dy = (p - floor)/(rho c^2), df/dy = c ds/dy.
+// False where c^2 <= 0 (outside the convex part of the EOS).
+M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, double& f)
+{
+    double ks[4], kf[4];
+    // every stage on one Mie-Grueneisen branch: a step never spans a branch
+    // point (the walk ends steps on them), but a stage predictor near one may
+    // overshoot it, and a step may start on one.  The branch is the one a
+    // quarter step ahead (s moves with y, ds/dy > 0).
+    int br = 0;
+    if (m.fam == M2C_EOS_MG) {
+        const double rho0 = K.rho * exp(s), q0 = exp(y);
+        const double c20 = eos_c2(m, 1.0 / rho0, K.fl + q0);
+        if (!(c20 > 0.0)) return false;
+        const double probe = s + 0.25 * h * q0 / (rho0 * c20);
+        br = mg_branch(m, 1.0 - m.k[0] / (K.rho * exp(probe)));
+    }
+    for (int j = 0; j < 4; ++j) {
+        const double a = j == 0 ? 0.0 : (j == 3 ? h : 0.5 * h);
+        const double ss = j == 0 ? s : s + a * ks[j - 1];
+        const double q = exp(y + a), rho = K.rho * exp(ss);
+        const double c2 = eos_c2_on(m, 1.0 / rho, K.fl + q, br);
+        if (!(c2 > 0.0) || !isfinite(c2)) return false;
+        ks[j] = q / (rho * c2);
+        kf[j] = ks[j] * sqrt(c2);
+    }
+    s += h * (ks[0] + 2.0 * ks[1] + 2.0 * ks[2] + ks[3]) * (1.0 / 6.0);
+    f += h * (kf[0] + 2.0 * kf[1] + 2.0 * kf[2] + kf[3]) * (1.0 / 6.0);
+    return isfinite(s) && isfinite(f);
+}
+
+// Walk the side's isentrope from its current point to y = Y in steps of at
+// most hmax.  For Mie-Grueneisen the branch points of the reference curves
+// (eta = 0 and eta = eta_min, where the slope of c^2 jumps) are stepped onto
+// exactly -- a Newton iteration on the length of the step that ends there --
+// so that no RK4 step spans one and each keeps its order.
+M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
+{
+    double kink[2] = {INFINITY, INFINITY};
+    if (m.fam == M2C_EOS_MG) {
+        kink[0] = log(m.k[0] / K.rho);
+        kink[1] = log(m.k[0] / ((1.0 - m.k[4]) * K.rho));
+    }
+    for (int guard = 0; guard < 100000; ++guard) {
+        const double rem = Y - K.y;
+        if (rem == 0.0) return true;
+        const int n = (int)ceil(fabs(rem) / hmax);
+        const double h = rem / (double)n;
+        double s = K.s, f = K.f;
+        if (!rk4_y(m, K, K.y, h, s, f)) return false;
+        int crossed = -1;
+        for (int j = 0; j < 2; ++j)
+            if ((K.s - kink[j]) * (s - kink[j]) < 0.0) crossed = j;
+        if (crossed < 0) {
+            K.y = n == 1 ? Y : K.y + h;
+            K.s = s;
+            K.f = f;
+            continue;
+        }
+        // shorten the step so that it ends on the branch point: root of
+        // g(hk) = s(hk) - s_kink on [0, h] by the Illinois variant of
+        // regula falsi (c^2, and with it the slope of g, may jump there)
+        const double sk = kink[crossed];
+        double a = 0.0, ga = K.s - sk, b = h, gb = s - sk;
+        double hk = b, sk_got = s, fk_got = f;
+        int side = 0;
+        for (int it = 0; it < 80; ++it) {
+            hk = (a * gb - b * ga) / (gb - ga);
+            sk_got = K.s;
+            fk_got = K.f;
+            if (!rk4_y(m, K, K.y, hk, sk_got, fk_got)) return false;
+            const double g = sk_got - sk;
+            if (fabs(g) <= 1e-14 * (1.0 + fabs(sk)) || fabs(b - a) <= 1e-15 * fabs(h)) break;
+            if ((g < 0.0) == (gb < 0.0)) {
+                b = hk;
+                gb = g;
+                if (side == -1) ga *= 0.5;
+                side = -1;
+            } else {
+                a = hk;
+                ga = g;
+                if (side == 1) gb *= 0.5;
+                side = 1;
+            }
+        }
+        // land just beyond the branch point, so that the first stage of the
+        // next step sees the branch the walk is entering (c^2 itself jumps
+        // at eta_min); the offset is far below the step error
+        const double dir = s > K.s ? 1.0 : -1.0;
+        K.y += hk;
+        K.s = sk_got + dir * 1e-12 * (1.0 + fabs(sk));
+        K.f = fk_got;
+        kink[crossed] = INFINITY;            // passed
+    }
+    return false;
+}
+
+// f_K(p) for p <= p_K: the isentrope walked to y = ln(p - floor).
+M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
+{
+    const Side good = K;
+    if (!walk(m, K, log(p - K.fl), hmax)) {
+        K = good;
+        return false;
+    }
+    const double r = K.rho * exp(K.s);
+    const double c2 = eos_c2(m, 1.0 / r, p);
+    if (!(c2 > 0.0)) {
+        K = good;
+        return false;
+    }
+    w.f = K.f;
+    w.rho = r;
+    w.df = 1.0 / (r * sqrt(c2));
+    return true;
+}
+
+// f_K(p) for p > p_K: Hugoniot volume by Newton in v, bracketed by
+// (v_min, v_K].
+M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
+{
+    const double vK = K.v, half = 0.5 * (p + K.p);
+    double lo = m.k[KVMIN], hi = vK;
+    double v = K.vh;
+    if (!(v > lo && v < hi)) {
+        v = vK - (p - K.p) * vK * vK / (K.c * K.c);       // acoustic estimate
+        if (!(v > lo)) v = lo + 0.5 * (hi - lo);
+    }
+    bool ok = false;
+    for (int it = 0; it < 100; ++it) {
+        const double H = eos_e(m, v, p) - K.e - half * (vK - v);
+        double ev, ep;
+        eos_ederiv(m, v, p, ev, ep);
+        if (H > 0.0) hi = v; else lo = v;
+        const double dH = ev + half;
+        double vn = v - H / dH;
+        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
+        const double dv = vn - v;
+        v = vn;
+        if (fabs(dv) <= 1e-15 * v) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok || !(v > m.k[KVMIN]) || !(v < vK)) return false;
+    K.vh = v;
+    const double dp = p - K.p, dvol = vK - v;
+    w.f = sqrt(dp * dvol);
+    w.rho = 1.0 / v;
+    // slope of f along the Hugoniot: v'(p) = -H_p / H_v
+    double ev, ep;
+    eos_ederiv(m, v, p, ev, ep);
+    const double vp = -(ep - 0.5 * dvol) / (ev + half);
+    // (the acoustic slope where the shock is too weak for the quotient)
+    w.df = dp > 1e-10 * (K.p - K.fl) ? (dvol - dp * vp) / (2.0 * w.f) : 1.0 / (K.rho * K.c);
+    return true;
+}
+
+M2C_HD inline bool wave(const EosK& m, Side& K, double p, double hmax, Wave& w)
+{
+    return p > K.p ? shock(m, K, p, w) : rarefaction(m, K, p, hmax, w);
+}
+
+M2C_HD inline double floor_margin(const Side& K)
+{
+    return 1e-12 * (K.p - K.fl) + 1e-6 * fabs(K.fl);
+}
+
+M2C_HD bool side_init(const EosK& m, double rho, double p, Side& K)
+{
+    K.fl = m.k[KFLOOR];
+    if (!(rho > 0.0) || !isfinite(rho) || !isfinite(p)) return false;
+    K.rho = rho;
+    K.v = 1.0 / rho;
+    K.p = p;
+    if (!(K.v > m.k[KVMIN])) return false;
+    if (!(p - K.fl > floor_margin(K))) return false;
+    const double c2 = eos_c2(m, K.v, p);
+    if (!(c2 > 0.0) || !isfinite(c2)) return false;
+    K.c = sqrt(c2);
+    K.e = eos_e(m, K.v, p);
+    K.s = 0.0;
+    K.y = log(p - K.fl);
+    K.f = 0.0;
+    K.vh = 0.0;
+    return true;
+}
+
+// Bisection point of the star-pressure bracket (lo, hi): geometric in the
+// distance from the higher floor when the bracket spans decades (near
+// cavitation the root sits many decades below the initial pressures),
+// arithmetic otherwise.
+M2C_HD inline double bisect(double lo, double hi, double base)
+{
+    const double a = lo - base, b = hi - base;
+    return b > 1e3 * a ? base + sqrt(a * b) : 0.5 * (lo + hi);
+}
+
+// One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials ml, mr;
+// res = (p*, u*, rho*_L, rho*_R) or NaN; returns the Newton steps (negative
+// after a bisection step; 0: no star state or an inadmissible input).
+M2C_HD inline int solve_one(const EosTable& tab, int ml, int mr, const double* q, double rtol, int maxit,
+                            double hmax, double* res)
+{
+    for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
+    int its = 0;
+    Side L, R;
+    bool ok = ml >= 0 && ml < tab.n && mr >= 0 && mr < tab.n;
+    ok = ok && side_init(tab.m[ok ? ml : 0], q[0], q[2], L);
+    ok = ok && side_init(tab.m[ok ? mr : 0], q[3], q[5], R);
+    if (ok) {
+        const EosK& mL = tab.m[ml];
+        const EosK& mR = tab.m[mr];
+        const double uL = q[1], uR = q[4], du = uR - uL;
+        const double pfl = fmax(L.fl + floor_margin(L), R.fl + floor_margin(R));
+        const double base = fmax(L.fl, R.fl);
+        // acoustic start
+        const double zL = L.rho * L.c, zR = R.rho * R.c;
+        double p = (zR * L.p + zL * R.p - zL * zR * du) / (zL + zR);
+        if (!(p > pfl)) p = pfl + 0.5 * (fmin(L.p, R.p) - pfl);
+        double lo = pfl, hi = INFINITY;
+        bool bis = false, floor_checked = false, conv = false;
+        Wave wl, wr;
+        ok = false;
+        for (its = 1; its <= maxit; ++its) {
+            if (!wave(mL, L, p, hmax, wl) || !wave(mR, R, p, hmax, wr)) {
+                // p lies below where an isentrope ends (c^2 reaches zero
+                // before the floor): it bounds the bracket from below
+                lo = p;
+                p = isinf(hi) ? 0.5 * (p + fmax(L.p, R.p)) : bisect(lo, hi, base);
+                bis = true;
+                continue;
+            }
+            const double F = wl.f + wr.f + du;
+            if (F < 0.0) lo = p; else hi = p;
+            double pn = p - F / (wl.df + wr.df);
+            const double tol = rtol * fmin(p - L.fl, p - R.fl);
+            if (fabs(pn - p) <= tol && pn > pfl) {
+                p = pn;
+                conv = true;
+                break;
+            }
+            if (!(pn > lo && pn < hi)) {
+                if (!(pn > lo) && lo == pfl && !floor_checked) {
+                    // the Newton step leaves the admissible range: is
+                    // there a star state above the floor at all?
+                    floor_checked = true;
+                    Wave a, b;
+                    if (!wave(mL, L, pfl, hmax, a) || !wave(mR, R, pfl, hmax, b)) break;
+                    if (a.f + b.f + du > 0.0) break;          // cavitation
+                }
+                pn = isinf(hi) ? p + fmax(p - pfl, fabs(p) + 1.0) : bisect(lo, hi, base);
+                bis = true;
+            }
+            p = pn;
+        }
+        if (conv && wave(mL, L, p, hmax, wl) && wave(mR, R, p, hmax, wr)) {
+            res[0] = p;
+            res[1] = 0.5 * (uL - wl.f + uR + wr.f);
+            res[2] = wl.rho;
+            res[3] = wr.rho;
+            ok = true;
+            if (bis) its = -its;
+        }
+    }
+    return ok ? its : 0;
+}
+
+// Table of prepared constants; false for invalid parameters.
+inline bool prepare(int32_t nmat, const m2c_eos* eos, EosTable& t)
+{
+    if (nmat < 1 || nmat > M2C_EOS_MAX || !eos) return false;
+    t = EosTable{};
+    t.n = nmat;
+    for (int i = 0; i < nmat; ++i) {
+        const double* a = eos[i].prm;
+        for (int j = 0; j < 7; ++j)
+            if (!isfinite(a[j])) return false;
+        EosK& m = t.m[i];
+        m.fam = eos[i].family;
+        double* k = m.k;
+        switch (m.fam) {
+            case M2C_EOS_NASG:
+                if (!(a[0] > 1.0) || !(a[1] >= 0.0) || !(a[2] >= 0.0)) return false;
+                k[0] = a[0];
+                k[1] = a[1];
+                k[2] = a[2];
+                k[3] = a[3];
+                k[4] = 1.0 / (a[0] - 1.0);
+                k[5] = a[0] * a[1];
+                k[KVMIN] = a[2];
+                k[KFLOOR] = -a[1];
+                break;
+            case M2C_EOS_MG: {
+                if (!(a[0] > 0.0) || !(a[1] > 0.0) || !(a[2] > 0.0) || !(a[3] >= 0.0) || !(a[5] < 0.0))
+                    return false;
+                const double K0 = a[0] * a[1] * a[1];
+                k[0] = a[0];
+                k[1] = a[2];
+                k[2] = a[3];
+                k[3] = a[4];
+                k[4] = a[5];
+                k[5] = K0;
+                k[6] = a[0] * a[2];
+                k[7] = 0.5 * K0 * a[5] * a[5] / a[0] + a[4];
+                k[8] = 1.0 / (a[0] * a[2]);
+                k[KVMIN] = a[3] > 1.0 ? (1.0 - 1.0 / a[3]) / a[0] : 0.0;
+                k[KFLOOR] = K0 * a[5];
+                break;
+            }
+            case M2C_EOS_JWL:
+                if (!(a[0] > 0.0) || !(a[3] > 0.0) || !(a[4] > 0.0) || !(a[5] > 0.0)) return false;
+                k[0] = a[0];
+                k[1] = a[1];
+                k[2] = a[2];
+                k[3] = a[3] * a[5];
+                k[4] = a[4] * a[5];
+                k[5] = a[0] / (a[3] * a[5]);
+                k[6] = a[0] / (a[4] * a[5]);
+                k[7] = 1.0 / a[0];
+                k[KVMIN] = 0.0;
+                k[KFLOOR] = 0.0;
+                break;
+            default:
+                return false;
+        }
+    }
+    return true;
+}
+
+}  // namespace eos
+}  // namespace m2c

@@ -134,6 +134,56 @@ def test_batch_create_rejects_unsupported_without_gpu(field, value):
     assert not h.value
 
 
+_GOOD_EOS = [(0, [1.4, 0.0, 0.0, 0.0]), (1, [2204.0, 2220.0, 0.65, 1.61, 0.0, -0.5]),
+             (2, [0.3, 3.712e11, 3.231e9, 4.15, 0.95, 1630.0])]
+
+
+@pytest.mark.parametrize("case,ok", [
+    ("valid", True), ("nmat0", False), ("nmat9", False), ("family", False), ("nasg_gamma", False),
+    ("mg_eta_min", False), ("mg_c0", False), ("jwl_omega", False), ("nan_param", False), ("ds_small", False),
+    ("ds_big", False), ("ds_default", True), ("rtol", False), ("maxit", False),
+])
+def test_riemann_eos_argument_checks_without_gpu(case, ok):
+    """m2c_riemann_solve_eos / m2c_eos_eval check their arguments and the
+    EOS table before any device call (n = 0 returns after the checks)."""
+    import paper_2508_16387_amd as m
+    mats = [(f, list(p)) for f, p in _GOOD_EOS]
+    nmat, ds, rtol, maxit = len(mats), 0.02, 1e-12, 50
+    if case == "nmat0":
+        nmat = 0
+    elif case == "nmat9":
+        mats = mats * 3
+        nmat = 9
+    elif case == "family":
+        mats[0] = (7, mats[0][1])
+    elif case == "nasg_gamma":
+        mats[0][1][0] = 1.0
+    elif case == "mg_eta_min":
+        mats[1][1][5] = 0.0
+    elif case == "mg_c0":
+        mats[1][1][1] = -1.0
+    elif case == "jwl_omega":
+        mats[2][1][0] = 0.0
+    elif case == "nan_param":
+        mats[2][1][1] = float("nan")
+    elif case == "ds_small":
+        ds = 1e-4
+    elif case == "ds_big":
+        ds = 0.6
+    elif case == "ds_default":
+        ds = 0.0
+    elif case == "rtol":
+        rtol = 0.0
+    elif case == "maxit":
+        maxit = 0
+    tab = m.eos_table(mats)
+    rc = m.lib().m2c_riemann_solve_eos(0, None, None, nmat, tab, rtol, maxit, ds, None, None, None)
+    assert (rc == m.M2C_OK) == ok, (case, rc)
+    if case not in ("ds_small", "ds_big", "rtol", "maxit"):
+        rc = m.lib().m2c_eos_eval(0, None, None, None, nmat, tab, None, None, None)
+        assert (rc == m.M2C_OK) == ok, (case, rc)
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without the built HIP library the package raises instead of falling
     back to anything else (checked in a fresh interpreter)."""

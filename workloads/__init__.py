@@ -33,7 +33,7 @@ __all__ = [
     "SplitMix64", "Problem", "WATER", "AIR",
     "shock_tube_1d", "shock_bubble", "bubble_cloud", "batched_shock_bubbles",
     "riemann_problem_set", "uniform_translation", "periodic_box",
-    "post_shock_state",
+    "post_shock_state", "EOS_MATERIALS", "general_eos_problem_set",
 ]
 
 _MASK = (1 << 64) - 1
@@ -388,3 +388,79 @@ def riemann_problem_set(seed: int, n: int, zero_du_fraction: float = 0.5):
     inp[:, 1] = -0.5 * du
     inp[:, 4] = 0.5 * du
     return inp, eos
+
+
+# Materials of the general-EOS Riemann problems, as (family, parameters) in
+# the layout of the library's material table (0 Noble-Abel stiffened gas:
+# gamma, p_c, b, e_c; 1 Mie-Grueneisen: rho_0, c_0, Gamma_0, s, e_0, eta_min;
+# 2 JWL: omega, A_1, A_2, R_1, R_2, rho_0; SI units), the kinds of materials
+# of the paper's Riemann-problem and impact examples, with the sampling
+# ranges of their states: density (lo, hi, log?), pressure (lo, hi, log?) and
+# a nominal sound speed that only scales the velocity jumps.
+EOS_MATERIALS = {
+    "air": (0, [1.4, 0.0, 0.0, 0.0], (0.5, 50.0, True), (3e4, 3e7, True), 340.0),
+    "gas_nasg": (0, [1.6, 0.0, 2.0e-4, 3.0e5], (0.5, 50.0, True), (3e4, 3e7, True), 400.0),
+    "water_sg": (0, [6.12, 3.43e8, 0.0, 0.0], (950.0, 1100.0, False), (1e5, 1e9, True), 1500.0),
+    "water_nasg": (0, [1.19, 7.028e8, 6.61e-4, -1.177788e6], (950.0, 1100.0, False), (1e5, 1e9, True), 1500.0),
+    "glass": (1, [2204.0, 2220.0, 0.65, 1.61, 0.0, -0.5], (2193.0, 2336.0, False), (0.0, 5e9, False), 2220.0),
+    "copper": (1, [8930.0, 3940.0, 2.0, 1.49, 0.0, -0.1], (8885.0, 9466.0, False), (0.0, 5e9, False), 3940.0),
+    "tantalum": (1, [16650.0, 3414.0, 1.6, 1.2, 1.0e4, -0.05], (16567.0, 17649.0, False), (0.0, 5e9, False),
+                 3414.0),
+    "tnt": (2, [0.3, 3.712e11, 3.231e9, 4.15, 0.95, 1630.0], (300.0, 1700.0, False), (1e8, 2e10, True), 3000.0),
+}
+
+# Material pairs of the general-EOS problem sets: gas / solid, liquid / gas,
+# solid / solid, detonation products / gas, liquid and solid.
+EOS_PAIRS = [("air", "glass"), ("water_nasg", "gas_nasg"), ("copper", "tantalum"), ("tnt", "air"),
+             ("tnt", "water_sg"), ("glass", "water_nasg"), ("copper", "tnt"), ("water_sg", "air")]
+
+
+def general_eos_problem_set(seed: int, n: int, pairs=None):
+    """Random two-material Riemann problems with general EOS.
+
+    Returns (inp [6, n], mat [2, n] int32, materials, names): inp rows are
+    (rho_L, u_L, p_L, rho_R, u_R, p_R), mat the left and right indices into
+    materials = [(family, params)] (in the order of ``names``).
+
+    Per problem, seven draws in this order: the pair (uniform over
+    ``pairs``, default EOS_PAIRS); which member goes left (the first if
+    U < 0.5); left density; left pressure; right density; right pressure
+    (each uniform or log-uniform over the material's range); the velocity
+    jump factor U(-1, 0.6), times the smaller nominal sound speed of the
+    two: du = u_R - u_L > 0 separates the sides (rarefactions, and
+    cavitation when too fast), du < 0 compresses them (shocks);
+    u_L = -du/2, u_R = +du/2.
+    """
+    pairs = list(pairs or EOS_PAIRS)
+    names = sorted({m for pr in pairs for m in pr})
+    index = {m: i for i, m in enumerate(names)}
+    materials = [(EOS_MATERIALS[m][0], list(EOS_MATERIALS[m][1])) for m in names]
+    rng = SplitMix64(seed)
+    U = rng.uniforms(n * 7).reshape(n, 7)
+
+    def draw(u, rng_spec):
+        lo, hi, log = rng_spec
+        return np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo))) if log else lo + u * (hi - lo)
+
+    inp = np.empty((6, n))
+    mat = np.empty((2, n), dtype=np.int32)
+    k = np.minimum((U[:, 0] * len(pairs)).astype(np.int64), len(pairs) - 1)
+    for j, (a, b) in enumerate(pairs):
+        sel = k == j
+        first_left = U[sel, 1] < 0.5
+        left = np.where(first_left, index[a], index[b])
+        right = np.where(first_left, index[b], index[a])
+        mat[0, sel], mat[1, sel] = left, right
+        for side, (ur, up, row) in enumerate(((2, 3, 0), (4, 5, 3))):
+            ids = left if side == 0 else right
+            for m in (a, b):
+                t = ids == index[m]
+                spec = EOS_MATERIALS[m]
+                where = np.flatnonzero(sel)[t]
+                inp[row, where] = draw(U[where, ur], spec[2])
+                inp[row + 2, where] = draw(U[where, up], spec[3])
+        cmin = min(EOS_MATERIALS[a][4], EOS_MATERIALS[b][4])
+        du = (-1.0 + 1.6 * U[sel, 6]) * cmin
+        inp[1, sel] = -0.5 * du
+        inp[4, sel] = 0.5 * du
+    return inp, mat, materials, names
