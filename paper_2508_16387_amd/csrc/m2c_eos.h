@@ -250,6 +250,32 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
     for (int guard = 0; guard < 100000; ++guard) {
         const double rem = Y - K.y;
         if (rem == 0.0) return true;
+        if (m.fam == M2C_EOS_MG) {
+            // below eta_min the isentrope is known in closed form: there
+            // c^2 = rho_0 Gamma_0 (p - p_min) v^2, so ds/dy = rho/(rho_0
+            // Gamma_0), i.e. exp(-s) falls linearly in y, and df/dy =
+            // sqrt((p - p_min)/(rho_0 Gamma_0))
+            const double dir = rem > 0.0 ? 1.0 : -1.0;
+            if (mg_branch(m, 1.0 - m.k[0] / (K.rho * exp(K.s + dir * 1e-10))) == 2) {
+                const double a = K.rho * m.k[8];
+                double yend = Y;
+                bool to_kink = false;
+                if (dir > 0.0 && isfinite(kink[1])) {
+                    const double yk = K.y + (exp(-K.s) - exp(-kink[1])) / a;
+                    if (yk < Y) {
+                        yend = yk;
+                        to_kink = true;
+                    }
+                }
+                const double em = exp(-K.s) - a * (yend - K.y);
+                if (!(em > 0.0)) return false;
+                K.f += 2.0 * sqrt(m.k[8]) * (exp(0.5 * yend) - exp(0.5 * K.y));
+                K.s = to_kink ? kink[1] + 1e-12 * (1.0 + fabs(kink[1])) : -log(em);
+                K.y = yend;
+                if (to_kink) kink[1] = INFINITY;
+                continue;
+            }
+        }
         const int n = (int)ceil(fabs(rem) / hmax);
         const double h = rem / (double)n;
         double s = K.s, f = K.f;
@@ -304,6 +330,22 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
 // f_K(p) for p <= p_K: the isentrope walked to y = ln(p - floor).
 M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
+    if (m.fam == M2C_EOS_NASG) {
+        // closed form: along the isentrope (p + p_c)(v - b)^gamma is
+        // constant, and integrating dp/(rho c) with c^2 = gamma (p + p_c)
+        // v^2/(v - b) gives f = 2 c_K (1 - b rho_K)/(gamma - 1)
+        // ((p + p_c)/(p_K + p_c))^((gamma - 1)/(2 gamma)) - 1)
+        const double g = m.k[0], pc = m.k[1], b = m.k[2];
+        const double qb = p + pc, qK = K.p + pc;
+        if (!(qb > 0.0)) return false;
+        // ln((p + p_c)/(p_K + p_c)), accurate near 0 and near cavitation
+        const double lr = fabs(p - K.p) < 0.5 * qK ? log1p((p - K.p) / qK) : log(qb / qK);
+        const double VK = K.v - b, V = VK * exp(-lr / g);
+        w.f = 2.0 * K.c * (VK / K.v) / (g - 1.0) * expm1(0.5 * (g - 1.0) / g * lr);
+        w.rho = 1.0 / (V + b);
+        w.df = sqrt(V / (g * qb));                        // 1/(rho c)
+        return true;
+    }
     const Side good = K;
     if (!walk(m, K, log(p - K.fl), hmax)) {
         K = good;
@@ -443,6 +485,14 @@ M2C_HD inline int solve_one(const EosTable& tab, int ml, int mr, const double* q
             const double tol = rtol * fmin(p - L.fl, p - R.fl);
             if (fabs(pn - p) <= tol && pn > pfl) {
                 p = pn;
+                conv = true;
+                break;
+            }
+            // F at the rounding level of its terms, or a bracket closed to a
+            // few ulps: p is as good as FP64 resolves it (near cavitation
+            // the stopping rule above asks for more)
+            if (fabs(F) <= 8e-16 * (fabs(wl.f) + fabs(wr.f) + fabs(uL) + fabs(uR)) ||
+                (isfinite(hi) && hi - lo <= 4e-16 * fabs(hi))) {
                 conv = true;
                 break;
             }
