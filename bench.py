@@ -181,6 +181,33 @@ def fiver_standalone(m2c, torch, n=1_000_000):
             "newton_iters_per_solve": float(it[ok].mean()), "vacuum": int((~ok).sum())}
 
 
+def general_eos_standalone(m2c, torch, n=1 << 20):
+    """Two-material Riemann solves/s with a general EOS on each side (NASG,
+    Mie-Grueneisen, JWL): the mixed set of eight material pairs in one launch,
+    and single-pair sets of three kinds (gas / solid, detonation products /
+    gas, solid / solid in tension)."""
+    import workloads as W
+
+    def run(pairs):
+        inp, mat, mats, _ = W.general_eos_problem_set(2024, n, pairs=pairs)
+        ti = torch.tensor(inp, dtype=torch.float64, device="cuda")
+        tm = torch.tensor(mat, dtype=torch.int32, device="cuda")
+        m2c.riemann_solve_eos(ti, tm, mats)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, it, rc = m2c.riemann_solve_eos(ti, tm, mats)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        ok = it != 0
+        return {"solves_per_s": n / T, "ms": T * 1e3, "newton_iters_per_solve": float(it.abs().double()[ok].mean()),
+                "no_star_state": int((~ok).sum())}
+
+    res = {"problems": n, "ds": 0.01, "mixed_pairs": run(None)}
+    for pr in (("air", "glass"), ("tnt", "air"), ("copper", "tantalum")):
+        res["-".join(pr)] = run([pr])
+    return res
+
+
 def host_round_trip(m2c, torch, problem, steps):
     """The same FP64 run with the state handed over in host memory: upload
     (primitive -> conservative on the device), `steps` steps, download.  A
@@ -281,10 +308,23 @@ def cpu_baseline(problem, steps):
     t = time.perf_counter() - t0
     assert rc == 0
     N = problem.ncells
+    # the general-EOS Riemann oracle on a sample of the mixed problem set
+    import workloads as W
+    from oracle import riemann_eos as RE
+
+    ne = 64
+    inp, mat, mats, _ = W.general_eos_problem_set(2024, ne)
+    eos = [RE.make_eos(f, prm) for f, prm in mats]
+    t0 = time.perf_counter()
+    RE.solve(inp, mat, eos)
+    te = time.perf_counter() - t0
     return {"value": N * steps * 2 / t, "unit": "cell-updates/s per RK stage", "cores": 1,
             "kind": "oracle",
             "sample": f"first {steps} steps of the same {problem.n[0]}x{problem.n[1]}x{problem.n[2]} "
-                      f"shock-bubble run, single-threaded C oracle ({t:.1f} s)"}
+                      f"shock-bubble run, single-threaded C oracle ({t:.1f} s)",
+            "general_eos_riemann": {"solves_per_s": ne / te, "cores": 1,
+                                    "sample": f"first {ne} problems of the mixed general-EOS set, Python/scipy "
+                                              f"oracle ({te:.1f} s)"}}
 
 
 def main():
@@ -374,6 +414,7 @@ def main():
             "batched": batched_forms(m2c, torch, args.batch_steps),
             "fiver_standalone": fiver_standalone(m2c, torch),
             "learned_guess_standalone": learned_standalone(m2c, torch),
+            "general_eos_riemann": general_eos_standalone(m2c, torch),
             "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
         }
         if args.cloud_steps > 0:
