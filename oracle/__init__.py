@@ -16,6 +16,9 @@ Contents
 * ``riemann_eos.py`` -- the two-material Riemann problem with a general EOS
   on each side (Noble-Abel stiffened gas, Mie-Grueneisen, JWL): bracketed
   roots and a DOP853 integration of the isentropes.
+* ``reinit.py`` -- level-set reinitialization towards a signed distance
+  (upwind Godunov |grad phi|, smoothed sign, fixed first layer, optional
+  narrow band), in numpy.
 
 Parity status: the phase-update rule is a reading of an under-specified step
 and is "parity unpinned" beyond the translation and self-consistency tests;
