@@ -17,7 +17,8 @@ b = D^+ phi per axis,
     S < 0:  |grad phi|^2 = sum_d max(min(a_d, 0)^2, max(b_d, 0)^2)
 
 and forward-Euler pseudo-time steps phi <- phi - dtau S (|grad phi| - 1),
-dtau = 0.5 min_d h_d (below the monotonicity limit 1/sqrt(sum_d h_d^-2)).
+dtau = 0.5 min_d h_d (below the monotonicity limit 1/sqrt(sum_d h_d^-2));
+the minima run over the axes with more than one cell.
 
 Readings (the paper gives the equation, not these choices): first-order
 one-sided differences and forward Euler; a fixed number of pseudo-time
@@ -67,9 +68,16 @@ def first_layer(phi0, bc):
     return fl
 
 
+def _hmin(shape, h):
+    """Smallest cell width over the axes with more than one cell."""
+    act = [h[d] for d in range(3) if shape[2 - d] > 1]
+    return min(act) if act else min(h)
+
+
 def speed(phi0, h, bc, band=0.0, eps=None):
-    """S(phi_0) with the frozen cells (first layer, outside the band) at 0."""
-    eps = min(h) if eps is None else eps
+    """S(phi_0) with the frozen cells (first layer, outside the band) at 0;
+    eps defaults to the smallest cell width."""
+    eps = _hmin(phi0.shape, h) if eps is None else eps
     S = smoothed_sign(phi0, eps)
     S[first_layer(phi0, bc)] = 0.0
     if band > 0.0:
@@ -99,7 +107,7 @@ def reinit(phi0, h, bc, iters, band=0.0, eps=None):
     """phi after `iters` pseudo-time steps (phi0 is (nz, ny, nx) float64)."""
     phi0 = np.asarray(phi0, dtype=np.float64)
     S = speed(phi0, h, bc, band, eps)
-    dtau = 0.5 * min(h[d] for d in range(3) if phi0.shape[2 - d] > 1)
+    dtau = 0.5 * _hmin(phi0.shape, h)
     phi = phi0.copy()
     for _ in range(iters):
         phi = phi - dtau * S * (grad_norm(phi, S, h, bc) - 1.0)

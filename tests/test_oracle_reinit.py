@@ -115,7 +115,7 @@ MUTANTS = [
      "check_plane_fixed_point"),
     ("first layer not frozen", "    S[first_layer(phi0, bc)] = 0.0\n", "", "check_1d_steady_state"),
     ("one-sided difference sign", "a = (c - P[lo]) / h[d]", "a = (P[lo] - c) / h[d]", "check_1d_steady_state"),
-    ("pseudo-time step", "dtau = 0.5 * min(", "dtau = 0.05 * min(", "check_sphere_converges"),
+    ("pseudo-time step", "dtau = 0.5 * _hmin(", "dtau = 0.05 * _hmin(", "check_sphere_converges"),
 ]
 
 
