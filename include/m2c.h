@@ -310,6 +310,34 @@ int m2c_riemann_solve_learned(const m2c_mlp* m, int64_t n, const double* in, con
  * steps (NULL: back to the acoustic guess). */
 int m2c_set_guess(m2c_ctx* ctx, const m2c_mlp* m);
 
+/* ---- level-set reinitialization (section "Level set method", eq. reinit) --
+ * iters forward-Euler pseudo-time steps (dtau = 0.5 of the smallest cell
+ * width over the axes with more than one cell) of
+ *   d phi/d tau + S(phi_0)(|grad phi| - 1) = 0,  S = phi_0/sqrt(phi_0^2 + eps^2),
+ * eps = the smallest cell width, |grad phi| by the Godunov upwind form of
+ * one-sided differences.  Cells with a face neighbour on the other side of
+ * the zero level set (phi >= 0 counting as the non-negative side) keep their
+ * value (fixed first layer), so the interface and the material ids stay
+ * where they are; band > 0 restricts the update to |phi_0| < band (narrow
+ * band), band = 0 updates the whole grid.  Boundary images as in the step:
+ * periodic axes wrap, transmissive and wall sides repeat the boundary cell.
+ * FP64, deterministic (Jacobi iterates). */
+/* On the context's current level set, between steps (stream-ordered on the
+ * context's stream; uses the context's stage buffer as workspace).
+ * M2C_ERR_STATE before a state is set; M2C_ERR_ARG for iters < 0 or
+ * band < 0. */
+int m2c_reinit(m2c_ctx* ctx, int32_t iters, double band);
+/* Workspace bytes m2c_reinit_field needs for an nx x ny x nz grid:
+ * 16 N + 4 ceil(nx/64) ceil(ny/4) ceil(nz/4). */
+int m2c_reinit_workspace(int32_t nx, int32_t ny, int32_t nz, int64_t* bytes);
+/* On a level set phi [N] (device, x fastest, updated in place) with cell
+ * widths h[3] and boundary codes bc[6] (host), work = device workspace of
+ * m2c_reinit_workspace bytes; asynchronous on hip_stream.  M2C_ERR_ARG for
+ * invalid sizes, widths, boundary codes (periodic must pair up), iters < 0,
+ * band < 0, or null pointers when iters > 0. */
+int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], const int32_t bc[6], double* phi,
+                     void* work, int32_t iters, double band, void* hip_stream);
+
 /* ---- general-EOS exact Riemann problems (device pointers, given stream) --
  * The two-material Riemann problem of eq. 1DRiemannProblem with its own
  * equation of state p = p(rho, e) on each side (section "Equations of

@@ -33,7 +33,7 @@ EXPORTS = [
     "m2c_batch_get_stats", "m2c_batch_set_tile", "m2c_batch_get_tile", "m2c_batch_autotune",
     "m2c_train_opts_default", "m2c_mlp_create", "m2c_mlp_destroy", "m2c_mlp_get_params", "m2c_mlp_features",
     "m2c_mlp_forward", "m2c_mlp_grad", "m2c_mlp_train", "m2c_riemann_solve_learned", "m2c_set_guess",
-    "m2c_riemann_solve_eos", "m2c_eos_eval",
+    "m2c_riemann_solve_eos", "m2c_eos_eval", "m2c_reinit", "m2c_reinit_workspace", "m2c_reinit_field",
 ]
 _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
               "m2c_batch_last_error", "m2c_train_opts_default", "m2c_mlp_destroy")
@@ -161,6 +161,9 @@ def _declare(L):
     L.m2c_set_guess.argtypes = [vp, vp]
     L.m2c_riemann_solve_eos.argtypes = [i64, vp, vp, i32, vp, d, i32, d, vp, vp, vp]
     L.m2c_eos_eval.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp, vp]
+    L.m2c_reinit.argtypes = [vp, i32, d]
+    L.m2c_reinit_workspace.argtypes = [i32, i32, i32, C.POINTER(i64)]
+    L.m2c_reinit_field.argtypes = [i32, i32, i32, vp, vp, vp, vp, i32, d, vp]
     for name in EXPORTS:
         if name not in _NO_STATUS:
             getattr(L, name).restype = C.c_int
@@ -294,6 +297,13 @@ class Sim:
     def step(self, n=1, check=True):
         t = C.c_double(0.0)
         rc = self.L.m2c_step(self.h, n, C.byref(t))
+        if check:
+            self._check(rc)
+        return rc
+
+    def reinit(self, iters, band=0.0, check=True):
+        """Level-set reinitialization of the current state (between steps)."""
+        rc = self.L.m2c_reinit(self.h, iters, band)
         if check:
             self._check(rc)
         return rc
@@ -501,6 +511,24 @@ def eos_eval(rho, e, mat, materials, stream=None):
     if rc != M2C_OK:
         raise M2CError(rc, lib().m2c_strerror(rc).decode())
     return p, c
+
+
+def reinit_field(phi, h, bc, iters, band=0.0, stream=None):
+    """Level-set reinitialization of a float64 cuda tensor phi shaped (nz,
+    ny, nx), in place; h = cell widths (x, y, z), bc = six boundary codes."""
+    import torch
+    nz, ny, nx = phi.shape
+    nbytes = C.c_int64()
+    rc = lib().m2c_reinit_workspace(nx, ny, nz, C.byref(nbytes))
+    if rc != M2C_OK:
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    work = torch.empty(int(nbytes.value), dtype=torch.uint8, device=phi.device)
+    hh = (C.c_double * 3)(*h)
+    bb = (C.c_int32 * 6)(*bc)
+    rc = lib().m2c_reinit_field(nx, ny, nz, hh, bb, _ptr(phi), _ptr(work), iters, band, _stream_of(phi, stream))
+    if rc != M2C_OK:
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return phi
 
 
 def _stream_of(t, stream):

@@ -1,0 +1,223 @@
+// k_reinit.hip -- level-set reinitialization (section "Level set method",
+// eq. reinit): pseudo-time steps of
+//     d phi / d tau + S(phi_0) (|grad phi| - 1) = 0,
+//     S(phi_0) = phi_0 / sqrt(phi_0^2 + eps^2),
+// with the upwind (Godunov) |grad phi| of one-sided differences a = D^- phi,
+// b = D^+ phi per active axis:
+//     S > 0: sum_d max(max(a_d, 0)^2, min(b_d, 0)^2)
+//     S < 0: sum_d max(min(a_d, 0)^2, max(b_d, 0)^2)
+// and forward-Euler steps dtau = 0.5 min_d h_d (Jacobi: every cell reads the
+// previous iterate).  First-layer cells (a face neighbour on the other side
+// of the zero level set, phi >= 0 counting as the non-negative side) keep
+// phi_0, which is the paper's fixed-first-layer treatment; with a narrow
+// band only cells with |phi_0| < band move.  Both are expressed as S = 0.
+//
+// Boundary images: one layer, periodic axes wrap, transmissive and wall
+// boundaries repeat the boundary cell (the zero-gradient and mirror images
+// of phi coincide for one layer).
+//
+// Work decomposition (MI355X): a 256-thread block owns a 64 x 4 tile of an
+// xy-plane and RZ consecutive planes; x is the contiguous axis, so every
+// wavefront reads one 512-byte row per plane and the x and y neighbours
+// come from the same or adjacent rows in cache.  The speed kernel also marks
+// the blocks that hold any cell with S != 0.  The iterate is kept in two
+// buffers that both start as phi_0; a frozen cell never changes, so it is
+// never written, and a block without moving cells returns at once -- a
+// narrow band costs only the blocks it touches.  Per iteration and moving
+// cell the algorithmic traffic is phi and S read, phi written: 24 bytes.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "m2c.h"
+#include "m2c_reinit.h"
+
+namespace m2c {
+namespace {
+
+constexpr int RX = 64, RY = 4, RZ = 4;
+
+__device__ __forceinline__ int image(int i, int n, int periodic)
+{
+    return i < 0 ? (periodic ? i + n : 0) : (i >= n ? (periodic ? i - n : n - 1) : i);
+}
+
+struct Tile {
+    int i, j, k0, k1;
+};
+
+__device__ __forceinline__ Tile tile_of(const ReinitGrid& g)
+{
+    const int bx = blockIdx.x % g.bx, r = blockIdx.x / g.bx;
+    const int by = r % g.by, bz = r / g.by;
+    Tile t;
+    t.i = bx * RX + (int)(threadIdx.x % RX);
+    t.j = by * RY + (int)(threadIdx.x / RX);
+    t.k0 = bz * RZ;
+    t.k1 = min(t.k0 + RZ, g.nz);
+    return t;
+}
+
+__global__ __launch_bounds__(256) void k_reinit_speed(const ReinitGrid g, const double* __restrict__ phi0,
+                                                      double eps2, double band, double* __restrict__ S,
+                                                      int32_t* __restrict__ active)
+{
+    const Tile t = tile_of(g);
+    const bool in = t.i < g.nx && t.j < g.ny;
+    int any = 0;
+    if (in) {
+        for (int k = t.k0; k < t.k1; ++k) {
+            const long long c = (long long)t.i + (long long)g.nx * (t.j + (long long)g.ny * k);
+            const double p = phi0[c];
+            const bool pos = p >= 0.0;
+            bool fl = false;
+            if (g.nx > 1) {
+                fl |= (phi0[c - t.i + image(t.i - 1, g.nx, g.per[0])] >= 0.0) != pos;
+                fl |= (phi0[c - t.i + image(t.i + 1, g.nx, g.per[0])] >= 0.0) != pos;
+            }
+            if (g.ny > 1) {
+                const long long r0 = c - (long long)g.nx * t.j;
+                fl |= (phi0[r0 + (long long)g.nx * image(t.j - 1, g.ny, g.per[1])] >= 0.0) != pos;
+                fl |= (phi0[r0 + (long long)g.nx * image(t.j + 1, g.ny, g.per[1])] >= 0.0) != pos;
+            }
+            if (g.nz > 1) {
+                const long long pl = (long long)g.nx * g.ny, r0 = c - pl * k;
+                fl |= (phi0[r0 + pl * image(k - 1, g.nz, g.per[2])] >= 0.0) != pos;
+                fl |= (phi0[r0 + pl * image(k + 1, g.nz, g.per[2])] >= 0.0) != pos;
+            }
+            double s = p / sqrt(p * p + eps2);
+            if (fl || (band > 0.0 && fabs(p) >= band)) s = 0.0;
+            S[c] = s;
+            any |= s != 0.0;
+        }
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) active[blockIdx.x] = any;
+}
+
+__global__ __launch_bounds__(256) void k_reinit_step(const ReinitGrid g, const double* __restrict__ phi,
+                                                     double* __restrict__ out, const double* __restrict__ S,
+                                                     const int32_t* __restrict__ active, double dtau)
+{
+    if (!active[blockIdx.x]) return;                  // nothing in this block moves
+    const Tile t = tile_of(g);
+    if (t.i >= g.nx || t.j >= g.ny) return;
+    const long long pl = (long long)g.nx * g.ny;
+    for (int k = t.k0; k < t.k1; ++k) {
+        const long long c = (long long)t.i + (long long)g.nx * t.j + pl * k;
+        const double s = S[c];
+        if (s == 0.0) continue;                       // frozen: both buffers hold phi_0
+        const double p = phi[c];
+        double g2 = 0.0;
+        double nb[3][2];
+        nb[0][0] = phi[c - t.i + image(t.i - 1, g.nx, g.per[0])];
+        nb[0][1] = phi[c - t.i + image(t.i + 1, g.nx, g.per[0])];
+        const long long r0 = c - (long long)g.nx * t.j;
+        nb[1][0] = phi[r0 + (long long)g.nx * image(t.j - 1, g.ny, g.per[1])];
+        nb[1][1] = phi[r0 + (long long)g.nx * image(t.j + 1, g.ny, g.per[1])];
+        const long long z0 = c - pl * k;
+        nb[2][0] = phi[z0 + pl * image(k - 1, g.nz, g.per[2])];
+        nb[2][1] = phi[z0 + pl * image(k + 1, g.nz, g.per[2])];
+        for (int d = 0; d < 3; ++d) {
+            if (!g.act[d]) continue;
+            const double a = (p - nb[d][0]) / g.h[d], b = (nb[d][1] - p) / g.h[d];
+            double q;
+            if (s > 0.0) {
+                const double u = fmax(a, 0.0), w = fmin(b, 0.0);
+                q = fmax(u * u, w * w);
+            } else {
+                const double u = fmin(a, 0.0), w = fmax(b, 0.0);
+                q = fmax(u * u, w * w);
+            }
+            g2 += q;
+        }
+        out[c] = p - dtau * s * (sqrt(g2) - 1.0);
+    }
+}
+
+}  // namespace
+
+long long reinit_blocks(const ReinitGrid& g)
+{
+    return (long long)g.bx * g.by * g.bz;
+}
+
+bool reinit_grid(int nx, int ny, int nz, const double h[3], const int32_t bc[6], ReinitGrid& g)
+{
+    if (nx < 1 || ny < 1 || nz < 1) return false;
+    if ((long long)nx * ny * nz > (1LL << 31)) return false;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    const int n[3] = {nx, ny, nz};
+    double hmin = INFINITY;
+    for (int d = 0; d < 3; ++d) {
+        if (!(h[d] > 0.0) || !isfinite(h[d])) return false;
+        for (int s = 0; s < 2; ++s)
+            if (bc[2 * d + s] < M2C_BC_TRANSMISSIVE || bc[2 * d + s] > M2C_BC_PERIODIC) return false;
+        if ((bc[2 * d] == M2C_BC_PERIODIC) != (bc[2 * d + 1] == M2C_BC_PERIODIC)) return false;
+        g.per[d] = bc[2 * d] == M2C_BC_PERIODIC;
+        g.act[d] = n[d] > 1;
+        g.h[d] = h[d];
+        if (g.act[d]) hmin = fmin(hmin, h[d]);
+    }
+    g.hmin = isfinite(hmin) ? hmin : fmin(h[0], fmin(h[1], h[2]));
+    g.bx = (nx + RX - 1) / RX;
+    g.by = (ny + RY - 1) / RY;
+    g.bz = (nz + RZ - 1) / RZ;
+    return true;
+}
+
+hipError_t reinit_run(const ReinitGrid& g, double* phi, double* S, double* tmp, int32_t* active, int iters,
+                      double band, hipStream_t s)
+{
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    const long long nb = reinit_blocks(g);
+    if (iters <= 0) return hipSuccess;
+    const double eps = g.hmin;                        // smallest cell width
+    hipLaunchKernelGGL(k_reinit_speed, dim3((unsigned)nb), dim3(256), 0, s, g, phi, eps * eps, band, S, active);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(tmp, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    const double dtau = 0.5 * g.hmin;
+    for (int it = 0; it < iters; ++it) {
+        const double* src = (it & 1) ? tmp : phi;
+        double* dst = (it & 1) ? phi : tmp;
+        hipLaunchKernelGGL(k_reinit_step, dim3((unsigned)nb), dim3(256), 0, s, g, src, dst, S, active, dtau);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (iters & 1) e = hipMemcpyAsync(phi, tmp, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return e;
+}
+
+}  // namespace m2c
+
+using namespace m2c;
+
+extern "C" int m2c_reinit_workspace(int32_t nx, int32_t ny, int32_t nz, int64_t* bytes)
+{
+    const double h[3] = {1.0, 1.0, 1.0};
+    const int32_t bc[6] = {0, 0, 0, 0, 0, 0};
+    ReinitGrid g;
+    if (!bytes || !reinit_grid(nx, ny, nz, h, bc, g)) return M2C_ERR_ARG;
+    *bytes = reinit_workspace_bytes(g);
+    return M2C_OK;
+}
+
+extern "C" int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], const int32_t bc[6],
+                                double* phi, void* work, int32_t iters, double band, void* hip_stream)
+{
+    ReinitGrid g;
+    if (!h || !bc || !reinit_grid(nx, ny, nz, h, bc, g)) return M2C_ERR_ARG;
+    if (iters < 0 || !(band >= 0.0) || !isfinite(band)) return M2C_ERR_ARG;
+    if (iters == 0) return M2C_OK;
+    if (!phi || !work) return M2C_ERR_ARG;
+    const long long N = (long long)nx * ny * nz;
+    double* S = (double*)work;
+    double* tmp = S + N;
+    int32_t* active = (int32_t*)(tmp + N);
+    return reinit_run(g, phi, S, tmp, active, iters, band, (hipStream_t)hip_stream) == hipSuccess ? M2C_OK
+                                                                                                  : M2C_ERR_DEVICE;
+}

@@ -23,6 +23,7 @@
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
 #include "m2c_mlp.h"
+#include "m2c_reinit.h"
 
 using namespace m2c;
 
@@ -602,6 +603,23 @@ int m2c_set_conserved(m2c_ctx* c, const double* w6)
 }
 
 int m2c_step(m2c_ctx* c, int32_t nsteps, double* t_out) { return run_steps(c, nsteps, 0.0, t_out); }
+
+int m2c_reinit(m2c_ctx* c, int32_t iters, double band)
+{
+    if (!c) return M2C_ERR_ARG;
+    if (iters < 0 || !(band >= 0.0) || !std::isfinite(band))
+        return set_err(c, M2C_ERR_ARG, "iters must be >= 0 and band >= 0");
+    if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
+    if (iters == 0) return M2C_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    ReinitGrid g;
+    if (!reinit_grid(c->g.nx, c->g.ny, c->g.nz, c->g.h, c->cfg.bc, g)) return set_err(c, M2C_ERR_ARG, "grid");
+    // the stage buffer is free between steps: S, the second iterate, block flags
+    const long long N = c->g.N;
+    double* phi = c->W[c->cur] + 5 * N;
+    HIPCHK(c, reinit_run(g, phi, c->W1, c->W1 + N, (int32_t*)(c->W1 + 2 * N), iters, band, c->stream));
+    return M2C_OK;
+}
 
 int m2c_step_dt(m2c_ctx* c, int32_t nsteps, double dt, double* t_out)
 {

@@ -1,0 +1,30 @@
+// m2c_reinit.h -- level-set reinitialization launch interface (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace m2c {
+
+struct ReinitGrid {
+    int nx, ny, nz;
+    int per[3];                    // axis is periodic
+    int act[3];                    // axis has more than one cell
+    double h[3];
+    double hmin;                   // smallest width over the active axes
+    int bx, by, bz;                // blocks per axis (64 x 4 x 4 cells each)
+};
+
+// false for invalid sizes, widths or boundary codes (periodic must pair up)
+bool reinit_grid(int nx, int ny, int nz, const double h[3], const int32_t bc[6], ReinitGrid& g);
+long long reinit_blocks(const ReinitGrid& g);
+// workspace: S [N] and the second iterate [N] (FP64), block flags [blocks] (int32)
+inline long long reinit_workspace_bytes(const ReinitGrid& g)
+{
+    const long long N = (long long)g.nx * g.ny * g.nz;
+    return 16 * N + 4 * reinit_blocks(g);
+}
+// iters pseudo-time steps on phi (device, in place) with the given workspace
+hipError_t reinit_run(const ReinitGrid& g, double* phi, double* S, double* tmp, int32_t* active, int iters,
+                      double band, hipStream_t s);
+
+}  // namespace m2c

@@ -184,6 +184,38 @@ def test_riemann_eos_argument_checks_without_gpu(case, ok):
         assert (rc == m.M2C_OK) == ok, (case, rc)
 
 
+@pytest.mark.parametrize("case,ok", [("valid", True), ("nx0", False), ("h0", False), ("bc", False),
+                                     ("unpaired", False), ("iters", False), ("band", False), ("null", False)])
+def test_reinit_argument_checks_without_gpu(case, ok):
+    """m2c_reinit_workspace / m2c_reinit_field check sizes, widths, boundary
+    codes and counts before any device call (iters = 0 returns after them)."""
+    import paper_2508_16387_amd as m
+    n, h, bc, iters, band = [16, 8, 4], [0.1, 0.1, 0.2], [0, 1, 2, 2, 0, 0], 0, 0.0
+    if case == "nx0":
+        n[0] = 0
+    elif case == "h0":
+        h[1] = 0.0
+    elif case == "bc":
+        bc[0] = 5
+    elif case == "unpaired":
+        bc[2] = 0
+    elif case == "iters":
+        iters = -1
+    elif case == "band":
+        band = -1.0
+    elif case == "null":
+        iters = 3                      # nonzero steps need phi and work
+    b = C.c_int64()
+    rcw = m.lib().m2c_reinit_workspace(n[0], n[1], n[2], C.byref(b))
+    assert (rcw == m.M2C_OK) == (case != "nx0")
+    if rcw == m.M2C_OK:
+        blocks = -(-n[0] // 64) * -(-n[1] // 4) * -(-n[2] // 4)
+        assert b.value == 16 * n[0] * n[1] * n[2] + 4 * blocks
+    rc = m.lib().m2c_reinit_field(n[0], n[1], n[2], (C.c_double * 3)(*h), (C.c_int32 * 6)(*bc), None, None,
+                                  iters, band, None)
+    assert (rc == m.M2C_OK) == ok, (case, rc)
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Without the built HIP library the package raises instead of falling
     back to anything else (checked in a fresh interpreter)."""
