@@ -208,6 +208,35 @@ def general_eos_standalone(m2c, torch, n=1 << 20):
     return res
 
 
+def reinit_form(m2c, torch, problem, iters=100):
+    """Level-set reinitialization of the benchmark's level set: pseudo-time
+    steps per second over the whole grid and in a narrow band of six cells,
+    with the HBM rate of the algorithmic 24 bytes (phi and S read, phi
+    written) per moving cell and step."""
+    nx, ny, nz = problem.n
+    N = nx * ny * nz
+    h, bc = problem.dx(), problem.bc
+    phi0 = torch.tensor(problem.prim[5], dtype=torch.float64, device="cuda").contiguous()
+    # a level set far from a distance: the signed distance stretched by 3
+    # on the positive side
+    phi0 = torch.where(phi0 > 0, 3.0 * phi0, phi0)
+    m2c.reinit_field(phi0.clone(), h, bc, 4)
+    torch.cuda.synchronize()
+    res = {"grid": [nx, ny, nz], "iters": iters}
+    for name, band in (("full", 0.0), ("band_6h", 6.0 * min(h))):
+        moving = int(((phi0.abs() < band) if band > 0 else torch.ones_like(phi0, dtype=torch.bool)).sum())
+        t = phi0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m2c.reinit_field(t, h, bc, iters, band)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        res[name] = {"ms_per_iter": T / iters * 1e3, "cell_iters_per_s": N * iters / T,
+                     "moving_fraction": moving / N, "hbm_gbs_algorithmic": 24.0 * moving * iters / T / 1e9,
+                     "hbm_frac": 24.0 * moving * iters / T / 8e12}
+    return res
+
+
 def host_round_trip(m2c, torch, problem, steps):
     """The same FP64 run with the state handed over in host memory: upload
     (primitive -> conservative on the device), `steps` steps, download.  A
@@ -415,6 +444,7 @@ def main():
             "fiver_standalone": fiver_standalone(m2c, torch),
             "learned_guess_standalone": learned_standalone(m2c, torch),
             "general_eos_riemann": general_eos_standalone(m2c, torch),
+            "reinit_128": reinit_form(m2c, torch, p),
             "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
         }
         if args.cloud_steps > 0:

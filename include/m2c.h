@@ -323,18 +323,20 @@ int m2c_set_guess(m2c_ctx* ctx, const m2c_mlp* m);
  * periodic axes wrap, transmissive and wall sides repeat the boundary cell.
  * FP64, deterministic (Jacobi iterates). */
 /* On the context's current level set, between steps (stream-ordered on the
- * context's stream; uses the context's stage buffer as workspace).
+ * context's stream, which it synchronises once; uses the context's stage
+ * buffer as workspace).
  * M2C_ERR_STATE before a state is set; M2C_ERR_ARG for iters < 0 or
  * band < 0. */
 int m2c_reinit(m2c_ctx* ctx, int32_t iters, double band);
 /* Workspace bytes m2c_reinit_field needs for an nx x ny x nz grid:
- * 16 N + 4 ceil(nx/64) ceil(ny/4) ceil(nz/4). */
+ * 16 N + 4 (1 + ceil(nx/64) ceil(ny/4) nz). */
 int m2c_reinit_workspace(int32_t nx, int32_t ny, int32_t nz, int64_t* bytes);
 /* On a level set phi [N] (device, x fastest, updated in place) with cell
  * widths h[3] and boundary codes bc[6] (host), work = device workspace of
  * m2c_reinit_workspace bytes; asynchronous on hip_stream.  M2C_ERR_ARG for
  * invalid sizes, widths, boundary codes (periodic must pair up), iters < 0,
- * band < 0, or null pointers when iters > 0. */
+ * band < 0, or null pointers when iters > 0.  Synchronises hip_stream once
+ * (after the setup kernel, to size the step launches). */
 int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], const int32_t bc[6], double* phi,
                      void* work, int32_t iters, double band, void* hip_stream);
 

@@ -17,14 +17,16 @@
 // of phi coincide for one layer).
 //
 // Work decomposition (MI355X): a 256-thread block owns a 64 x 4 tile of an
-// xy-plane and RZ consecutive planes; x is the contiguous axis, so every
+// xy-plane and a few consecutive planes; x is the contiguous axis, so every
 // wavefront reads one 512-byte row per plane and the x and y neighbours
-// come from the same or adjacent rows in cache.  The speed kernel also marks
-// the blocks that hold any cell with S != 0.  The iterate is kept in two
-// buffers that both start as phi_0; a frozen cell never changes, so it is
-// never written, and a block without moving cells returns at once -- a
-// narrow band costs only the blocks it touches.  Per iteration and moving
-// cell the algorithmic traffic is phi and S read, phi written: 24 bytes.
+// come from the same or adjacent rows in cache, while the column's z
+// neighbours stay in a three-plane register window.  The speed kernel
+// appends the blocks that hold any cell with S != 0 to a list, and the step
+// kernel runs on that list only.  The iterate is kept in two buffers that
+// both start as phi_0; a frozen cell never changes, so it is never written
+// -- a narrow band costs only the blocks it touches.  Per iteration and
+// moving cell the algorithmic traffic is phi and S read, phi written: 24
+// bytes.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -35,7 +37,13 @@
 namespace m2c {
 namespace {
 
-constexpr int RX = 64, RY = 4, RZ = 4;
+constexpr int RX = 64, RY = 4;
+// planes per block: 4 over the whole grid (fewer z reloads); 1 in a narrow
+// band, where few blocks move and the serial plane loop of each would be
+// exposed latency (measured at 128^3: whole grid 20.0 us per step with 4
+// planes against 23.8 with 1; band of six cells 5.4 us with 1 against 7.5
+// with 4 and 12.1 with 8)
+constexpr int RZ_FULL = 4, RZ_BAND = 1;
 
 __device__ __forceinline__ int image(int i, int n, int periodic)
 {
@@ -46,23 +54,23 @@ struct Tile {
     int i, j, k0, k1;
 };
 
-__device__ __forceinline__ Tile tile_of(const ReinitGrid& g)
+__device__ __forceinline__ Tile tile_of(const ReinitGrid& g, int b)
 {
-    const int bx = blockIdx.x % g.bx, r = blockIdx.x / g.bx;
+    const int bx = b % g.bx, r = b / g.bx;
     const int by = r % g.by, bz = r / g.by;
     Tile t;
     t.i = bx * RX + (int)(threadIdx.x % RX);
     t.j = by * RY + (int)(threadIdx.x / RX);
-    t.k0 = bz * RZ;
-    t.k1 = min(t.k0 + RZ, g.nz);
+    t.k0 = bz * g.rz;
+    t.k1 = min(t.k0 + g.rz, g.nz);
     return t;
 }
 
 __global__ __launch_bounds__(256) void k_reinit_speed(const ReinitGrid g, const double* __restrict__ phi0,
                                                       double eps2, double band, double* __restrict__ S,
-                                                      int32_t* __restrict__ active)
+                                                      int32_t* __restrict__ list)
 {
-    const Tile t = tile_of(g);
+    const Tile t = tile_of(g, blockIdx.x);
     const bool in = t.i < g.nx && t.j < g.ny;
     int any = 0;
     if (in) {
@@ -92,46 +100,56 @@ __global__ __launch_bounds__(256) void k_reinit_speed(const ReinitGrid g, const 
         }
     }
     any = __syncthreads_or(any);
-    if (threadIdx.x == 0) active[blockIdx.x] = any;
+    // list[0] counts the blocks with moving cells, list[1..] holds them
+    if (threadIdx.x == 0 && any) list[1 + atomicAdd(&list[0], 1)] = blockIdx.x;
 }
 
 __global__ __launch_bounds__(256) void k_reinit_step(const ReinitGrid g, const double* __restrict__ phi,
                                                      double* __restrict__ out, const double* __restrict__ S,
-                                                     const int32_t* __restrict__ active, double dtau)
+                                                     const int32_t* __restrict__ list, double dtau)
 {
-    if (!active[blockIdx.x]) return;                  // nothing in this block moves
-    const Tile t = tile_of(g);
+    const Tile t = tile_of(g, list[1 + blockIdx.x]);
     if (t.i >= g.nx || t.j >= g.ny) return;
     const long long pl = (long long)g.nx * g.ny;
+    const long long col = (long long)t.i + (long long)g.nx * t.j;
+    const long long xm = col - t.i + image(t.i - 1, g.nx, g.per[0]);
+    const long long xp = col - t.i + image(t.i + 1, g.nx, g.per[0]);
+    const long long row0 = col - (long long)g.nx * t.j;
+    const long long ym = row0 + (long long)g.nx * image(t.j - 1, g.ny, g.per[1]);
+    const long long yp = row0 + (long long)g.nx * image(t.j + 1, g.ny, g.per[1]);
+    // z window: phi of planes k - 1, k, k + 1 of this column
+    double pzm = phi[col + pl * image(t.k0 - 1, g.nz, g.per[2])];
+    double p = phi[col + pl * t.k0];
     for (int k = t.k0; k < t.k1; ++k) {
-        const long long c = (long long)t.i + (long long)g.nx * t.j + pl * k;
+        const double pzp = phi[col + pl * image(k + 1, g.nz, g.per[2])];
+        const long long c = col + pl * k;
         const double s = S[c];
-        if (s == 0.0) continue;                       // frozen: both buffers hold phi_0
-        const double p = phi[c];
-        double g2 = 0.0;
-        double nb[3][2];
-        nb[0][0] = phi[c - t.i + image(t.i - 1, g.nx, g.per[0])];
-        nb[0][1] = phi[c - t.i + image(t.i + 1, g.nx, g.per[0])];
-        const long long r0 = c - (long long)g.nx * t.j;
-        nb[1][0] = phi[r0 + (long long)g.nx * image(t.j - 1, g.ny, g.per[1])];
-        nb[1][1] = phi[r0 + (long long)g.nx * image(t.j + 1, g.ny, g.per[1])];
-        const long long z0 = c - pl * k;
-        nb[2][0] = phi[z0 + pl * image(k - 1, g.nz, g.per[2])];
-        nb[2][1] = phi[z0 + pl * image(k + 1, g.nz, g.per[2])];
-        for (int d = 0; d < 3; ++d) {
-            if (!g.act[d]) continue;
-            const double a = (p - nb[d][0]) / g.h[d], b = (nb[d][1] - p) / g.h[d];
-            double q;
-            if (s > 0.0) {
-                const double u = fmax(a, 0.0), w = fmin(b, 0.0);
-                q = fmax(u * u, w * w);
-            } else {
-                const double u = fmin(a, 0.0), w = fmax(b, 0.0);
-                q = fmax(u * u, w * w);
+        if (s != 0.0) {                               // frozen: both buffers hold phi_0
+            double nb[3][2];
+            nb[0][0] = phi[xm + pl * k];
+            nb[0][1] = phi[xp + pl * k];
+            nb[1][0] = phi[ym + pl * k];
+            nb[1][1] = phi[yp + pl * k];
+            nb[2][0] = pzm;
+            nb[2][1] = pzp;
+            double g2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                if (!g.act[d]) continue;
+                const double a = (p - nb[d][0]) / g.h[d], b = (nb[d][1] - p) / g.h[d];
+                double q;
+                if (s > 0.0) {
+                    const double u = fmax(a, 0.0), w = fmin(b, 0.0);
+                    q = fmax(u * u, w * w);
+                } else {
+                    const double u = fmin(a, 0.0), w = fmax(b, 0.0);
+                    q = fmax(u * u, w * w);
+                }
+                g2 += q;
             }
-            g2 += q;
+            out[c] = p - dtau * s * (sqrt(g2) - 1.0);
         }
-        out[c] = p - dtau * s * (sqrt(g2) - 1.0);
+        pzm = p;
+        p = pzp;
     }
 }
 
@@ -164,31 +182,43 @@ bool reinit_grid(int nx, int ny, int nz, const double h[3], const int32_t bc[6],
     g.hmin = isfinite(hmin) ? hmin : fmin(h[0], fmin(h[1], h[2]));
     g.bx = (nx + RX - 1) / RX;
     g.by = (ny + RY - 1) / RY;
-    g.bz = (nz + RZ - 1) / RZ;
+    g.rz = RZ_FULL;
+    g.bz = (nz + g.rz - 1) / g.rz;
     return true;
 }
 
-hipError_t reinit_run(const ReinitGrid& g, double* phi, double* S, double* tmp, int32_t* active, int iters,
+hipError_t reinit_run(const ReinitGrid& g0, double* phi, double* S, double* tmp, int32_t* list, int iters,
                       double band, hipStream_t s)
 {
+    ReinitGrid g = g0;
+    g.rz = band > 0.0 ? RZ_BAND : RZ_FULL;
+    g.bz = (g.nz + g.rz - 1) / g.rz;
     const long long N = (long long)g.nx * g.ny * g.nz;
     const long long nb = reinit_blocks(g);
     if (iters <= 0) return hipSuccess;
     const double eps = g.hmin;                        // smallest cell width
-    hipLaunchKernelGGL(k_reinit_speed, dim3((unsigned)nb), dim3(256), 0, s, g, phi, eps * eps, band, S, active);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipMemsetAsync(list, 0, sizeof(int32_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reinit_speed, dim3((unsigned)nb), dim3(256), 0, s, g, phi, eps * eps, band, S, list);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(tmp, phi, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
+    // the number of moving blocks sizes every step launch
+    int32_t nact = 0;
+    e = hipMemcpyAsync(&nact, list, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (nact < 0 || nact > nb) return hipErrorUnknown;
     const double dtau = 0.5 * g.hmin;
-    for (int it = 0; it < iters; ++it) {
+    for (int it = 0; it < iters && nact > 0; ++it) {
         const double* src = (it & 1) ? tmp : phi;
         double* dst = (it & 1) ? phi : tmp;
-        hipLaunchKernelGGL(k_reinit_step, dim3((unsigned)nb), dim3(256), 0, s, g, src, dst, S, active, dtau);
+        hipLaunchKernelGGL(k_reinit_step, dim3((unsigned)nact), dim3(256), 0, s, g, src, dst, S, list, dtau);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (iters & 1) e = hipMemcpyAsync(phi, tmp, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if ((iters & 1) && nact > 0) e = hipMemcpyAsync(phi, tmp, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     return e;
 }
 

@@ -209,8 +209,8 @@ def test_reinit_argument_checks_without_gpu(case, ok):
     rcw = m.lib().m2c_reinit_workspace(n[0], n[1], n[2], C.byref(b))
     assert (rcw == m.M2C_OK) == (case != "nx0")
     if rcw == m.M2C_OK:
-        blocks = -(-n[0] // 64) * -(-n[1] // 4) * -(-n[2] // 4)
-        assert b.value == 16 * n[0] * n[1] * n[2] + 4 * blocks
+        blocks = -(-n[0] // 64) * -(-n[1] // 4) * n[2]
+        assert b.value == 16 * n[0] * n[1] * n[2] + 4 * (1 + blocks)
     rc = m.lib().m2c_reinit_field(n[0], n[1], n[2], (C.c_double * 3)(*h), (C.c_int32 * 6)(*bc), None, None,
                                   iters, band, None)
     assert (rc == m.M2C_OK) == ok, (case, rc)
