@@ -103,6 +103,10 @@ typedef struct m2c_config {
     int32_t limiter_k;          /* Van Albada exponent: even, 2..8 (default 2;
                                    odd k has a pole at theta = -1)              */
     int32_t flux;               /* M2C_FLUX_* (default HLLC; batches: HLLC only) */
+    double ls_band;             /* > 0: narrow band -- the level set is advanced
+                                   only where the stage-input |phi| < ls_band and
+                                   held elsewhere (section "Level set method");
+                                   0 (default): whole grid; batches: 0 only     */
 } m2c_config;
 
 /* Counters and timings since m2c_create (or the last m2c_reset_stats). */

@@ -67,7 +67,7 @@ class Cfg(C.Structure):
                 ("bc", C.c_int32 * 6), ("alpha", C.c_double), ("rk_order", C.c_int32),
                 ("cfl", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double),
                 ("maxit", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_int32),
-                ("flux", C.c_int32)]
+                ("flux", C.c_int32), ("ls_band", C.c_double)]
 
 
 LIM_MC, LIM_VA, LIM_VA_MOD = 0, 1, 2
@@ -139,7 +139,7 @@ def lib():
 
 
 def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_MC, limiter_k=2,
-             flux=FLUX_HLLC):
+             flux=FLUX_HLLC, ls_band=0.0):
     c = Cfg()
     c.nx, c.ny, c.nz = problem.n
     for d in range(3):
@@ -159,6 +159,7 @@ def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_M
     c.limiter = limiter
     c.limiter_k = limiter_k
     c.flux = flux
+    c.ls_band = ls_band
     return c
 
 

@@ -677,6 +677,10 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
     for (int64_t c = 0; c < s->N; ++c) {
         for (int v = 0; v < 5; ++v) R[v][c] = -R[v][c];
         L[c] = -L[c];
+        /* narrow band (section "Level set method" of the numerical methods):
+         * the level-set equation is solved only where the stage-input |phi|
+         * is below the bandwidth; elsewhere phi is held */
+        if (s->c.ls_band > 0.0 && fabs(phi[c]) >= s->c.ls_band) L[c] = 0.0;
     }
     return rc;
 }

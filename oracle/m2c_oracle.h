@@ -49,6 +49,7 @@ typedef struct {
     int32_t limiter;          /* ORA_LIM_MC, ORA_LIM_VA, ORA_LIM_VA_MOD            */
     int32_t limiter_k;        /* Van Albada exponent k                           */
     int32_t flux;             /* ORA_FLUX_HLLC, ORA_FLUX_LLF                     */
+    double ls_band;           /* > 0: level set advanced only where |phi| < band */
 } ora_cfg;
 
 enum { ORA_LIM_MC = 0, ORA_LIM_VA = 1, ORA_LIM_VA_MOD = 2 };

@@ -48,7 +48,8 @@ class Config(C.Structure):
                 ("dt_fixed", C.c_double), ("precision", C.c_int32), ("guess", C.c_int32),
                 ("riemann_rtol", C.c_double), ("riemann_maxit", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
-                ("limiter", C.c_int32), ("limiter_k", C.c_int32), ("flux", C.c_int32)]
+                ("limiter", C.c_int32), ("limiter_k", C.c_int32), ("flux", C.c_int32),
+                ("ls_band", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -194,7 +195,7 @@ def config_default() -> Config:
 
 
 def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None,
-               rk_order=2, limiter=M2C_LIM_MC, limiter_k=2, flux=M2C_FLUX_HLLC) -> Config:
+               rk_order=2, limiter=M2C_LIM_MC, limiter_k=2, flux=M2C_FLUX_HLLC, ls_band=0.0) -> Config:
     """Configuration for a problem description with attributes n, lo, hi,
     gamma, pc, bc, cfl, dt_fixed (as built by the ``workloads`` module)."""
     c = config_default()
@@ -215,6 +216,7 @@ def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2
     c.limiter = limiter
     c.limiter_k = limiter_k
     c.flux = flux
+    c.ls_band = ls_band
     if tile is not None:
         c.tile_x, c.tile_y, c.tile_z = tile
     return c

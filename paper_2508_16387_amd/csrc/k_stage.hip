@@ -85,7 +85,8 @@ bool stage_tile_supported(int tx, int ty)
 
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s)
 {
-    if (a.g.limiter != LIM_MC || a.g.flux != FLUX_HLLC) return launch_stage_opts(stage, mixed, tx, ty, a, s);
+    if (a.g.limiter != LIM_MC || a.g.flux != FLUX_HLLC || a.g.ls_band > 0.0)
+        return launch_stage_opts(stage, mixed, tx, ty, a, s);
 #define M2C_TILE(TX_, TY_)                                                              \
     if (tx == TX_ && ty == TY_)                                                         \
         return mixed ? launch_tile<TX_, TY_, float, false>(stage, a, s)                \

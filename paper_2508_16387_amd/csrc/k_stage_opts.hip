@@ -1,6 +1,7 @@
-// k_stage_opts.hip -- the stage kernels with the limiter and numerical flux
-// taken from the configuration at run time (MC, Van Albada or modified Van
-// Albada slopes; HLLC or local Lax-Friedrichs fluxes).  Kept apart from the
+// k_stage_opts.hip -- the stage kernels with the limiter, numerical flux and
+// level-set band taken from the configuration at run time (MC, Van Albada or
+// modified Van Albada slopes; HLLC or local Lax-Friedrichs fluxes; whole-grid
+// or narrow-band level set).  Kept apart from the
 // default kernels, whose register allocation the run-time choice would
 // otherwise enlarge.
 #include "m2c_stage.h"

@@ -117,6 +117,7 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
     if (c->limiter != M2C_LIM_MC && (c->limiter_k < 2 || c->limiter_k > 8 || c->limiter_k % 2 != 0))
         return snprintf(why, n, "Van Albada exponent k must be even, 2..8"), false;
     if (c->flux != M2C_FLUX_HLLC && c->flux != M2C_FLUX_LLF) return snprintf(why, n, "bad flux"), false;
+    if (!(c->ls_band >= 0.0) || !std::isfinite(c->ls_band)) return snprintf(why, n, "ls_band must be >= 0"), false;
     if (c->rk_order < 1 || c->rk_order > 3)
         return snprintf(why, n, "rk_order must be 1 (forward Euler), 2 or 3 (TVD-RK)"), false;
     if (!(c->dt_fixed > 0.0) && !(c->cfl > 0.0)) return snprintf(why, n, "cfl must be > 0"), false;
@@ -161,6 +162,7 @@ void fill_grid(Grid& g, const m2c_config& c)
     g.limiter = c.limiter;
     g.limk = c.limiter_k;
     g.flux = c.flux;
+    g.ls_band = c.ls_band;
 }
 
 // Reset the error state of the device scalars (host mirror -> device).
@@ -435,6 +437,7 @@ void m2c_config_default(m2c_config* c)
     c->limiter = M2C_LIM_MC;
     c->limiter_k = 2;
     c->flux = M2C_FLUX_HLLC;
+    c->ls_band = 0.0;
 }
 
 const char* m2c_strerror(int status) { return status_name(status); }

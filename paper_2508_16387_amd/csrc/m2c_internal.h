@@ -46,6 +46,7 @@ struct Grid {
     int rk_stages;                 // Runge-Kutta stages per step (1, 2 or 3)
     int limiter, limk;             // slope limiter (M2C_LIM_*) and Van Albada exponent
     int flux;                      // numerical flux (M2C_FLUX_*)
+    double ls_band;                // > 0: level set advanced only where |phi| < ls_band
 };
 
 // Device buffers of one simulation.

@@ -64,10 +64,10 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 // One tile (TX x TY columns, a.kz planes) of one stage.  Called once per
 // block by the single-grid kernel and once per work item by the persistent
 // batched kernel; the whole block takes part.  LM: material parameters from
-// an LDS table (see below).  OPTS: limiter and flux as configured (Van
-// Albada, local Lax-Friedrichs); otherwise MC and HLLC, fixed at compile
-// time so that the default kernels carry neither the code nor the registers
-// of the other options.
+// an LDS table (see below).  OPTS: limiter, flux and level-set band as
+// configured (Van Albada, local Lax-Friedrichs, narrow band); otherwise MC,
+// HLLC and the whole grid, fixed at compile time so that the default kernels
+// carry neither the code nor the registers of the other options.
 template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
@@ -518,6 +518,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (xact) Ls += ls_term(Vc[0], sp[-2], sp[-1], sp[0], sp[1], sp[2], G.rh6[0]);
             if (yact) Ls += ls_term(Vc[1], sp[-2 * LX], sp[-LX], sp[0], sp[LX], sp[2 * LX], G.rh6[1]);
             if (zact) Ls += ls_term(Vc[2], PH[0], PH[1], PH[2], PH[3], PH[4], G.rh6[2]);
+            // narrow band: phi is held where the stage-input |phi| reaches the bandwidth
+            if (OPTS && G.ls_band > 0.0 && fabs(PH[2]) >= G.ls_band) Ls = 0.0;
 
             double wn[6];
             if (!BLEND) {

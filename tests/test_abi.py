@@ -82,6 +82,8 @@ def test_create_rejects_bad_config_without_gpu():
     ("va_k", 10, False),
     ("flux", 1, True),                      # local Lax-Friedrichs
     ("flux", 2, False),
+    ("ls_band", 0.05, True),
+    ("ls_band", -1.0, False),
     ("cfl", 0.0, False),
     ("precision", 7, False),
     ("riemann_rtol", 0.0, False),
@@ -119,7 +121,8 @@ def test_validate_config_without_gpu(field, value, ok):
     assert (rc == m.M2C_OK) == ok, (field, value, rc)
 
 
-@pytest.mark.parametrize("field,value", [("rk_order", 3), ("limiter", 1), ("flux", 1), ("precision", None)])
+@pytest.mark.parametrize("field,value", [("rk_order", 3), ("limiter", 1), ("flux", 1), ("ls_band", 0.1),
+                                         ("precision", None)])
 def test_batch_create_rejects_unsupported_without_gpu(field, value):
     """The batched kernels are TVD-RK2 with MC and HLLC and one precision;
     anything else is refused before any device call."""

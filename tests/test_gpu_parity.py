@@ -237,6 +237,25 @@ def test_limiter_and_flux_options(m2c, lim, k, flux, alpha, order, tile, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_narrow_band_level_set(m2c, prec):
+    """Level set advanced only where |phi| < band (section "Level set
+    method"): parity with the oracle, phi held outside the band."""
+    p = W.shock_bubble(5, nxyz=(27, 22, 19), radius=0.25, p_shock=1e9, shock_x=0.3)
+    band = 3.0 * min(p.dx())
+    o = oracle.OracleSim(p, ls_band=band)
+    g = m2c.Sim(m2c.config_for(p, precision=prec, ls_band=band), p.prim)
+    assert g.step(20) == 0 and o.step(20) == 0
+    e = compare_runs(g, o, p)
+    print("band", prec, e)
+    assert e["id_mismatch"] == 0
+    tol = TOL_FP64 if prec == 0 else 1e-3
+    for name in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[name] <= tol, (name, e[name])
+    out = np.abs(p.prim[5]) >= band
+    assert np.array_equal(g.get_conserved()[5][out], p.prim[5][out])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_bubble_next_to_rigid_wall(m2c, prec):
     """The paper's shock-induced collapse of a bubble near a rigid wall:
     walls on every side, bubble 0.04 from the +x wall, a 1 GPa shock; FIVER

@@ -519,6 +519,26 @@ def test_oracle_pin(name, oracle_lib):
     CHECKS[name](oracle_lib)
 
 
+def test_narrow_band_level_set():
+    """Narrow band (section "Level set method"): phi is held outside the band
+    and the run equals the whole-grid run when the band covers everything."""
+    p = W.shock_bubble(5, nxyz=(20, 18, 16), radius=0.25, p_shock=1e9, shock_x=0.3)
+    band = 2.5 * min(p.dx())
+    full = oracle.OracleSim(p)
+    wide = oracle.OracleSim(p, ls_band=1e9)
+    narrow = oracle.OracleSim(p, ls_band=band)
+    for s in (full, wide, narrow):
+        assert s.step(12) == 0
+    assert np.array_equal(full.cons(), wide.cons())
+    phi0 = p.prim[5]
+    out = np.abs(phi0) >= band
+    wn, wf = narrow.cons(), full.cons()
+    assert out.any() and np.array_equal(wn[5][out], phi0[out])
+    assert not np.array_equal(wf[5][out], phi0[out])          # the whole-grid run moves them
+    inner = np.abs(phi0) < band
+    assert not np.array_equal(wn[5][inner], phi0[inner])
+
+
 # ------------------------------------------------------ planted mistakes ---
 # (source fragment, replacement) pairs: each plants a plausible mistake in a
 # private copy of the oracle; the pins must catch every one.
