@@ -17,10 +17,11 @@
 // of phi coincide for one layer).
 //
 // Work decomposition (MI355X): a 256-thread block owns a 64 x 4 tile of an
-// xy-plane and a few consecutive planes; x is the contiguous axis, so every
-// wavefront reads one 512-byte row per plane and the x and y neighbours
-// come from the same or adjacent rows in cache, while the column's z
-// neighbours stay in a three-plane register window.  The speed kernel
+// xy-plane and a few consecutive planes; x is the contiguous axis and every
+// wavefront holds one 512-byte row per plane.  A cell's x neighbours come
+// from the adjacent lanes (shuffles), its y neighbours from the other rows
+// of the block through LDS, its z neighbours from a three-plane register
+// window; only the tile's edge lanes and rows load halo values.  The speed kernel
 // appends the blocks that hold any cell with S != 0 to a list, and the step
 // kernel runs on that list only.  The iterate is kept in two buffers that
 // both start as phi_0; a frozen cell never changes, so it is never written
@@ -38,11 +39,10 @@ namespace m2c {
 namespace {
 
 constexpr int RX = 64, RY = 4;
-// planes per block: 4 over the whole grid (fewer z reloads); 1 in a narrow
-// band, where few blocks move and the serial plane loop of each would be
-// exposed latency (measured at 128^3: whole grid 20.0 us per step with 4
-// planes against 23.8 with 1; band of six cells 5.4 us with 1 against 7.5
-// with 4 and 12.1 with 8)
+// planes per block: 4 over the whole grid; 1 in a narrow band, where few
+// blocks move and the serial plane loop of each would be exposed latency
+// (measured at 128^3: whole grid 15.5 us per step with 4 planes against
+// 17.3 with 8; band of six cells 5.3 us with 1 against 7.5 with 4)
 constexpr int RZ_FULL = 4, RZ_BAND = 1;
 
 __device__ __forceinline__ int image(int i, int n, int periodic)
@@ -104,49 +104,63 @@ __global__ __launch_bounds__(256) void k_reinit_speed(const ReinitGrid g, const 
     if (threadIdx.x == 0 && any) list[1 + atomicAdd(&list[0], 1)] = blockIdx.x;
 }
 
+// LIST: the block runs tile list[1 + blockIdx.x] (narrow band); otherwise
+// the tile of the 3D block index (whole grid, no integer division)
+template <bool LIST>
 __global__ __launch_bounds__(256) void k_reinit_step(const ReinitGrid g, const double* __restrict__ phi,
                                                      double* __restrict__ out, const double* __restrict__ S,
                                                      const int32_t* __restrict__ list, double dtau)
 {
-    const Tile t = tile_of(g, list[1 + blockIdx.x]);
-    if (t.i >= g.nx || t.j >= g.ny) return;
-    const long long pl = (long long)g.nx * g.ny;
-    const long long col = (long long)t.i + (long long)g.nx * t.j;
-    const long long xm = col - t.i + image(t.i - 1, g.nx, g.per[0]);
-    const long long xp = col - t.i + image(t.i + 1, g.nx, g.per[0]);
-    const long long row0 = col - (long long)g.nx * t.j;
-    const long long ym = row0 + (long long)g.nx * image(t.j - 1, g.ny, g.per[1]);
-    const long long yp = row0 + (long long)g.nx * image(t.j + 1, g.ny, g.per[1]);
-    // z window: phi of planes k - 1, k, k + 1 of this column
+    // one wavefront per x-row of the tile: x neighbours by lane shuffles, y
+    // neighbours through a double-buffered LDS copy of the block's four rows,
+    // z neighbours in a register window; only the tile's edges load halos.
+    // Offsets are 32-bit (grids up to 2^31 cells); the one-sided
+    // differences multiply by 1/h.
+    __shared__ double sRow[2][RY][RX];
+    Tile t;
+    if (LIST) {
+        t = tile_of(g, list[1 + blockIdx.x]);
+    } else {
+        t.i = (int)blockIdx.x * RX + (int)(threadIdx.x % RX);
+        t.j = (int)blockIdx.y * RY + (int)(threadIdx.x / RX);
+        t.k0 = (int)blockIdx.z * g.rz;
+        t.k1 = min(t.k0 + g.rz, g.nz);
+    }
+    const int lane = (int)(threadIdx.x % RX), w = (int)(threadIdx.x / RX);
+    const bool live = t.i < g.nx && t.j < g.ny;
+    const int ic = min(t.i, g.nx - 1), jc = min(t.j, g.ny - 1);      // clamped: loads stay in range
+    const uint32_t pl = (uint32_t)g.nx * (uint32_t)g.ny;
+    const uint32_t row0 = (uint32_t)g.nx * (uint32_t)jc, col = row0 + (uint32_t)ic;
+    const bool xlo = lane == 0 || ic == 0, xhi = lane == RX - 1 || ic == g.nx - 1;
+    const bool ylo = w == 0 || jc == 0, yhi = w == RY - 1 || jc == g.ny - 1;
+    const uint32_t xm = row0 + image(ic - 1, g.nx, g.per[0]), xp = row0 + image(ic + 1, g.nx, g.per[0]);
+    const uint32_t ym = (uint32_t)g.nx * image(jc - 1, g.ny, g.per[1]) + ic;
+    const uint32_t yp = (uint32_t)g.nx * image(jc + 1, g.ny, g.per[1]) + ic;
     double pzm = phi[col + pl * image(t.k0 - 1, g.nz, g.per[2])];
     double p = phi[col + pl * t.k0];
-    for (int k = t.k0; k < t.k1; ++k) {
+    int buf = 0;
+    for (int k = t.k0; k < t.k1; ++k, buf ^= 1) {
+        const uint32_t o = pl * (uint32_t)k;
         const double pzp = phi[col + pl * image(k + 1, g.nz, g.per[2])];
-        const long long c = col + pl * k;
-        const double s = S[c];
-        if (s != 0.0) {                               // frozen: both buffers hold phi_0
-            double nb[3][2];
-            nb[0][0] = phi[xm + pl * k];
-            nb[0][1] = phi[xp + pl * k];
-            nb[1][0] = phi[ym + pl * k];
-            nb[1][1] = phi[yp + pl * k];
-            nb[2][0] = pzm;
-            nb[2][1] = pzp;
+        const double s = S[col + o];
+        sRow[buf][w][lane] = p;
+        const double su = __shfl_up(p, 1), sd = __shfl_down(p, 1);
+        __syncthreads();
+        const double xa = xlo ? phi[xm + o] : su, xb = xhi ? phi[xp + o] : sd;
+        const double ya = ylo ? phi[ym + o] : sRow[buf][w - 1][lane];
+        const double yb = yhi ? phi[yp + o] : sRow[buf][w + 1][lane];
+        if (live && s != 0.0) {                       // frozen: both buffers hold phi_0
+            const bool up = s > 0.0;
+            auto term = [&](double lo, double hi, double rh) {
+                const double a = (p - lo) * rh, b = (hi - p) * rh;
+                const double u = up ? fmax(a, 0.0) : fmin(a, 0.0), v = up ? fmin(b, 0.0) : fmax(b, 0.0);
+                return fmax(u * u, v * v);
+            };
             double g2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                if (!g.act[d]) continue;
-                const double a = (p - nb[d][0]) / g.h[d], b = (nb[d][1] - p) / g.h[d];
-                double q;
-                if (s > 0.0) {
-                    const double u = fmax(a, 0.0), w = fmin(b, 0.0);
-                    q = fmax(u * u, w * w);
-                } else {
-                    const double u = fmin(a, 0.0), w = fmax(b, 0.0);
-                    q = fmax(u * u, w * w);
-                }
-                g2 += q;
-            }
-            out[c] = p - dtau * s * (sqrt(g2) - 1.0);
+            if (g.act[0]) g2 += term(xa, xb, g.rh[0]);
+            if (g.act[1]) g2 += term(ya, yb, g.rh[1]);
+            if (g.act[2]) g2 += term(pzm, pzp, g.rh[2]);
+            out[col + o] = p - dtau * s * (sqrt(g2) - 1.0);
         }
         pzm = p;
         p = pzp;
@@ -177,6 +191,7 @@ bool reinit_grid(int nx, int ny, int nz, const double h[3], const int32_t bc[6],
         g.per[d] = bc[2 * d] == M2C_BC_PERIODIC;
         g.act[d] = n[d] > 1;
         g.h[d] = h[d];
+        g.rh[d] = 1.0 / h[d];
         if (g.act[d]) hmin = fmin(hmin, h[d]);
     }
     g.hmin = isfinite(hmin) ? hmin : fmin(h[0], fmin(h[1], h[2]));
@@ -211,10 +226,17 @@ hipError_t reinit_run(const ReinitGrid& g0, double* phi, double* S, double* tmp,
     if (e != hipSuccess) return e;
     if (nact < 0 || nact > nb) return hipErrorUnknown;
     const double dtau = 0.5 * g.hmin;
+    // whole grid: a 3D launch over every tile (nearly all move); band: the list
+    const bool use_list = band > 0.0 || g.by > 65535 || g.bz > 65535;
     for (int it = 0; it < iters && nact > 0; ++it) {
         const double* src = (it & 1) ? tmp : phi;
         double* dst = (it & 1) ? phi : tmp;
-        hipLaunchKernelGGL(k_reinit_step, dim3((unsigned)nact), dim3(256), 0, s, g, src, dst, S, list, dtau);
+        if (use_list)
+            hipLaunchKernelGGL(k_reinit_step<true>, dim3((unsigned)nact), dim3(256), 0, s, g, src, dst, S, list,
+                               dtau);
+        else
+            hipLaunchKernelGGL(k_reinit_step<false>, dim3((unsigned)g.bx, (unsigned)g.by, (unsigned)g.bz),
+                               dim3(256), 0, s, g, src, dst, S, list, dtau);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

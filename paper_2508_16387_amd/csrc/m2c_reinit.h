@@ -9,7 +9,7 @@ struct ReinitGrid {
     int nx, ny, nz;
     int per[3];                    // axis is periodic
     int act[3];                    // axis has more than one cell
-    double h[3];
+    double h[3], rh[3];            // width, 1/width
     double hmin;                   // smallest width over the active axes
     int rz;                        // planes per block
     int bx, by, bz;                // blocks per axis (64 x 4 x rz cells each)
