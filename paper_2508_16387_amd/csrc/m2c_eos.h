@@ -197,6 +197,7 @@ struct Side {
     double fl;                     // pressure floor of the material
     double s, y, f;                // current point of the isentrope walk
     double vh;                     // last Hugoniot volume (0: none yet)
+    double jC;                     // JWL: constant of the isentrope through K
 };
 
 struct Wave {
@@ -327,9 +328,111 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
     return false;
 }
 
+// JWL isentropes in closed form: along the isentrope through K
+//   p_s(v) = A_1 exp(-a_1 v) + A_2 exp(-a_2 v) + C v^-(1 + omega),  a_i = R_i rho_0,
+// with C fixed by p_s(v_K) = p_K (the homogeneous part of de = -p dv for
+// eq. JWL_EOS), so rho^2 c^2 = -dp_s/dv and f = -int_{v_K}^{v} sqrt(-p_s') dv.
+M2C_HD inline void jwl_ps(const EosK& m, double C, double v, double& ps, double& dps)
+{
+    const double x1 = exp(-m.k[3] * v), x2 = exp(-m.k[4] * v);
+    const double vp = exp(-(1.0 + m.k[0]) * log(v));
+    ps = m.k[1] * x1 + m.k[2] * x2 + C * vp;
+    dps = -m.k[1] * m.k[3] * x1 - m.k[2] * m.k[4] * x2 - (1.0 + m.k[0]) * C * vp / v;
+}
+
+// int_{v0}^{v1} sqrt(-p_s'(v)) dv: 8-point Gauss-Legendre on panels of at
+// most 0.1 in ln v; where both exponentials are below e^-40 of their
+// amplitude the integrand is the power law sqrt((1 + omega) C) v^-(1 + omega/2)
+// and the rest is integrated in closed form.  False where -p_s' <= 0.
+M2C_HD bool jwl_quad(const EosK& m, double C, double v0, double v1, double& I)
+{
+    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double w = m.k[0];
+    const double ve = 40.0 / fmin(m.k[3], m.k[4]);        // beyond: exponentials negligible
+    const double lo = fmin(v0, v1), hi = fmax(v0, v1);
+    double acc = 0.0;                                   // integral over [lo, hi]
+    if (hi > ve) {                                      // tail [max(lo, ve), hi] in closed form
+        if (!(C > 0.0)) return false;
+        const double t0 = fmax(lo, ve);
+        // int v^-(1 + w/2) dv = -(2/w) v^(-w/2)
+        acc += sqrt((1.0 + w) * C) * (2.0 / w) * (exp(-0.5 * w * log(t0)) - exp(-0.5 * w * log(hi)));
+    }
+    if (lo < ve) {                                      // body [lo, min(hi, ve)] by quadrature
+        const double u0 = log(lo), u1 = log(fmin(hi, ve));
+        const int n = (int)ceil((u1 - u0) / 0.1);
+        const double hu = n > 0 ? (u1 - u0) / n : 0.0;
+        for (int i = 0; i < n; ++i) {
+            const double um = u0 + (i + 0.5) * hu;
+            double sum = 0.0;
+            for (int j = 0; j < 8; ++j) {
+                const double u = um + 0.5 * hu * (j < 4 ? -gx[j] : gx[j - 4]);
+                const double v = exp(u);
+                double ps, dps;
+                jwl_ps(m, C, v, ps, dps);
+                if (!(dps < 0.0)) return false;
+                sum += gw[j & 3] * sqrt(-dps) * v;
+            }
+            acc += 0.5 * hu * sum;
+        }
+    }
+    I = v1 >= v0 ? acc : -acc;
+    return isfinite(I);
+}
+
+// f_K(p) for p <= p_K on a JWL side: v* from p_s(v*) = p by safeguarded
+// Newton in ln v, f continued from the last point of this isentrope.
+M2C_HD bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
+{
+    const double C = K.jC;
+    double lo = K.v, hi = INFINITY;                     // p_s(lo) >= p > p_s(hi)
+    double v = K.v * exp(-K.s);                         // start from the last point
+    if (!(v > lo)) v = K.v * exp(log(K.p / p) / (1.0 + m.k[0]));
+    bool ok = false;
+    double ps = 0.0, dps = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        jwl_ps(m, C, v, ps, dps);
+        if (!(dps < 0.0) || !isfinite(ps)) {            // past the convex part
+            hi = v;
+            v = isinf(hi) ? 0.5 * (lo + v) : sqrt(lo * hi);
+            continue;
+        }
+        if (ps > p) lo = v; else hi = v;
+        double vn = v * exp((p - ps) / (dps * v));
+        if (!(vn > lo && vn < hi)) vn = isinf(hi) ? 2.0 * v : sqrt(lo * hi);
+        const double dv = vn - v;
+        v = vn;
+        if (fabs(dv) <= 1e-15 * v) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok) return false;
+    jwl_ps(m, C, v, ps, dps);
+    if (!(dps < 0.0)) return false;
+    double I;
+    const double vlast = K.v * exp(-K.s);
+    if (!jwl_quad(m, C, vlast, v, I)) return false;
+    K.f -= I;
+    K.s = log(K.v / v);
+    w.f = K.f;
+    w.rho = 1.0 / v;
+    w.df = 1.0 / sqrt(-dps);                            // 1/(rho c)
+    return true;
+}
+
 // f_K(p) for p <= p_K: the isentrope walked to y = ln(p - floor).
 M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
+    if (m.fam == M2C_EOS_JWL) {
+        if (p == K.p) {
+            w.f = 0.0;
+            w.rho = K.rho;
+            w.df = 1.0 / (K.rho * K.c);
+            return true;
+        }
+        return jwl_rarefaction(m, K, p, w);
+    }
     if (m.fam == M2C_EOS_NASG) {
         // closed form: along the isentrope (p + p_c)(v - b)^gamma is
         // constant, and integrating dp/(rho c) with c^2 = gamma (p + p_c)
@@ -431,6 +534,11 @@ M2C_HD bool side_init(const EosK& m, double rho, double p, Side& K)
     K.y = log(p - K.fl);
     K.f = 0.0;
     K.vh = 0.0;
+    K.jC = 0.0;
+    if (m.fam == M2C_EOS_JWL) {
+        const double vK = K.v;
+        K.jC = (p - m.k[1] * exp(-m.k[3] * vK) - m.k[2] * exp(-m.k[4] * vK)) * exp((1.0 + m.k[0]) * log(vK));
+    }
     return true;
 }
 

@@ -3,7 +3,9 @@ against the oracle (``oracle/riemann_eos.py``), through the C ABI.
 
 Numerics bar.  The oracle integrates isentropes with DOP853 at relative
 tolerance 1e-13 and brackets every root; the library integrates them with
-RK4 over ln(p - floor) at steps of at most ds and stops its Newton iterations
+RK4 over ln(p - floor) at steps of at most ds (Mie-Grueneisen; NASG and
+JWL isentropes are closed forms, the JWL Riemann-invariant integral by
+Gauss-Legendre quadrature) and stops its Newton iterations
 at |dp| <= rtol (p - floor).  Both are FP64, so the difference is the RK4
 truncation error plus the two stopping rules.  Errors are measured as:
 p* relative to the smaller distance of p* from the two floors (the scale
@@ -87,20 +89,23 @@ def test_riemann_eos_matches_oracle(m2c, pair):
 
 
 def test_rk4_step_size_order(m2c):
-    """Rarefaction-dominated JWL and Mie-Grueneisen problems at two step
-    sizes: the error against the oracle falls by about 2^4 when ds halves."""
-    inp, mat, mats, _ = W.general_eos_problem_set(7, 24, pairs=[("tnt", "air"), ("copper", "tnt")])
+    """Rarefaction-dominated Mie-Grueneisen problems (the family whose
+    isentropes are integrated by RK4; NASG and JWL use closed forms) at two
+    step sizes: the error against the oracle falls by about 2^4 when ds
+    halves."""
+    inp, mat, mats, _ = W.general_eos_problem_set(7, 24, pairs=[("glass", "water_nasg"), ("copper", "tantalum")])
     inp[1], inp[4] = -np.abs(inp[1]), np.abs(inp[4])       # separating: both waves rarefactions
     eos = [RE.make_eos(f, p) for f, p in mats]
     ref = RE.solve(inp, mat, eos)
     ok = ~np.isnan(ref[0])
     errs = []
-    for ds in (0.2, 0.1):
+    # (at ds = 0.2 and 0.1 the glass isentropes are still pre-asymptotic)
+    for ds in (0.04, 0.02):
         got, it, _ = _gpu(m2c, inp, mat, mats, ds=ds, rtol=1e-14)
         e = _errors(inp[:, ok], mat[:, ok], eos, ref[:, ok], got[:, ok])
         errs.append(e[1].max())
-    print("ds 0.2 / 0.1 u errors", errs, flush=True)
-    assert errs[0] > 1e-11, errs                      # the truncation error is visible at ds = 0.2
+    print("ds 0.04 / 0.02 u errors", errs, flush=True)
+    assert errs[0] > 1e-10, errs                      # the truncation error is visible at ds = 0.04
     assert 8.0 <= errs[0] / errs[1] <= 32.0, errs
 
 
