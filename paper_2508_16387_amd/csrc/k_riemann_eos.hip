@@ -3,8 +3,12 @@
 // numerics are in m2c_eos.h.
 //
 // Work decomposition: one thread per problem, grid-stride, FP64 throughout;
-// the material table travels in the kernel arguments (materials may differ
-// between the lanes of a wavefront).
+// the material table travels in the kernel arguments.  The work of one
+// problem depends strongly on its two materials (closed forms for NASG and
+// JWL, RK4 walks for Mie-Grueneisen), and a wavefront runs as long as its
+// slowest lane, so a set that mixes material pairs is first grouped by pair
+// (a counting sort over the at most 64 pair keys) and solved through that
+// permutation: the lanes of a wavefront then share their materials.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -17,14 +21,72 @@ namespace {
 
 using namespace m2c::eos;
 
+// pair key of problem i: ml * nmat + mr, or nmat^2 for an index outside the table
+__device__ __forceinline__ int pair_key(const int32_t* mat, long long n, long long i, int nmat)
+{
+    const int ml = mat[i], mr = mat[n + i];
+    return (ml >= 0 && ml < nmat && mr >= 0 && mr < nmat) ? ml * nmat + mr : nmat * nmat;
+}
+
+constexpr int NKEY = M2C_EOS_MAX * M2C_EOS_MAX + 1;
+
+// counts[key] += problems of that key (block histogram in LDS first)
+__global__ __launch_bounds__(256) void k_pair_count(long long n, const int32_t* __restrict__ mat, int nmat,
+                                                    int32_t* __restrict__ counts)
+{
+    __shared__ int32_t h[NKEY];
+    for (int k = threadIdx.x; k < NKEY; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&h[pair_key(mat, n, i, nmat)], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < NKEY; k += blockDim.x)
+        if (h[k]) atomicAdd(&counts[k], h[k]);
+}
+
+// cursor = exclusive prefix sum of counts (one thread; NKEY entries)
+__global__ void k_pair_scan(const int32_t* __restrict__ counts, int32_t* __restrict__ cursor)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        int32_t acc = 0;
+        for (int k = 0; k < NKEY; ++k) {
+            cursor[k] = acc;
+            acc += counts[k];
+        }
+    }
+}
+
+// perm[slot] = i, slots of one key contiguous: each block reserves its
+// share of every key with one atomic and ranks its problems in LDS
+__global__ __launch_bounds__(256) void k_pair_place(long long n, const int32_t* __restrict__ mat, int nmat,
+                                                    int32_t* __restrict__ cursor, int32_t* __restrict__ perm)
+{
+    __shared__ int32_t h[NKEY], base[NKEY];
+    for (int k = threadIdx.x; k < NKEY; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    int key = 0, rank = 0;
+    if (i < n) {
+        key = pair_key(mat, n, i, nmat);
+        rank = atomicAdd(&h[key], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < NKEY; k += blockDim.x)
+        if (h[k]) base[k] = atomicAdd(&cursor[k], h[k]);
+    __syncthreads();
+    if (i < n) perm[base[key] + rank] = (int32_t)i;
+}
+
+// perm (nullable): thread t solves problem perm[t]
 __global__ __launch_bounds__(256) void k_riemann_eos(long long n, const double* __restrict__ in,
                                                      const int32_t* __restrict__ mat, const EosTable tab,
                                                      double rtol, int maxit, double hmax,
                                                      double* __restrict__ out, int32_t* __restrict__ iters,
-                                                     int32_t* __restrict__ nbad)
+                                                     int32_t* __restrict__ nbad, const int32_t* __restrict__ perm)
 {
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const long long i = perm ? (long long)perm[t] : t;
         double q[6], res[4];
         for (int k = 0; k < 6; ++k) q[k] = in[k * n + i];
         const int its = solve_one(tab, mat[i], mat[n + i], q, rtol, maxit, hmax, res);
@@ -79,14 +141,28 @@ extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t*
     if (!prepare(nmat, eos, tab)) return M2C_ERR_ARG;
     if (n == 0) return M2C_OK;
     hipStream_t s = (hipStream_t)hip_stream;
+    // grouping by material pair pays once the set is large and mixes pairs
+    const bool group = nmat > 1 && n >= 4096 && n < (1LL << 31);
+    // workspace (int32): failure count, key counts, key cursors, permutation
+    const long long words = 1 + 2 * NKEY + (group ? n : 0);
     int32_t* dbad = nullptr;
-    if (hipMalloc((void**)&dbad, sizeof(int32_t)) != hipSuccess) return M2C_ERR_NOMEM;
+    if (hipMalloc((void**)&dbad, words * sizeof(int32_t)) != hipSuccess) return M2C_ERR_NOMEM;
+    int32_t* counts = dbad + 1;
+    int32_t* cursor = counts + NKEY;
+    int32_t* perm = group ? cursor + NKEY : nullptr;
     int32_t hb = 0;
     int rc = M2C_OK;
-    if (hipMemsetAsync(dbad, 0, sizeof(int32_t), s) != hipSuccess) rc = M2C_ERR_DEVICE;
+    if (hipMemsetAsync(dbad, 0, (1 + NKEY) * sizeof(int32_t), s) != hipSuccess) rc = M2C_ERR_DEVICE;
+    if (rc == M2C_OK && group) {
+        const unsigned nb = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, s, (long long)n, mat, (int)nmat, counts);
+        hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(64), 0, s, counts, cursor);
+        hipLaunchKernelGGL(k_pair_place, dim3(nb), dim3(256), 0, s, (long long)n, mat, (int)nmat, cursor, perm);
+        if (hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
+    }
     if (rc == M2C_OK) {
         hipLaunchKernelGGL(k_riemann_eos, dim3(grid_for(n)), dim3(256), 0, s, (long long)n, in, mat, tab, rtol,
-                           (int)maxit, ds, out, iters, dbad);
+                           (int)maxit, ds, out, iters, dbad, (const int32_t*)perm);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(&hb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
