@@ -225,23 +225,29 @@ class Side:
         eos, fl = self.eos, self.eos.floor
         q0 = self.p - fl                              # distance from the floor
 
+        def c2_at(t, q):
+            rho = self.rho * math.exp(t)
+            return eos.c2(rho, eos.e(rho, fl + q))
+
         def rhs(s, y):
-            rho = self.rho * math.exp(s)
-            p = fl + y[0]
-            e = eos.e(rho, p)
-            c2 = eos.c2(rho, e)
-            c = math.sqrt(c2) if c2 > 0 else 0.0
-            return [rho * c2, c]
+            c2 = c2_at(s, y[0])
+            if not c2 > 0:                      # outside the convex part (trial stages only)
+                return [0.0, 0.0]
+            return [self.rho * math.exp(s) * c2, math.sqrt(c2)]
 
         # Stepped by hand so that the run is bounded.  Pressures are carried
         # as the distance q from the floor; where the floor is far below
         # the pressure (large p_c), q is only known to the rounding of p
         # itself, so the absolute tolerance of q is that rounding level.
+        # The isentrope ends where q reaches q_stop or where c^2 reaches 0
+        # (the EOS is admissible only where it is convex), each located
+        # inside the accepted step that passes it.
         st = integrate.DOP853(rhs, 0.0, [q0, 0.0], _S_END, rtol=1e-13,
                               atol=[1e-15 * abs(fl) + 1e-300, 1e-15 * self.c])
         ts, interps = [0.0], []
         q_stop = _FLOOR_MARGIN * q0 + _FLOOR_REL * abs(fl)
-        while st.status == "running" and st.y[0] > q_stop:
+        end = None
+        while st.status == "running":
             if len(interps) >= _MAX_STEPS:
                 raise RuntimeError("isentrope integration exceeded its step budget")
             st.step()
@@ -249,10 +255,23 @@ class Side:
                 raise RuntimeError("isentrope integration failed")
             ts.append(st.t)
             interps.append(st.dense_output())
+            nonconvex = not c2_at(st.t, st.y[0]) > 0
+            if not nonconvex and st.y[0] > q_stop:
+                continue
+            sol = integrate._ivp.common.OdeSolution(ts, interps)
+            if nonconvex:
+                end = optimize.brentq(lambda t: c2_at(t, sol(t)[0]), ts[-1], ts[-2], xtol=1e-300, rtol=1e-15)
+                end = end + 1e-12 * (ts[-2] - end)      # stay on the convex side
+            if st.y[0] <= q_stop:
+                t_q = optimize.brentq(lambda t: sol(t)[0] - q_stop, ts[-1], ts[-2], xtol=1e-300, rtol=1e-15)
+                end = t_q if end is None else max(end, t_q)
+            if end is not None:
+                break
         sol = integrate._ivp.common.OdeSolution(ts, interps)
-        self.s_end = ts[-1]
-        self.p_end = fl + float(st.y[0])
-        self.f_end = float(st.y[1])
+        self.s_end = ts[-1] if end is None else end
+        y_end = sol(self.s_end)
+        self.p_end = fl + float(y_end[0])
+        self.f_end = float(y_end[1])
         self._sol = sol
         return sol
 

@@ -351,7 +351,8 @@ MUTANTS = [
      "check_jwl_isentrope"),
     ("jwl derivative", "a * x * R * self.rho0 / (rho * rho)", "a * x * R * self.rho0 / rho", "check_jwl_isentrope"),
     ("hugoniot mean pressure", "0.5 * (pstar + pK)", "0.5 * (pstar - pK)", "check_stiffened_gas"),
-    ("rarefaction df/ds", "return [rho * c2, c]", "return [rho * c2, c / rho]", "check_stiffened_gas"),
+    ("rarefaction df/ds", "return [self.rho * math.exp(s) * c2, math.sqrt(c2)]",
+     "return [self.rho * math.exp(s) * c2, math.sqrt(c2) / self.rho]", "check_stiffened_gas"),
     ("sound speed sign", "+ self.p(rho, e) * self.p_e(rho, e)", "- self.p(rho, e) * self.p_e(rho, e)",
      "check_stiffened_gas"),
     ("star velocity side", "0.5 * (left.u - fL + right.u + fR)", "0.5 * (left.u + fL + right.u - fR)",
