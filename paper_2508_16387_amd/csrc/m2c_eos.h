@@ -276,6 +276,76 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
                 if (to_kink) kink[1] = INFINITY;
                 continue;
             }
+            if (mg_branch(m, 1.0 - m.k[0] / (K.rho * exp(K.s + dir * 1e-10))) == 1) {
+                // small tension: along the isentrope e - e_R(eta) decays as
+                // exp(-rho_0 Gamma_0 v) (de = -p dv with p_R = K_0 eta, e_R
+                // quadratic), so p(v) = K_0 (1 - rho_0 v) + (p_a - K_0 eta_a)
+                // exp(-rho_0 Gamma_0 (v - v_a)); v at the target pressure by
+                // Newton, f by Gauss-Legendre; the branch ends (eta_min when
+                // p falls, eta = 0 when it rises) are stepped onto exactly
+                const double r0 = m.k[0], G = m.k[6], K0 = m.k[5];
+                const double va = K.v * exp(-K.s);
+                const double ga = (K.fl + exp(K.y)) - K0 * (1.0 - r0 * va);     // rho_0 Gamma_0 (e - e_R)
+                auto P = [&](double v) { return K0 * (1.0 - r0 * v) + ga * exp(-G * (v - va)); };
+                auto mdP = [&](double v) { return K0 * r0 + G * ga * exp(-G * (v - va)); };   // -dp/dv
+                const int j = dir < 0.0 ? 1 : 0;
+                const double vk = dir < 0.0 ? (1.0 - m.k[4]) / r0 : 1.0 / r0;
+                const double pt = K.fl + exp(Y), pk = P(vk);
+                const bool to_kink = dir < 0.0 ? pt <= pk : pt >= pk;
+                double v = vk;
+                if (!to_kink) {
+                    double lo = fmin(va, vk), hi = fmax(va, vk);      // P(lo) > pt > P(hi)
+                    v = va;
+                    bool conv = false;
+                    for (int it = 0; it < 100; ++it) {
+                        const double d = mdP(v);
+                        if (!(d > 0.0)) return false;
+                        const double r = P(v) - pt;
+                        if (r > 0.0) lo = v; else hi = v;
+                        // converged (before the bracket test): a step of a few
+                        // ulp, or a bracket closed to that width
+                        if (fabs(r / d) <= 1e-15 * v || hi - lo <= 4e-16 * v) {
+                            v += r / d;
+                            v = fmin(fmax(v, lo), hi);
+                            conv = true;
+                            break;
+                        }
+                        double vn = v + r / d;
+                        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
+                        v = vn;
+                    }
+                    if (!conv) return false;
+                }
+                // f -= int_{va}^{v} sqrt(-dp/dv) dv
+                {
+                    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267,
+                                          0.9602898564975363};
+                    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745,
+                                          0.1012285362903763};
+                    const int np = 1 + (int)(G * fabs(v - va) / 0.5);
+                    const double hv = (v - va) / np;
+                    double I = 0.0;
+                    for (int i = 0; i < np; ++i) {
+                        const double vm = va + (i + 0.5) * hv;
+                        for (int q = 0; q < 8; ++q) {
+                            const double d = mdP(vm + 0.5 * hv * (q < 4 ? -gx[q] : gx[q - 4]));
+                            if (!(d > 0.0)) return false;
+                            I += 0.5 * hv * gw[q & 3] * sqrt(d);
+                        }
+                    }
+                    K.f -= I;
+                }
+                if (to_kink) {
+                    K.s = kink[j] + (dir < 0.0 ? -1e-12 : 1e-12) * (1.0 + fabs(kink[j]));
+                    if (!isfinite(kink[j])) K.s = log(K.v / vk);
+                    K.y = log(pk - K.fl);
+                    kink[j] = INFINITY;
+                } else {
+                    K.s = log(K.v / v);
+                    K.y = Y;
+                }
+                continue;
+            }
         }
         const int n = (int)ceil(fabs(rem) / hmax);
         const double h = rem / (double)n;
@@ -398,14 +468,19 @@ M2C_HD bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
             continue;
         }
         if (ps > p) lo = v; else hi = v;
-        double vn = v * exp((p - ps) / (dps * v));
-        if (!(vn > lo && vn < hi)) vn = isinf(hi) ? 2.0 * v : sqrt(lo * hi);
-        const double dv = vn - v;
-        v = vn;
-        if (fabs(dv) <= 1e-15 * v) {
+        const double du = (p - ps) / (dps * v);
+        // converged (before the bracket test): ln v to 1e-14 (the power
+        // term is evaluated as exp(-(1 + omega) ln v), whose rounding grows
+        // with ln v), or a bracket closed to a few ulp
+        if (fabs(du) <= 1e-14 || (isfinite(hi) && hi - lo <= 4e-16 * hi)) {
+            v *= exp(du);
+            v = fmin(fmax(v, lo), hi);
             ok = true;
             break;
         }
+        double vn = v * exp(du);
+        if (!(vn > lo && vn < hi)) vn = isinf(hi) ? 2.0 * v : sqrt(lo * hi);
+        v = vn;
     }
     if (!ok) return false;
     jwl_ps(m, C, v, ps, dps);
@@ -483,15 +558,19 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
         double ev, ep;
         eos_ederiv(m, v, p, ev, ep);
         if (H > 0.0) hi = v; else lo = v;
-        const double dH = ev + half;
-        double vn = v - H / dH;
-        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
-        const double dv = vn - v;
-        v = vn;
-        if (fabs(dv) <= 1e-15 * v) {
+        const double step = H / (ev + half);
+        // a converged Newton step is taken before the bracket is consulted
+        // (a step below rounding would otherwise fail the bracket test and
+        // restart a bisection)
+        if (fabs(step) <= 1e-15 * v || hi - lo <= 4e-16 * hi) {
+            v -= step;
+            v = fmin(fmax(v, lo), hi);
             ok = true;
             break;
         }
+        double vn = v - step;
+        if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
+        v = vn;
     }
     if (!ok || !(v > m.k[KVMIN]) || !(v < vK)) return false;
     K.vh = v;

@@ -8,9 +8,11 @@ JWL isentropes are closed forms, the JWL Riemann-invariant integral by
 Gauss-Legendre quadrature) and stops its Newton iterations
 at |dp| <= rtol (p - floor).  Both are FP64, so the difference is the RK4
 truncation error plus the two stopping rules.  Errors are measured as:
-p* relative to the smaller distance of p* from the two floors (the scale
-the solver's stopping rule uses), u* relative to the larger sound speed of
-the two initial states, rho* relative.  TOL_EOS bounds all three at the
+u* relative to the larger sound speed of the two initial states; p* as the
+velocity change its difference amounts to across the two star impedances
+(|dp| (1/(rho* c*)_L + 1/(rho* c*)_R)), on the same scale -- near
+cavitation p* is many decades below the pressures of the problem and is
+fixed by the velocities; rho* relative.  TOL_EOS bounds all three at the
 default ds = 0.01; the test of the step size shows that the RK4 part of the
 error shrinks at fourth order.
 """
@@ -56,10 +58,14 @@ def _errors(inp, mat, eos, ref, got):
     n = inp.shape[1]
     e = np.zeros((3, n))
     for i in range(n):
-        fl = min(ref[0, i] - eos[mat[0, i]].floor, ref[0, i] - eos[mat[1, i]].floor)
-        cL = RE.Side(eos[mat[0, i]], inp[0, i], inp[1, i], inp[2, i]).c
-        cR = RE.Side(eos[mat[1, i]], inp[3, i], inp[4, i], inp[5, i]).c
-        e[0, i] = abs(got[0, i] - ref[0, i]) / fl
+        mL, mR = eos[mat[0, i]], eos[mat[1, i]]
+        cL = RE.Side(mL, inp[0, i], inp[1, i], inp[2, i]).c
+        cR = RE.Side(mR, inp[3, i], inp[4, i], inp[5, i]).c
+        # the velocity change that the p* difference amounts to across the
+        # two star impedances rho* c*
+        p, rL, rR = ref[0, i], ref[2, i], ref[3, i]
+        zinv = 1.0 / (rL * np.sqrt(mL.c2(rL, mL.e(rL, p)))) + 1.0 / (rR * np.sqrt(mR.c2(rR, mR.e(rR, p))))
+        e[0, i] = abs(got[0, i] - p) * zinv / max(cL, cR)
         e[1, i] = abs(got[1, i] - ref[1, i]) / max(cL, cR)
         e[2, i] = max(abs(got[2, i] / ref[2, i] - 1), abs(got[3, i] / ref[3, i] - 1))
     return e
