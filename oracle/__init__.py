@@ -60,6 +60,14 @@ def build_variant(path: str, defines=()):
     return path
 
 
+class EosC(C.Structure):
+    _fields_ = [("family", C.c_int32), ("reserved", C.c_int32), ("prm", C.c_double * 7)]
+
+
+# star state of one two-material Riemann problem: (ml, mr, in[6], out[4]) -> rc
+RIEMANN_FN = C.CFUNCTYPE(C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double))
+
+
 class Cfg(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -67,7 +75,31 @@ class Cfg(C.Structure):
                 ("bc", C.c_int32 * 6), ("alpha", C.c_double), ("rk_order", C.c_int32),
                 ("cfl", C.c_double), ("dt_fixed", C.c_double), ("rtol", C.c_double),
                 ("maxit", C.c_int32), ("limiter", C.c_int32), ("limiter_k", C.c_int32),
-                ("flux", C.c_int32), ("ls_band", C.c_double)]
+                ("flux", C.c_int32), ("ls_band", C.c_double), ("eos_general", C.c_int32),
+                ("eos", EosC * 2), ("riemann", RIEMANN_FN)]
+
+
+def general_eos_riemann(eos_pair):
+    """The interface solver of a general-EOS run: the star state from
+    ``riemann_eos`` (bracketed roots, adaptive isentropes) for the two
+    materials (family, params) of eos_pair."""
+    from . import riemann_eos as RE
+    mats = [RE.make_eos(f, prm) for f, prm in eos_pair]
+
+    def solve(ml, mr, inp, out):
+        try:
+            L = RE.Side(mats[ml], inp[0], inp[1], inp[2])
+            R = RE.Side(mats[mr], inp[3], inp[4], inp[5])
+            res = RE.star_state(L, R)
+        except (ValueError, RuntimeError, ZeroDivisionError, OverflowError):
+            return ERR_RIEMANN
+        if not all(np.isfinite(res)):
+            return ERR_RIEMANN
+        for k in range(4):
+            out[k] = res[k]
+        return OK
+
+    return RIEMANN_FN(solve)
 
 
 LIM_MC, LIM_VA, LIM_VA_MOD = 0, 1, 2
@@ -125,6 +157,11 @@ def load(path: str | None = None):
     lib.ora_riemann_many.argtypes = [C.c_int64, _D, _D, C.c_double, C.c_int32, _D, C.c_void_p]
     lib.ora_ls_derivative.restype = C.c_double
     lib.ora_ls_derivative.argtypes = [_D, C.c_double, C.c_double]
+    for name in ("ora_eos_p", "ora_eos_e", "ora_eos_c2"):
+        getattr(lib, name).restype = C.c_double
+        getattr(lib, name).argtypes = [C.POINTER(EosC), C.c_double, C.c_double]
+    lib.ora_eos_floor.restype = C.c_double
+    lib.ora_eos_floor.argtypes = [C.POINTER(EosC)]
     return lib
 
 
@@ -140,6 +177,8 @@ def lib():
 
 def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_MC, limiter_k=2,
              flux=FLUX_HLLC, ls_band=0.0):
+    """The oracle configuration of a problem; a problem with an ``eos``
+    attribute (two (family, params) pairs) runs with those general EOS."""
     c = Cfg()
     c.nx, c.ny, c.nz = problem.n
     for d in range(3):
@@ -160,7 +199,21 @@ def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_M
     c.limiter_k = limiter_k
     c.flux = flux
     c.ls_band = ls_band
+    eos = getattr(problem, "eos", None)
+    if eos is not None:
+        c.eos_general = 1
+        for m in range(2):
+            c.eos[m] = eos_struct(*eos[m])
+        c.riemann = general_eos_riemann(eos)
     return c
+
+
+def eos_struct(family, params):
+    e = EosC()
+    e.family = family
+    for k, v in enumerate(params):
+        e.prm[k] = v
+    return e
 
 
 class OracleSim:
@@ -283,6 +336,18 @@ def cons_to_prim(w, gamma, pc):
     q = np.empty(5)
     lib().ora_cons_to_prim(np.asarray(w, dtype=np.float64), gamma, pc, q)
     return q
+
+
+def eos_point(family, params, rho, x, what):
+    """General EOS point function of the C oracle: what = "p" (x = e),
+    "e" or "c2" (x = p)."""
+    e = eos_struct(family, params)
+    return getattr(lib(), "ora_eos_" + what)(C.byref(e), rho, x)
+
+
+def eos_floor(family, params):
+    e = eos_struct(family, params)
+    return lib().ora_eos_floor(C.byref(e))
 
 
 def ls_derivative(f5, v, h):

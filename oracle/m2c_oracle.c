@@ -61,6 +61,119 @@ double ora_sound_speed(double rho, double p, double gamma, double pc)
 }
 
 /* ------------------------------------------------------------------------ */
+/* General equations of state (section "Equations of state", eq. eos_all):
+ * p = p(rho, e) per family, e(rho, p) its inverse in e (each family is
+ * affine in e), and c^2 = dp/drho|_e + p dp/de|_rho / rho^2.
+ *   NASG (eq. NASG_EOS): p = (gamma - 1) rho (e - e_c) / (1 - b rho) - gamma p_c;
+ *   Mie-Grueneisen (appendix on equations of state): p = p_R(eta) +
+ *     rho_0 Gamma_0 (e - e_R(eta)), eta = 1 - rho_0/rho, with the reference
+ *     curves of compression (eta >= 0, where e_R takes the Hugoniot pressure
+ *     of the reference state to be p_R), small tension (eta_min <= eta < 0)
+ *     and the tensile cutoff below eta_min;
+ *   JWL (eq. JWL_EOS, both exponentials decaying):
+ *     p = omega rho e + sum_i A_i (1 - omega rho / (R_i rho_0)) exp(-R_i rho_0 / rho).
+ * Lowest admissible pressure: -p_c (NASG), rho_0 c_0^2 eta_min (MG), 0 (JWL). */
+
+/* MG reference curves p_R, e_R and their eta-derivatives. */
+static void mg_reference(const double* a, double eta, double* pR, double* eR, double* dpR, double* deR)
+{
+    double r0 = a[0], K0 = a[0] * a[1] * a[1], s = a[3], e0 = a[4], em = a[5];
+    if (eta >= 0.0) {
+        double d = 1.0 - s * eta;
+        *pR = K0 * eta / (d * d);
+        *dpR = K0 * (1.0 + s * eta) / (d * d * d);
+        *eR = *pR * eta / (2.0 * r0) + e0;
+        *deR = (*dpR * eta + *pR) / (2.0 * r0);
+    } else if (eta >= em) {
+        *pR = K0 * eta;
+        *dpR = K0;
+        *eR = K0 * eta * eta / (2.0 * r0) + e0;
+        *deR = K0 * eta / r0;
+    } else {
+        double pmin = K0 * em;
+        *pR = pmin;
+        *dpR = 0.0;
+        *eR = K0 * em * em / (2.0 * r0) + e0 + pmin / r0 * (eta - em);
+        *deR = pmin / r0;
+    }
+}
+
+/* JWL: T(rho) = sum_i A_i (1 - omega rho/(R_i rho_0)) exp(-R_i rho_0/rho) and dT/drho. */
+static void jwl_exp_terms(const double* a, double rho, double* T, double* dT)
+{
+    double w = a[0], r0 = a[5];
+    *T = 0.0;
+    *dT = 0.0;
+    for (int i = 0; i < 2; ++i) {
+        double A = a[1 + i], R = a[3 + i];
+        double x = exp(-R * r0 / rho);
+        double f = 1.0 - w * rho / (R * r0);
+        *T += A * f * x;
+        *dT += A * (-w / (R * r0) * x + f * x * R * r0 / (rho * rho));
+    }
+}
+
+double ora_eos_p(const ora_eos* m, double rho, double e)
+{
+    const double* a = m->prm;
+    if (m->family == ORA_EOS_NASG)
+        return (a[0] - 1.0) * rho * (e - a[3]) / (1.0 - a[2] * rho) - a[0] * a[1];
+    if (m->family == ORA_EOS_MG) {
+        double pR, eR, dpR, deR;
+        mg_reference(a, 1.0 - a[0] / rho, &pR, &eR, &dpR, &deR);
+        return pR + a[0] * a[2] * (e - eR);
+    }
+    double T, dT;
+    jwl_exp_terms(a, rho, &T, &dT);
+    return a[0] * rho * e + T;
+}
+
+double ora_eos_e(const ora_eos* m, double rho, double p)
+{
+    const double* a = m->prm;
+    if (m->family == ORA_EOS_NASG)
+        return (p + a[0] * a[1]) * (1.0 - a[2] * rho) / ((a[0] - 1.0) * rho) + a[3];
+    if (m->family == ORA_EOS_MG) {
+        double pR, eR, dpR, deR;
+        mg_reference(a, 1.0 - a[0] / rho, &pR, &eR, &dpR, &deR);
+        return eR + (p - pR) / (a[0] * a[2]);
+    }
+    double T, dT;
+    jwl_exp_terms(a, rho, &T, &dT);
+    return (p - T) / (a[0] * rho);
+}
+
+double ora_eos_c2(const ora_eos* m, double rho, double p)
+{
+    const double* a = m->prm;
+    double e = ora_eos_e(m, rho, p), p_rho, p_e;
+    if (m->family == ORA_EOS_NASG) {
+        double d = 1.0 - a[2] * rho;
+        p_rho = (a[0] - 1.0) * (e - a[3]) / (d * d);
+        p_e = (a[0] - 1.0) * rho / d;
+    } else if (m->family == ORA_EOS_MG) {
+        double pR, eR, dpR, deR;
+        mg_reference(a, 1.0 - a[0] / rho, &pR, &eR, &dpR, &deR);
+        p_rho = (dpR - a[0] * a[2] * deR) * a[0] / (rho * rho);
+        p_e = a[0] * a[2];
+    } else {
+        double T, dT;
+        jwl_exp_terms(a, rho, &T, &dT);
+        p_rho = a[0] * e + dT;
+        p_e = a[0] * rho;
+    }
+    return p_rho + p * p_e / (rho * rho);
+}
+
+double ora_eos_floor(const ora_eos* m)
+{
+    const double* a = m->prm;
+    if (m->family == ORA_EOS_NASG) return -a[1];
+    if (m->family == ORA_EOS_MG) return a[0] * a[1] * a[1] * a[5];
+    return 0.0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* MC limiter, appendix "Slope limiters", eqs. theta and AB on a uniform
  * grid: theta = (w_i - w_{i-1}) / (w_{i+1} - w_i), A = B = 1,
  * phi = max(0, min(alpha theta, B (theta + 1)/(A + 1), alpha)), and the
@@ -126,14 +239,12 @@ static double specific_total_energy(const double* q, double gamma, double pc)
     return e + 0.5 * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
 }
 
-void ora_hllc(const double* qL, const double* qR, double gamma, double pc, double* F)
+/* HLLC with the sound speeds and specific total energies of the two
+ * states given (they are all the flux needs of the EOS). */
+static void hllc_ce(const double* qL, const double* qR, double cL, double cR, double EL, double ER, double* F)
 {
     double rL = qL[0], uL = qL[1], pL = qL[4];
     double rR = qR[0], uR = qR[1], pR = qR[4];
-    double cL = sound_speed(rL, pL, gamma, pc);
-    double cR = sound_speed(rR, pR, gamma, pc);
-    double EL = specific_total_energy(qL, gamma, pc);
-    double ER = specific_total_energy(qR, gamma, pc);
 
     double SL = fmin(uL - cL, uR - cR);
     double SR = fmax(uL + cL, uR + cR);
@@ -169,32 +280,80 @@ void ora_hllc(const double* qL, const double* qR, double gamma, double pc, doubl
     }
 }
 
+void ora_hllc(const double* qL, const double* qR, double gamma, double pc, double* F)
+{
+    double cL = sound_speed(qL[0], qL[4], gamma, pc);
+    double cR = sound_speed(qR[0], qR[4], gamma, pc);
+    double EL = specific_total_energy(qL, gamma, pc);
+    double ER = specific_total_energy(qR, gamma, pc);
+    hllc_ce(qL, qR, cL, cR, EL, ER, F);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Local Lax-Friedrichs, appendix "Local Lax-Friedrichs flux" (eq.
  * Lax-Friedrichs): the mean of the two physical fluxes minus half the
  * fastest wave speed max(|u_L| + c_L, |u_R| + c_R) times the jump of the
  * conservative state.                                                     */
-void ora_llf(const double* qL, const double* qR, double gamma, double pc, double* F)
+static void llf_ce(const double* qL, const double* qR, double cL, double cR, double EL, double ER, double* F)
 {
-    double EL = specific_total_energy(qL, gamma, pc);
-    double ER = specific_total_energy(qR, gamma, pc);
     double FL[5], FR[5], UL[5], UR[5];
     euler_flux(qL, EL, FL);
     euler_flux(qR, ER, FR);
     UL[0] = qL[0]; UL[1] = qL[0] * qL[1]; UL[2] = qL[0] * qL[2]; UL[3] = qL[0] * qL[3]; UL[4] = qL[0] * EL;
     UR[0] = qR[0]; UR[1] = qR[0] * qR[1]; UR[2] = qR[0] * qR[2]; UR[3] = qR[0] * qR[3]; UR[4] = qR[0] * ER;
-    double lmax = fmax(fabs(qL[1]) + sound_speed(qL[0], qL[4], gamma, pc),
-                       fabs(qR[1]) + sound_speed(qR[0], qR[4], gamma, pc));
+    double lmax = fmax(fabs(qL[1]) + cL, fabs(qR[1]) + cR);
     for (int v = 0; v < 5; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lmax * (UR[v] - UL[v]);
+}
+
+void ora_llf(const double* qL, const double* qR, double gamma, double pc, double* F)
+{
+    llf_ce(qL, qR, sound_speed(qL[0], qL[4], gamma, pc), sound_speed(qR[0], qR[4], gamma, pc),
+           specific_total_energy(qL, gamma, pc), specific_total_energy(qR, gamma, pc), F);
 }
 
 /* The numerical flux of the configuration (section "Spatial discretization
  * of governing equations": one flux function Phi for every face, the
  * one-sided FIVER fluxes included).                                       */
-static void num_flux(const ora_cfg* c, const double* qL, const double* qR, double gamma, double pc, double* F)
+static void num_flux(const ora_cfg* c, const double* qL, const double* qR, int m, double* F)
 {
-    if (c->flux == ORA_FLUX_LLF) ora_llf(qL, qR, gamma, pc, F);
-    else ora_hllc(qL, qR, gamma, pc, F);
+    if (!c->eos_general) {
+        if (c->flux == ORA_FLUX_LLF) ora_llf(qL, qR, c->gamma[m], c->pc[m], F);
+        else ora_hllc(qL, qR, c->gamma[m], c->pc[m], F);
+        return;
+    }
+    const ora_eos* e = &c->eos[m];
+    double cL = sqrt(ora_eos_c2(e, qL[0], qL[4])), cR = sqrt(ora_eos_c2(e, qR[0], qR[4]));
+    double EL = ora_eos_e(e, qL[0], qL[4]) + 0.5 * (qL[1] * qL[1] + qL[2] * qL[2] + qL[3] * qL[3]);
+    double ER = ora_eos_e(e, qR[0], qR[4]) + 0.5 * (qR[1] * qR[1] + qR[2] * qR[2] + qR[3] * qR[3]);
+    if (c->flux == ORA_FLUX_LLF) llf_ce(qL, qR, cL, cR, EL, ER, F);
+    else hllc_ce(qL, qR, cL, cR, EL, ER, F);
+}
+
+/* Conservative <-> primitive and sound speed of material m of the
+ * configuration (stiffened gas or general EOS). */
+static void mat_cons_to_prim(const ora_cfg* c, int m, const double* w, double* q)
+{
+    if (!c->eos_general) { ora_cons_to_prim(w, c->gamma[m], c->pc[m], q); return; }
+    double rho = w[0];
+    double u = w[1] / rho, v = w[2] / rho, ww = w[3] / rho;
+    double e = w[4] / rho - 0.5 * (u * u + v * v + ww * ww);
+    q[0] = rho; q[1] = u; q[2] = v; q[3] = ww;
+    q[4] = ora_eos_p(&c->eos[m], rho, e);
+}
+
+static void mat_prim_to_cons(const ora_cfg* c, int m, const double* q, double* w)
+{
+    if (!c->eos_general) { ora_prim_to_cons(q, c->gamma[m], c->pc[m], w); return; }
+    double rho = q[0], u = q[1], v = q[2], ww = q[3];
+    double e = ora_eos_e(&c->eos[m], rho, q[4]);
+    w[0] = rho; w[1] = rho * u; w[2] = rho * v; w[3] = rho * ww;
+    w[4] = rho * (e + 0.5 * (u * u + v * v + ww * ww));
+}
+
+static double mat_sound_speed(const ora_cfg* c, int m, double rho, double p)
+{
+    if (!c->eos_general) return sound_speed(rho, p, c->gamma[m], c->pc[m]);
+    return sqrt(ora_eos_c2(&c->eos[m], rho, p));
 }
 
 /* ------------------------------------------------------------------------ */
@@ -358,6 +517,11 @@ static int64_t pidx(const ora_sim* s, int i, int j, int k)
 ora_sim* ora_create(const ora_cfg* cfg)
 {
     if (!cfg || cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return NULL;
+    if (cfg->eos_general) {
+        if (!cfg->riemann) return NULL;
+        for (int m = 0; m < 2; ++m)
+            if (cfg->eos[m].family < ORA_EOS_NASG || cfg->eos[m].family > ORA_EOS_JWL) return NULL;
+    }
     ora_sim* s = (ora_sim*)calloc(1, sizeof(ora_sim));
     if (!s) return NULL;
     s->c = *cfg;
@@ -397,10 +561,14 @@ void ora_destroy(ora_sim* s)
 /* Material 1 occupies phi < 0 (reading of the signed-distance convention). */
 static uint8_t material_of(double phi) { return phi < 0.0 ? 1 : 0; }
 
-static int physical(const double* q, double pc)
+/* Admissible primitive state of material m: finite, rho > 0 and p above
+ * the material's floor (p + p_c > 0 for the stiffened gas); with a general
+ * EOS also c^2 > 0 (the EOS is used only where it is convex). */
+static int physical(const ora_cfg* c, int m, const double* q)
 {
     for (int v = 0; v < 5; ++v) if (!isfinite(q[v])) return 0;
-    return q[0] > 0.0 && q[4] + pc > 0.0;
+    if (!c->eos_general) return q[0] > 0.0 && q[4] + c->pc[m] > 0.0;
+    return q[0] > 0.0 && q[4] > ora_eos_floor(&c->eos[m]) && ora_eos_c2(&c->eos[m], q[0], q[4]) > 0.0;
 }
 
 int ora_set_prim(ora_sim* s, const double* prim6)
@@ -410,8 +578,8 @@ int ora_set_prim(ora_sim* s, const double* prim6)
         for (int v = 0; v < 5; ++v) q[v] = prim6[v * s->N + c];
         double phi = prim6[5 * s->N + c];
         uint8_t m = material_of(phi);
-        if (!physical(q, s->c.pc[m]) || !isfinite(phi)) { s->st.err_cell = c; return ORA_ERR_NONPHYSICAL; }
-        ora_prim_to_cons(q, s->c.gamma[m], s->c.pc[m], w);
+        if (!physical(&s->c, m, q) || !isfinite(phi)) { s->st.err_cell = c; return ORA_ERR_NONPHYSICAL; }
+        mat_prim_to_cons(&s->c, m, q, w);
         for (int v = 0; v < 5; ++v) s->W[v][c] = w[v];
         s->phi[c] = phi;
         s->chi[c] = m;
@@ -444,7 +612,7 @@ int ora_get_prim(const ora_sim* s, double* prim6, uint8_t* chi)
         double w[5], q[5];
         for (int v = 0; v < 5; ++v) w[v] = s->W[v][c];
         uint8_t m = s->chi[c];
-        ora_cons_to_prim(w, s->c.gamma[m], s->c.pc[m], q);
+        mat_cons_to_prim(&s->c, m, w, q);
         for (int v = 0; v < 5; ++v) prim6[v * s->N + c] = q[v];
         prim6[5 * s->N + c] = s->phi[c];
         if (chi) chi[c] = m;
@@ -464,8 +632,8 @@ static double dt_of(const ora_sim* s, double* const W[5], const uint8_t* chi)
         double w[5], q[5];
         for (int v = 0; v < 5; ++v) w[v] = W[v][c];
         uint8_t m = chi[c];
-        ora_cons_to_prim(w, s->c.gamma[m], s->c.pc[m], q);
-        double cs = sound_speed(q[0], q[4], s->c.gamma[m], s->c.pc[m]);
+        mat_cons_to_prim(&s->c, m, w, q);
+        double cs = mat_sound_speed(&s->c, m, q[0], q[4]);
         double lam = 0.0;
         for (int d = 0; d < 3; ++d)
             if (s->act[d]) lam += (fabs(q[1 + d]) + cs) / s->h[d];
@@ -550,7 +718,7 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                 double w[5], q[5];
                 for (int v = 0; v < 5; ++v) w[v] = W[v][c];
                 uint8_t m = chi[c];
-                ora_cons_to_prim(w, s->c.gamma[m], s->c.pc[m], q);
+                mat_cons_to_prim(&s->c, m, w, q);
                 int64_t pc = pidx(s, i, j, k);
                 for (int v = 0; v < 5; ++v) s->P[v][pc] = q[v];
                 s->P[5][pc] = phi[c];
@@ -612,7 +780,7 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                             la[v] = qa[v] + 0.5 * sa;
                             rb[v] = qb[v] - 0.5 * sb;
                         }
-                        num_flux(&s->c, la, rb, s->c.gamma[xa], s->c.pc[xa], Fr_l);
+                        num_flux(&s->c, la, rb, xa, Fr_l);
                         for (int v = 0; v < 5; ++v) Fr_u[v] = Fr_l[v];
                     } else {
                         /* FIVER: exact two-material Riemann problem along the
@@ -625,8 +793,9 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                         double in[6] = {qa[0], qa[1], qa[4], qb[0], qb[1], qb[4]};
                         double eos[4] = {s->c.gamma[xa], s->c.pc[xa], s->c.gamma[xb], s->c.pc[xb]};
                         double out[4];
-                        int32_t it;
-                        int e = ora_riemann(in, eos, s->c.rtol, s->c.maxit, out, &it);
+                        int32_t it = 0;
+                        int e = s->c.eos_general ? s->c.riemann(xa, xb, in, out)
+                                                 : ora_riemann(in, eos, s->c.rtol, s->c.maxit, out, &it);
                         s->st.riemann_solves++;
                         s->st.newton_iters += it < 0 ? -it : it;
                         if (it < 0) s->st.bisection_fallbacks++;
@@ -640,8 +809,8 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                         } else {
                             double sa[5] = {out[2], out[1], qa[2], qa[3], out[0]};
                             double sb[5] = {out[3], out[1], qb[2], qb[3], out[0]};
-                            num_flux(&s->c, qa, sa, s->c.gamma[xa], s->c.pc[xa], Fr_l);
-                            num_flux(&s->c, sb, qb, s->c.gamma[xb], s->c.pc[xb], Fr_u);
+                            num_flux(&s->c, qa, sa, xa, Fr_l);
+                            num_flux(&s->c, sb, qb, xb, Fr_u);
                             if (record && m >= 1) {
                                 ora_star r;
                                 r.pstar = out[0]; r.ustar = out[1]; r.rhoL = out[2]; r.rhoR = out[3];
@@ -693,8 +862,8 @@ static int check_state(ora_sim* s, double* const W[5], const double* phi, const 
         double w[5], q[5];
         for (int v = 0; v < 5; ++v) w[v] = W[v][c];
         uint8_t m = chi[c];
-        ora_cons_to_prim(w, s->c.gamma[m], s->c.pc[m], q);
-        if (!physical(q, s->c.pc[m]) || !isfinite(phi[c])) {
+        mat_cons_to_prim(&s->c, m, w, q);
+        if (!physical(&s->c, m, q) || !isfinite(phi[c])) {
             if (s->st.err_cell < 0) s->st.err_cell = c;
             return ORA_ERR_NONPHYSICAL;
         }
@@ -757,14 +926,14 @@ static int phase_update(ora_sim* s)
                     for (int v = 0; v < 5; ++v) q[v] = sum[v] / cnt;
                 } else {
                     for (int v = 0; v < 5; ++v) w[v] = s->W[v][c];
-                    ora_cons_to_prim(w, s->c.gamma[A], s->c.pc[A], q);
+                    mat_cons_to_prim(&s->c, A, w, q);
                     s->st.orphans++;
                 }
-                if (!physical(q, s->c.pc[B])) {
+                if (!physical(&s->c, B, q)) {
                     if (s->st.err_cell < 0) s->st.err_cell = c;
                     rc = ORA_ERR_NONPHYSICAL;
                 }
-                ora_prim_to_cons(q, s->c.gamma[B], s->c.pc[B], w);
+                mat_prim_to_cons(&s->c, B, q, w);
                 for (int v = 0; v < 5; ++v) s->W[v][c] = w[v];
             }
     memcpy(s->chi, newchi, s->N);

@@ -19,7 +19,9 @@
  *   level-set advection (eq. levelset) with third-order upwind differences;
  *   TVD Runge-Kutta in time with a CFL-based dt; and the phase update for
  *   cells whose level-set sign flipped.  Stiffened gas per material:
- *   p = (gamma-1) rho e - gamma p_c (eq. NASG_EOS with b = e_c = 0).
+ *   p = (gamma-1) rho e - gamma p_c (eq. NASG_EOS with b = e_c = 0), or a
+ *   general EOS per material (NASG, Mie-Grueneisen, JWL) whose interface
+ *   Riemann problems are solved by a caller-given function.
  *
  * Arrays are structure-of-arrays, x fastest: cell (i,j,k) is at
  * i + nx*(j + ny*k).  Material 1 occupies phi < 0.
@@ -36,6 +38,20 @@ enum { ORA_OK = 0, ORA_ERR_ARG = -1, ORA_ERR_NONPHYSICAL = -2, ORA_ERR_RIEMANN =
        ORA_ERR_NOMEM = -7 };
 enum { ORA_BC_TRANSMISSIVE = 0, ORA_BC_WALL = 1, ORA_BC_PERIODIC = 2 };
 
+/* General EOS of one material: family and parameters in the order
+ *   NASG (gamma, p_c, b, e_c), eq. NASG_EOS;
+ *   MG   (rho_0, c_0, Gamma_0, s, e_0, eta_min), appendix on equations of state;
+ *   JWL  (omega, A_1, A_2, R_1, R_2, rho_0), eq. JWL_EOS. */
+enum { ORA_EOS_NASG = 0, ORA_EOS_MG = 1, ORA_EOS_JWL = 2 };
+typedef struct {
+    int32_t family;
+    int32_t reserved;
+    double prm[7];
+} ora_eos;
+/* Star state (p*, u*, rho*_L, rho*_R) of the two-material Riemann problem
+ * in = (rho_L, u_L, p_L, rho_R, u_R, p_R) between materials ml and mr. */
+typedef int32_t (*ora_riemann_fn)(int32_t ml, int32_t mr, const double* in, double* out);
+
 typedef struct {
     int32_t nx, ny, nz;
     double lo[3], hi[3];
@@ -50,6 +66,14 @@ typedef struct {
     int32_t limiter_k;        /* Van Albada exponent k                           */
     int32_t flux;             /* ORA_FLUX_HLLC, ORA_FLUX_LLF                     */
     double ls_band;           /* > 0: level set advanced only where |phi| < band */
+    /* General equations of state (section "Equations of state"): with
+     * eos_general set, material m follows eos[m] instead of the stiffened
+     * gas (gamma[m], pc[m]), and interface faces take their star states from
+     * riemann (which returns ORA_OK, or an error code when the problem has
+     * no star state). */
+    int32_t eos_general;
+    ora_eos eos[2];
+    ora_riemann_fn riemann;
 } ora_cfg;
 
 enum { ORA_LIM_MC = 0, ORA_LIM_VA = 1, ORA_LIM_VA_MOD = 2 };
@@ -98,6 +122,12 @@ double ora_mc_slope(double dminus, double dplus, double alpha);
 double ora_va_slope(double dminus, double dplus, int32_t k, int32_t modified);
 /* HLLC flux along +x in the face frame: q = (rho, u_n, v_t1, v_t2, p). */
 void ora_hllc(const double* qL, const double* qR, double gamma, double pc, double* F5);
+/* General EOS point functions: p(rho, e), e(rho, p), c^2(rho, p) and the
+ * lowest admissible pressure of one material. */
+double ora_eos_p(const ora_eos* m, double rho, double e);
+double ora_eos_e(const ora_eos* m, double rho, double p);
+double ora_eos_c2(const ora_eos* m, double rho, double p);
+double ora_eos_floor(const ora_eos* m);
 /* Local Lax-Friedrichs flux, same conventions. */
 void ora_llf(const double* qL, const double* qR, double gamma, double pc, double* F5);
 /* Exact two-material stiffened-gas Riemann problem.

@@ -547,9 +547,8 @@ MUTANTS = [
     ("Davis speed", "double SR = fmax(uL + cL, uR + cR);", "double SR = fmax(uL + cL, uR);"),
     ("shock wave function", "return (p - s->p) * q;", "return (p - s->p) * q * 1.0001;"),
     ("rarefaction exponent", "(pow(r, (g - 1.0) / (2.0 * g)) - 1.0)", "(pow(r, (g - 1.0) / (g)) - 1.0)"),
-    ("FIVER argument order", "num_flux(&s->c, sb, qb, s->c.gamma[xb]", "num_flux(&s->c, qb, sb, s->c.gamma[xb]"),
-    ("FIVER EOS side", "num_flux(&s->c, qa, sa, s->c.gamma[xa], s->c.pc[xa]",
-     "num_flux(&s->c, qa, sa, s->c.gamma[xb], s->c.pc[xb]"),
+    ("FIVER argument order", "num_flux(&s->c, sb, qb, xb, Fr_u)", "num_flux(&s->c, qb, sb, xb, Fr_u)"),
+    ("FIVER EOS side", "num_flux(&s->c, qa, sa, xa, Fr_l)", "num_flux(&s->c, qa, sa, xb, Fr_l)"),
     ("MC limiter middle term", "B / (A + 1.0) * (theta + 1.0)", "B / A * (theta + 1.0)"),
     ("face value half slope", "la[v] = qa[v] + 0.5 * sa;", "la[v] = qa[v] + sa;"),
     ("level-set stencil", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + f[0])", "(2.0 * f[3] + 3.0 * f[2] - 6.0 * f[1] + 2.0 * f[0])"),

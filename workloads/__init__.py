@@ -96,6 +96,9 @@ class Problem:
     dt_fixed: float = 0.0
     prim: np.ndarray = field(default=None, repr=False)   # (6, nz, ny, nx)
     meta: dict = field(default_factory=dict)
+    # general EOS of materials 0 and 1 as (family, params) pairs (families
+    # and parameter order of EOS_MATERIALS); None: the stiffened gases above
+    eos: tuple = None
 
     @property
     def ncells(self) -> int:
@@ -464,3 +467,55 @@ def general_eos_problem_set(seed: int, n: int, pairs=None):
         inp[1, sel] = -0.5 * du
         inp[4, sel] = 0.5 * du
     return inp, mat, materials, names
+
+
+def _eos_of(name):
+    fam, prm = EOS_MATERIALS[name][0], list(EOS_MATERIALS[name][1])
+    return fam, prm + [0.0] * (7 - len(prm))
+
+
+def eos_shock_tube_1d(left: str, right: str, left_state, right_state, nx: int = 200, steps: int = 60,
+                      cfl: float = 0.5, x0: float = 0.5) -> Problem:
+    """1D two-material Riemann problem with general EOS on nx x 1 x 1 cells
+    of the unit line: material ``left`` (material 1, phi = x - x0 < 0) with
+    primitive state (rho, u, p) left_state, material ``right`` (material 0)
+    with right_state; transmissive ends."""
+    h = 1.0 / nx
+    n = (nx, 1, 1)
+    lo, hi = (0.0, 0.0, 0.0), (1.0, h, h)
+    x, _, _ = _centres(n, lo, hi)
+    phi = x - x0
+    L = phi < 0
+    prim = np.zeros((6, 1, 1, nx))
+    for v, k in ((0, 0), (1, 1), (4, 2)):
+        prim[v, 0, 0] = np.where(L, left_state[k], right_state[k])
+    prim[5, 0, 0] = phi
+    return Problem("eos_shock_tube_1d", n, lo, hi, gamma=(1.4, 1.4), pc=(0.0, 0.0), cfl=cfl, steps=steps,
+                   prim=prim, meta={"left": left, "right": right, "x0": x0},
+                   eos=(_eos_of(right), _eos_of(left)))
+
+
+def eos_charge(seed: int, n=(12, 11, 10), inner: str = "tnt", outer: str = "water_nasg",
+               p_inner: float = 5e9, rho_inner: float = 1630.0, rho_outer: float = 1000.0,
+               p_outer: float = 1e5, radius: float = 0.28, steps: int = 10, cfl: float = 0.4) -> Problem:
+    """3D general-EOS problem: a sphere of material ``inner`` (material 1)
+    at high pressure in material ``outer`` at rest (an underwater charge of
+    detonation products when inner is JWL), on the unit box with
+    transmissive boundaries.  Draw order: three centre offsets U(-0.05,
+    0.05); then one relative density perturbation U(-0.02, 0.02) per cell
+    of the outer material, in cell order (x fastest)."""
+    rng = SplitMix64(seed)
+    c = [0.5 + rng.uniform(-0.05, 0.05) for _ in range(3)]
+    lo, hi = (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    xs, ys, zs = _centres(n, lo, hi)
+    Z, Y, X = np.meshgrid(zs, ys, xs, indexing="ij")
+    phi = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - radius
+    jit = 1.0 + rng.uniforms(n[0] * n[1] * n[2]).reshape(n[2], n[1], n[0]) * 0.04 - 0.02
+    inside = phi < 0
+    prim = np.zeros((6, n[2], n[1], n[0]))
+    prim[0] = np.where(inside, rho_inner, rho_outer * jit)
+    prim[4] = np.where(inside, p_inner, p_outer)
+    prim[5] = phi
+    return Problem("eos_charge", tuple(n), lo, hi, gamma=(1.4, 1.4), pc=(0.0, 0.0), cfl=cfl, steps=steps,
+                   prim=prim, meta={"seed": seed, "inner": inner, "outer": outer},
+                   eos=(_eos_of(outer), _eos_of(inner)))
