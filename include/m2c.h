@@ -76,6 +76,31 @@ enum { M2C_LIM_MC = 0,           /* monotonized central, parameter limiter_alpha
  * fluxes (appendix "Numerical flux functions"). */
 enum { M2C_FLUX_HLLC = 0, M2C_FLUX_LLF = 1 };
 
+/* General equations of state.  The two-material Riemann problem of eq. 1DRiemannProblem with its own
+ * equation of state p = p(rho, e) on each side (section "Equations of
+ * state", eq. eos_all), from the families of that section and its appendix:
+ *   M2C_EOS_NASG  Noble-Abel stiffened gas, eq. NASG_EOS:
+ *                 p = (gamma - 1) rho (e - e_c) / (1 - rho b) - gamma p_c;
+ *                 prm = {gamma > 1, p_c >= 0, b >= 0, e_c}
+ *   M2C_EOS_MG    Mie-Grueneisen in the compression / small-tension /
+ *                 tensile-cutoff form of the appendix:
+ *                 p = p_R(eta) + rho_0 Gamma_0 (e - e_R(eta)), eta = 1 - rho_0/rho;
+ *                 prm = {rho_0 > 0, c_0 > 0, Gamma_0 > 0, s >= 0, e_0, eta_min < 0}
+ *   M2C_EOS_JWL   Jones-Wilkins-Lee, eq. JWL_EOS (both exponentials decaying):
+ *                 p = omega rho e + sum_i A_i (1 - omega rho/(R_i rho_0)) exp(-R_i rho_0/rho);
+ *                 prm = {omega > 0, A_1, A_2, R_1 > 0, R_2 > 0, rho_0 > 0}
+ * Unused trailing prm entries are ignored.  A state or star pressure must
+ * lie above the family's floor by 1e-12 (p_K - floor) + 1e-6 |floor| (floor:
+ * -p_c for NASG, p_min = rho_0 c_0^2 eta_min for MG, 0 for JWL); a problem
+ * whose sides separate faster than that allows has no star state. */
+enum { M2C_EOS_NASG = 0, M2C_EOS_MG = 1, M2C_EOS_JWL = 2 };
+#define M2C_EOS_MAX 8                 /* materials per call                   */
+typedef struct m2c_eos {
+    int32_t family;                   /* M2C_EOS_*                            */
+    int32_t reserved;                 /* 0                                    */
+    double prm[7];                    /* parameters, in the order above       */
+} m2c_eos;
+
 /* Problem and method parameters (the "Mesh", "Equations", "BoundaryCondition",
  * "Space", "Time" and "ExactRiemannSolution" input classes of the paper's
  * input-file table). */
@@ -107,6 +132,16 @@ typedef struct m2c_config {
                                    only where the stage-input |phi| < ls_band and
                                    held elsewhere (section "Level set method");
                                    0 (default): whole grid; batches: 0 only     */
+    int32_t eos_general;        /* 1: material m follows eos[m] (gamma, pc are
+                                   then unused): every conversion, sound speed
+                                   and flux takes that EOS, and interface faces
+                                   take the general-EOS exact Riemann solve;
+                                   FP64 precision and the acoustic guess only,
+                                   no batches.  0 (default): stiffened gases   */
+    int32_t eos_reserved;       /* 0                                            */
+    m2c_eos eos[2];             /* materials 0 and 1 when eos_general           */
+    double riemann_ds;          /* RK4 step of general-EOS isentropes (0: 0.01;
+                                   else in [1e-3, 0.5])                          */
 } m2c_config;
 
 /* Counters and timings since m2c_create (or the last m2c_reset_stats). */
@@ -345,30 +380,7 @@ int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], cons
                      void* work, int32_t iters, double band, void* hip_stream);
 
 /* ---- general-EOS exact Riemann problems (device pointers, given stream) --
- * The two-material Riemann problem of eq. 1DRiemannProblem with its own
- * equation of state p = p(rho, e) on each side (section "Equations of
- * state", eq. eos_all), from the families of that section and its appendix:
- *   M2C_EOS_NASG  Noble-Abel stiffened gas, eq. NASG_EOS:
- *                 p = (gamma - 1) rho (e - e_c) / (1 - rho b) - gamma p_c;
- *                 prm = {gamma > 1, p_c >= 0, b >= 0, e_c}
- *   M2C_EOS_MG    Mie-Grueneisen in the compression / small-tension /
- *                 tensile-cutoff form of the appendix:
- *                 p = p_R(eta) + rho_0 Gamma_0 (e - e_R(eta)), eta = 1 - rho_0/rho;
- *                 prm = {rho_0 > 0, c_0 > 0, Gamma_0 > 0, s >= 0, e_0, eta_min < 0}
- *   M2C_EOS_JWL   Jones-Wilkins-Lee, eq. JWL_EOS (both exponentials decaying):
- *                 p = omega rho e + sum_i A_i (1 - omega rho/(R_i rho_0)) exp(-R_i rho_0/rho);
- *                 prm = {omega > 0, A_1, A_2, R_1 > 0, R_2 > 0, rho_0 > 0}
- * Unused trailing prm entries are ignored.  A state or star pressure must
- * lie above the family's floor by 1e-12 (p_K - floor) + 1e-6 |floor| (floor:
- * -p_c for NASG, p_min = rho_0 c_0^2 eta_min for MG, 0 for JWL); a problem
- * whose sides separate faster than that allows has no star state. */
-enum { M2C_EOS_NASG = 0, M2C_EOS_MG = 1, M2C_EOS_JWL = 2 };
-#define M2C_EOS_MAX 8                 /* materials per call                   */
-typedef struct m2c_eos {
-    int32_t family;                   /* M2C_EOS_*                            */
-    int32_t reserved;                 /* 0                                    */
-    double prm[7];                    /* parameters, in the order above       */
-} m2c_eos;
+ * (materials: m2c_eos above) */
 
 /* n problems: in = [rho_L,u_L,p_L,rho_R,u_R,p_R][n] (SoA), mat = [2][n]
  * material indices (left row, then right row) into the host table eos[nmat]

@@ -40,6 +40,13 @@ _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerr
 NPARAM = 4801
 
 
+class Eos(C.Structure):
+    """One material of the general-EOS entry points: family and up to seven
+    parameters (NASG: gamma, p_c, b, e_c; MG: rho_0, c_0, Gamma_0, s, e_0,
+    eta_min; JWL: omega, A_1, A_2, R_1, R_2, rho_0)."""
+    _fields_ = [("family", C.c_int32), ("reserved", C.c_int32), ("prm", C.c_double * 7)]
+
+
 class Config(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3),
@@ -49,7 +56,8 @@ class Config(C.Structure):
                 ("riemann_rtol", C.c_double), ("riemann_maxit", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("tile_z", C.c_int32),
                 ("limiter", C.c_int32), ("limiter_k", C.c_int32), ("flux", C.c_int32),
-                ("ls_band", C.c_double)]
+                ("ls_band", C.c_double), ("eos_general", C.c_int32), ("eos_reserved", C.c_int32),
+                ("eos", Eos * 2), ("riemann_ds", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -73,13 +81,6 @@ class TrainOpts(C.Structure):
 
 M2C_EOS_NASG, M2C_EOS_MG, M2C_EOS_JWL = 0, 1, 2
 M2C_EOS_MAX = 8
-
-
-class Eos(C.Structure):
-    """One material of the general-EOS entry points: family and up to seven
-    parameters (NASG: gamma, p_c, b, e_c; MG: rho_0, c_0, Gamma_0, s, e_0,
-    eta_min; JWL: omega, A_1, A_2, R_1, R_2, rho_0)."""
-    _fields_ = [("family", C.c_int32), ("reserved", C.c_int32), ("prm", C.c_double * 7)]
 
 
 def eos_table(materials):
@@ -197,7 +198,8 @@ def config_default() -> Config:
 def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2, tile=None,
                rk_order=2, limiter=M2C_LIM_MC, limiter_k=2, flux=M2C_FLUX_HLLC, ls_band=0.0) -> Config:
     """Configuration for a problem description with attributes n, lo, hi,
-    gamma, pc, bc, cfl, dt_fixed (as built by the ``workloads`` module)."""
+    gamma, pc, bc, cfl, dt_fixed and, for general equations of state, eos
+    (as built by the ``workloads`` module)."""
     c = config_default()
     c.nx, c.ny, c.nz = (int(v) for v in problem.n)
     for d in range(3):
@@ -217,6 +219,15 @@ def config_for(problem, precision=M2C_PREC_FP64, rtol=1e-12, maxit=50, alpha=1.2
     c.limiter_k = limiter_k
     c.flux = flux
     c.ls_band = ls_band
+    eos = getattr(problem, "eos", None)
+    if eos is not None:
+        # general EOS of materials 0 and 1: (family, [params]) pairs
+        c.eos_general = 1
+        for m in range(2):
+            fam, prm = eos[m]
+            c.eos[m].family = fam
+            for k, v in enumerate(prm[:7]):
+                c.eos[m].prm[k] = v
     if tile is not None:
         c.tile_x, c.tile_y, c.tile_z = tile
     return c

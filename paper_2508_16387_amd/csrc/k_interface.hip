@@ -342,27 +342,43 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a) 
 //   F_lower = HLLC(W_L, W*_L; EOS of the lower cell)
 //   F_upper = HLLC(W*_R, W_R; EOS of the upper cell)
 // with the arguments ordered along the face normal.
-__device__ __forceinline__ void cell_prim(const Grid& G, const double* __restrict__ W, uint32_t c, int x,
-                                          double q[5])
+template <bool EG>
+__device__ __forceinline__ void cell_prim(const Grid& G, const eos::EosK* sEos, const double* __restrict__ W,
+                                          uint32_t c, int x, double q[5])
 {
     const uint32_t N = (uint32_t)G.N;
     double u, v, w;
-    q[4] = eos_prim(ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
-                    pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, v, w);
+    if constexpr (EG)
+        q[4] = geos_prim(sEos[x], ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
+                         u, v, w);
+    else
+        q[4] = eos_prim(ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
+                        pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, v, w);
     q[0] = ldf(W, c);
     q[1] = u;
     q[2] = v;
     q[3] = w;
 }
 
+// EG: general EOS per material (the Riemann solve of section "Equations of
+// state" with Hugoniot and isentrope wave curves, fluxes with each side's
+// EOS).
+template <bool EG>
 __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk)
 {
     __shared__ unsigned long long sCnt[3][4];
     __shared__ int sErr;
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
     DevScalars* sc = a.sc;
     // skip when an earlier kernel failed; read once so that the whole block
     // takes the same branch (this kernel's own reports may raise the flag)
     if (threadIdx.x == 0) sErr = sc->err;
+    if (EG && threadIdx.x == 0) {
+        const double* src = reinterpret_cast<const double*>(a.g.ek);
+        double* dst = reinterpret_cast<double*>(sEos);
+#pragma unroll
+        for (int t = 0; t < (int)(2 * sizeof(eos::EosK) / sizeof(double)); ++t) dst[t] = src[t];
+    }
     __syncthreads();
     if (sErr != 0) return;
     const Grid& G = a.g;
@@ -374,16 +390,22 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], c, cn, d);
         const int xa = a.chi[c], xb = a.chi[cn];
         double qa[5], qb[5];
-        cell_prim(G, a.Win, c, xa, qa);
-        cell_prim(G, a.Win, cn, xb, qb);
+        cell_prim<EG>(G, sEos, a.Win, c, xa, qa);
+        cell_prim<EG>(G, sEos, a.Win, cn, xb, qb);
         const int t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
         const double ua = qa[1 + d], ub = qb[1 + d];
         const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
         double out[4];
         bool used = false;
-        const bool hg = a.guess != nullptr;
-        int it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg,
+        const bool hg = !EG && a.guess != nullptr;
+        int it;
+        if constexpr (EG) {
+            const double in[6] = {qa[0], ua, qa[4], qb[0], ub, qb[4]};
+            it = eos::solve_pair(sEos[xa], sEos[xb], in, G.rtol, G.maxit, G.rds, out);
+        } else {
+            it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg,
                                hg ? a.guess[q] : 0.0, out, &used);
+        }
         mlp_fb += hg && !used && it != 0;
         if (it == 0) {
             report_error(&sc->err, &sc->err_cell, ST_RIEMANN, c);
@@ -393,10 +415,15 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         fallbacks += it < 0;
         const double ps = out[0], us = out[1];
         double Fl[5], Fu[5];
-        num_flux<double>(G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA,
-                         pick(G.gpc, xa), pick(G.inv_gm1, xa), Fl);
-        num_flux<double>(G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB,
-                         pick(G.gpc, xb), pick(G.inv_gm1, xb), Fu);
+        if constexpr (EG) {
+            geos_flux(sEos[xa], G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, Fl);
+            geos_flux(sEos[xb], G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], Fu);
+        } else {
+            num_flux<double>(G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA,
+                             pick(G.gpc, xa), pick(G.inv_gm1, xa), Fl);
+            num_flux<double>(G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB,
+                             pick(G.gpc, xb), pick(G.inv_gm1, xb), Fu);
+        }
         const long long Q = a.qcap;
         // face frame (mass, normal, t1, t2, energy) -> global components
         a.fluxF[0 * Q + q] = Fl[0];
@@ -446,7 +473,12 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
 
 __global__ __launch_bounds__(256) void k_fiver(const IfaceArgs a, int record)
 {
-    fiver_body(a, record, blockIdx.x, gridDim.x);
+    fiver_body<false>(a, record, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_fiver_eos(const IfaceArgs a, int record)
+{
+    fiver_body<true>(a, record, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
@@ -454,7 +486,10 @@ hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
     long long nb = (a.qcap + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
+    if (a.g.eosg)
+        hipLaunchKernelGGL(k_fiver_eos, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -468,11 +503,14 @@ hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
 // with B's equation of state.  Without such a face it keeps its primitive
 // state (an "orphan").  The new state also enters the next step's CFL
 // maximum.
+template <bool EG>
 __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk)
 {
     DevScalars* sc = a.sc;
-    if (sc->err != 0) return;
     const Grid& G = a.g;
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
+    if constexpr (EG) geos_stage(G, sEos);
+    if (sc->err != 0) return;
     const int n = sc->nflip;
     const long long N = G.N, sxy = (long long)G.nx * G.ny, Q = a.qcap;
     const long long cstr[3] = {1, G.nx, sxy};
@@ -520,15 +558,18 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk
             for (int v = 0; v < 5; ++v) q[v] = sum[v] / cnt;
         } else {
             double u, vv, w;
-            q[4] = eos_prim(a.W[c], a.W[N + c], a.W[2 * N + c], a.W[3 * N + c], a.W[4 * N + c],
-                            pick(G.gamma, A) - 1.0, pick(G.gpc, A), u, vv, w);
+            if constexpr (EG)
+                q[4] = geos_prim(sEos[A], a.W[c], a.W[N + c], a.W[2 * N + c], a.W[3 * N + c], a.W[4 * N + c], u, vv, w);
+            else
+                q[4] = eos_prim(a.W[c], a.W[N + c], a.W[2 * N + c], a.W[3 * N + c], a.W[4 * N + c],
+                                pick(G.gamma, A) - 1.0, pick(G.gpc, A), u, vv, w);
             q[0] = a.W[c];
             q[1] = u;
             q[2] = vv;
             q[3] = w;
             ++orphans;
         }
-        bool ok = q[0] > 0.0 && q[4] + pick(G.pc, B) > 0.0;
+        bool ok = EG ? geos_ok(sEos[B], q[0], q[4]) : q[0] > 0.0 && q[4] + pick(G.pc, B) > 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) ok = ok && isfinite(q[v]);
         if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
@@ -536,9 +577,10 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk
         a.W[N + c] = q[0] * q[1];
         a.W[2 * N + c] = q[0] * q[2];
         a.W[3 * N + c] = q[0] * q[3];
-        a.W[4 * N + c] = eos_energy<double>(q[0], q[1], q[2], q[3], q[4], pick(G.gpc, B), pick(G.inv_gm1, B));
+        if constexpr (EG) a.W[4 * N + c] = geos_energy(sEos[B], q[0], q[1], q[2], q[3], q[4]);
+        else a.W[4 * N + c] = eos_energy<double>(q[0], q[1], q[2], q[3], q[4], pick(G.gpc, B), pick(G.inv_gm1, B));
         if (ok) {
-            const double cs = sqrt(pick(G.gamma, B) * (q[4] + pick(G.pc, B)) / q[0]);
+            const double cs = EG ? sqrt(geos_c2(sEos[B], q[0], q[4])) : sqrt(pick(G.gamma, B) * (q[4] + pick(G.pc, B)) / q[0]);
             double l = 0.0;
             for (int d = 0; d < 3; ++d)
                 if (G.act[d]) l += (fabs(q[1 + d]) + cs) * G.rh[d];
@@ -555,13 +597,17 @@ __device__ __forceinline__ void phase_body(const PhaseArgs& a, int blk, int nblk
     }
 }
 
-__global__ __launch_bounds__(256) void k_phase(const PhaseArgs a) { phase_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void k_phase(const PhaseArgs a) { phase_body<false>(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(256) void k_phase_eos(const PhaseArgs a) { phase_body<true>(a, blockIdx.x, gridDim.x); }
 
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
 {
     long long nb = (a.g.N + 255) / 256;
     if (nb > 256) nb = 256;
-    hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
+    if (a.g.eosg)
+        hipLaunchKernelGGL(k_phase_eos, dim3((unsigned)nb), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_phase, dim3((unsigned)nb), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -571,14 +617,22 @@ hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
 // forms dt from that maximum and closes the previous step comes after.
 __global__ __launch_bounds__(COMPACT_THREADS) void k_count_phase(const IfaceArgs a, const PhaseArgs pa)
 {
-    phase_body(pa, blockIdx.x, gridDim.x);
+    phase_body<false>(pa, blockIdx.x, gridDim.x);
+    count_body(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count_phase_eos(const IfaceArgs a, const PhaseArgs pa)
+{
+    phase_body<true>(pa, blockIdx.x, gridDim.x);
     count_body(a, blockIdx.x);
 }
 
 hipError_t launch_compact(const IfaceArgs& a, const PhaseArgs* prev_phase, bool end_prev, bool begin,
                           double dt_imposed, hipStream_t s)
 {
-    if (prev_phase)
+    if (prev_phase && a.g.eosg)
+        hipLaunchKernelGGL(k_count_phase_eos, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a, *prev_phase);
+    else if (prev_phase)
         hipLaunchKernelGGL(k_count_phase, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a, *prev_phase);
     else
         hipLaunchKernelGGL(k_count, dim3(a.nblk), dim3(COMPACT_THREADS), 0, s, a);
@@ -645,7 +699,7 @@ constexpr int PHASE_BLOCKS_PER_RUN = 8;
 __global__ __launch_bounds__(64) void k_fiver_batch(const RunDesc* __restrict__ runs, int stage)
 {
     const int r = blockIdx.x / FIVER_BLOCKS_PER_RUN, b = blockIdx.x % FIVER_BLOCKS_PER_RUN;
-    fiver_body(iface_of_run(runs[r], stage), stage == 2, b, FIVER_BLOCKS_PER_RUN);
+    fiver_body<false>(iface_of_run(runs[r], stage), stage == 2, b, FIVER_BLOCKS_PER_RUN);
 }
 
 hipError_t launch_fiver_batch(const RunDesc* runs, int nruns, int stage, hipStream_t s)
@@ -669,7 +723,7 @@ __global__ __launch_bounds__(256) void k_phase_batch(const RunDesc* __restrict__
     a.star = R.star;
     a.qcap = R.qcap;
     a.sc = R.sc;
-    phase_body(a, b, PHASE_BLOCKS_PER_RUN);
+    phase_body<false>(a, b, PHASE_BLOCKS_PER_RUN);
 }
 
 hipError_t launch_phase_batch(const RunDesc* runs, int nruns, hipStream_t s)

@@ -64,10 +64,13 @@ hipError_t launch_end_batch(const RunDesc* runs, int nruns, int stages, hipStrea
 
 // max_i lambda_i of a state (the CFL maximum of the first step after a
 // state is set); non-negative doubles order like their bit patterns.
+template <bool EG>
 __global__ __launch_bounds__(256) void k_lambda(const Grid G, const double* __restrict__ W,
                                                 const uint8_t* __restrict__ chi, DevScalars* sc)
 {
     __shared__ double sRed[4];
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
+    if constexpr (EG) geos_stage(G, sEos);
     const long long N = G.N;
     double lam = 0.0;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
@@ -75,9 +78,15 @@ __global__ __launch_bounds__(256) void k_lambda(const Grid G, const double* __re
         const int x = chi[c];
         double u, v, w;
         const double r = W[c];
-        const double p = eos_prim(r, W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
-                                  pick(G.gpc, x), u, v, w);
-        const double cs = sqrt(pick(G.gamma, x) * (p + pick(G.pc, x)) / r);
+        double cs;
+        if constexpr (EG) {
+            const double p = geos_prim(sEos[x], r, W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], u, v, w);
+            cs = sqrt(geos_c2(sEos[x], r, p));
+        } else {
+            const double p = eos_prim(r, W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
+                                      pick(G.gpc, x), u, v, w);
+            cs = sqrt(pick(G.gamma, x) * (p + pick(G.pc, x)) / r);
+        }
         double l = 0.0;
         if (G.act[0]) l += (fabs(u) + cs) * G.rh[0];
         if (G.act[1]) l += (fabs(v) + cs) * G.rh[1];
@@ -99,32 +108,41 @@ __global__ void k_zero_lam(DevScalars* sc) { sc->lam_bits = 0ull; }
 hipError_t launch_lambda(const Grid& g, const double* W, const uint8_t* chi, DevScalars* sc, hipStream_t s)
 {
     hipLaunchKernelGGL(k_zero_lam, dim3(1), dim3(1), 0, s, sc);
-    hipLaunchKernelGGL(k_lambda, dim3(grid_for(g.N, 256, 4096)), dim3(256), 0, s, g, W, chi, sc);
+    if (g.eosg)
+        hipLaunchKernelGGL(k_lambda<true>, dim3(grid_for(g.N, 256, 4096)), dim3(256), 0, s, g, W, chi, sc);
+    else
+        hipLaunchKernelGGL(k_lambda<false>, dim3(grid_for(g.N, 256, 4096)), dim3(256), 0, s, g, W, chi, sc);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Primitive [rho,u,v,w,p,phi][N] -> conservative state and material ids,
-// with the admissibility check (rho > 0, p + p_c > 0, all finite).  The
-// first failing cell (smallest index) is reported through err_cell.
+// with the admissibility check (rho > 0, p + p_c > 0, all finite; with a
+// general EOS p above the material's floor and c^2 > 0).  The first failing
+// cell (smallest index) is reported through err_cell.
+template <bool EG>
 __global__ __launch_bounds__(256) void k_prim_to_cons(const Grid G, const double* __restrict__ P,
                                                       double* __restrict__ W, uint8_t* __restrict__ chi,
                                                       DevScalars* sc)
 {
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
+    if constexpr (EG) geos_stage(G, sEos);
     const long long N = G.N;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
          c += (long long)gridDim.x * blockDim.x) {
         const double r = P[c], u = P[N + c], v = P[2 * N + c], w = P[3 * N + c], p = P[4 * N + c];
         const double phi = P[5 * N + c];
         const int x = phi < 0.0 ? 1 : 0;
+        const bool adm = EG ? geos_ok(sEos[x], r, p) : r > 0.0 && p + pick(G.pc, x) > 0.0;
         const bool ok = isfinite(r) && isfinite(u) && isfinite(v) && isfinite(w) && isfinite(p) &&
-                        isfinite(phi) && r > 0.0 && p + pick(G.pc, x) > 0.0;
+                        isfinite(phi) && adm;
         if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
         W[c] = r;
         W[N + c] = r * u;
         W[2 * N + c] = r * v;
         W[3 * N + c] = r * w;
-        W[4 * N + c] = eos_energy<double>(r, u, v, w, p, pick(G.gpc, x), pick(G.inv_gm1, x));
+        if constexpr (EG) W[4 * N + c] = geos_energy(sEos[x], r, u, v, w, p);
+        else W[4 * N + c] = eos_energy<double>(r, u, v, w, p, pick(G.gpc, x), pick(G.inv_gm1, x));
         W[5 * N + c] = phi;
         chi[c] = (uint8_t)x;
     }
@@ -133,20 +151,27 @@ __global__ __launch_bounds__(256) void k_prim_to_cons(const Grid G, const double
 hipError_t launch_prim_to_cons(const Grid& g, const double* prim6, double* W, uint8_t* chi, DevScalars* sc,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_prim_to_cons, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, prim6, W, chi, sc);
+    if (g.eosg)
+        hipLaunchKernelGGL(k_prim_to_cons<true>, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, prim6, W, chi, sc);
+    else
+        hipLaunchKernelGGL(k_prim_to_cons<false>, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, prim6, W, chi, sc);
     return hipGetLastError();
 }
 
+template <bool EG>
 __global__ __launch_bounds__(256) void k_cons_to_prim(const Grid G, const double* __restrict__ W,
                                                       const uint8_t* __restrict__ chi, double* __restrict__ P)
 {
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
+    if constexpr (EG) geos_stage(G, sEos);
     const long long N = G.N;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < N;
          c += (long long)gridDim.x * blockDim.x) {
         const int x = chi[c];
-        double u, v, w;
-        const double p = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
-                                  pick(G.gpc, x), u, v, w);
+        double u, v, w, p;
+        if constexpr (EG) p = geos_prim(sEos[x], W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], u, v, w);
+        else p = eos_prim(W[c], W[N + c], W[2 * N + c], W[3 * N + c], W[4 * N + c], pick(G.gamma, x) - 1.0,
+                          pick(G.gpc, x), u, v, w);
         P[c] = W[c];
         P[N + c] = u;
         P[2 * N + c] = v;
@@ -158,7 +183,10 @@ __global__ __launch_bounds__(256) void k_cons_to_prim(const Grid G, const double
 
 hipError_t launch_cons_to_prim(const Grid& g, const double* W, const uint8_t* chi, double* prim6, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_cons_to_prim, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, W, chi, prim6);
+    if (g.eosg)
+        hipLaunchKernelGGL(k_cons_to_prim<true>, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, W, chi, prim6);
+    else
+        hipLaunchKernelGGL(k_cons_to_prim<false>, dim3(grid_for(g.N, 256)), dim3(256), 0, s, g, W, chi, prim6);
     return hipGetLastError();
 }
 

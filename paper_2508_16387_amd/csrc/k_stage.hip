@@ -85,6 +85,7 @@ bool stage_tile_supported(int tx, int ty)
 
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s)
 {
+    if (a.g.eosg) return mixed ? hipErrorInvalidValue : launch_stage_eos(stage, tx, ty, a, s);
     if (a.g.limiter != LIM_MC || a.g.flux != FLUX_HLLC || a.g.ls_band > 0.0)
         return launch_stage_opts(stage, mixed, tx, ty, a, s);
 #define M2C_TILE(TX_, TY_)                                                              \

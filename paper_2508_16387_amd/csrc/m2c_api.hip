@@ -108,9 +108,20 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
         for (int s = 0; s < 2; ++s)
             if (c->bc[2 * d + s] < 0 || c->bc[2 * d + s] > 2) return snprintf(why, n, "bad bc"), false;
     }
-    for (int m = 0; m < 2; ++m)
-        if (!(c->gamma[m] > 1.0) || !(c->pc[m] >= 0.0) || !std::isfinite(c->pc[m]))
-            return snprintf(why, n, "material %d needs gamma > 1 and p_c >= 0", m), false;
+    if (c->eos_general != 0 && c->eos_general != 1) return snprintf(why, n, "eos_general must be 0 or 1"), false;
+    if (c->eos_general) {
+        eos::EosTable t;
+        if (!eos::prepare(2, c->eos, t)) return snprintf(why, n, "invalid general EOS parameters"), false;
+        if (c->precision != M2C_PREC_FP64) return snprintf(why, n, "general EOS runs in FP64 only"), false;
+        if (!(c->riemann_ds == 0.0 || (c->riemann_ds >= 1e-3 && c->riemann_ds <= 0.5)))
+            return snprintf(why, n, "riemann_ds must be 0 or in [1e-3, 0.5]"), false;
+        if ((c->tile_x || c->tile_y) && !stage_tile_supported_eos(c->tile_x, c->tile_y))
+            return snprintf(why, n, "general EOS: stage tile must be 16x16 or 64x2"), false;
+    } else {
+        for (int m = 0; m < 2; ++m)
+            if (!(c->gamma[m] > 1.0) || !(c->pc[m] >= 0.0) || !std::isfinite(c->pc[m]))
+                return snprintf(why, n, "material %d needs gamma > 1 and p_c >= 0", m), false;
+    }
     if (!(c->limiter_alpha >= 0.0 && c->limiter_alpha <= 2.0))
         return snprintf(why, n, "limiter alpha must lie in [0, 2]"), false;
     if (c->limiter < M2C_LIM_MC || c->limiter > M2C_LIM_VAN_ALBADA_MOD) return snprintf(why, n, "bad limiter"), false;
@@ -163,6 +174,21 @@ void fill_grid(Grid& g, const m2c_config& c)
     g.limk = c.limiter_k;
     g.flux = c.flux;
     g.ls_band = c.ls_band;
+    g.eosg = c.eos_general;
+    g.rds = c.riemann_ds > 0.0 ? c.riemann_ds : 0.01;
+    if (c.eos_general) {
+        eos::EosTable t;
+        if (eos::prepare(2, c.eos, t)) {
+            g.ek[0] = t.m[0];
+            g.ek[1] = t.m[1];
+        }
+        // the stiffened-gas fields stay valid numbers (unused)
+        for (int m = 0; m < 2; ++m) {
+            g.gamma[m] = 1.4;
+            g.pc[m] = g.gpc[m] = 0.0;
+            g.inv_gm1[m] = 2.5;
+        }
+    }
 }
 
 // Reset the error state of the device scalars (host mirror -> device).
@@ -438,6 +464,8 @@ void m2c_config_default(m2c_config* c)
     c->limiter_k = 2;
     c->flux = M2C_FLUX_HLLC;
     c->ls_band = 0.0;
+    c->eos_general = 0;
+    c->riemann_ds = 0.0;
 }
 
 const char* m2c_strerror(int status) { return status_name(status); }
@@ -756,8 +784,11 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
 
 int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
 {
-    static const int cands[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {16, 15, 8}, {32, 7, 8}, {16, 15, 4}};
+    static const int cands_sg[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {16, 15, 8}, {32, 7, 8}, {16, 15, 4}};
+    static const int cands_eos[][3] = {{16, 16, 8}, {16, 16, 4}};
     if (!c || steps < 1) return M2C_ERR_ARG;
+    const int(*cands)[3] = c->g.eosg ? cands_eos : cands_sg;
+    const int ncand = c->g.eosg ? 2 : 6;
     if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
     HIPCHK(c, hipSetDevice(c->device));
     int rc = pull_scalars(c);
@@ -801,7 +832,8 @@ int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (!rc && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = set_err(c, M2C_ERR_DEVICE, "event create");
-    for (const auto& cand : cands) {
+    for (int ci = 0; ci < ncand; ++ci) {
+        const int* cand = cands[ci];
         if (rc) break;
         set_tile(cand[0], cand[1], cand[2]);
         if ((rc = restore()) || (rc = run_steps(c, 1, 0.0, nullptr)) || (rc = restore())) break;
@@ -846,6 +878,7 @@ int m2c_set_guess(m2c_ctx* c, const m2c_mlp* m)
         c->use_mlp = false;
         return M2C_OK;
     }
+    if (c->g.eosg) return set_err(c, M2C_ERR_ARG, "the learned guess is for stiffened gases only");
     const MlpDev* src = m2c_mlp_dev(m);
     if (!c->mlp.master) {
         HIPCHK(c, hipMalloc((void**)&c->mlp.master, MLP_NPARAM * sizeof(float)));

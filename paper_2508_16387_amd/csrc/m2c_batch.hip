@@ -252,6 +252,7 @@ int m2c_batch_create(int32_t n, const m2c_config* cfgs, m2c_batch** out)
         if (m2c_validate_config(&cfgs[r]) != M2C_OK) return M2C_ERR_ARG;
         if (cfgs[r].precision != cfgs[0].precision) return M2C_ERR_ARG;
         if (cfgs[r].rk_order != 2) return M2C_ERR_ARG;         // the batched kernels are TVD-RK2
+        if (cfgs[r].eos_general) return M2C_ERR_ARG;           // and stiffened gases
         if (cfgs[r].limiter != M2C_LIM_MC || cfgs[r].flux != M2C_FLUX_HLLC || cfgs[r].ls_band != 0.0)
             return M2C_ERR_ARG;                                 // with MC, HLLC, the whole grid
     }

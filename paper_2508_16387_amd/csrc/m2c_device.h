@@ -134,16 +134,13 @@ __device__ __forceinline__ T lim_slope(int limiter, int k, T dm, T dp, T alpha)
 // rho_K (S_K - u_K)/(S_K - S_*) [1, S_*, v_t1, v_t2, E*_K] with Toro's E*.
 // The case selection reproduces the four cases of the appendix in the
 // same order, without divergent branches.
+// hllc_ce takes each state's 1/rho, sound speed and total energy per unit
+// volume (all the flux needs of the EOS); hllc computes them for a
+// stiffened gas.
 template <typename T>
-__device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
-                                     T rR, T uR, T aR, T bR, T pR,
-                                     T g, T pc, T gpc, T inv_gm1, T F[5])
+__device__ __forceinline__ void hllc_ce(T rL, T uL, T aL, T bL, T pL, T riL, T cL, T EL,
+                                        T rR, T uR, T aR, T bR, T pR, T riR, T cR, T ER, T F[5])
 {
-    const T riL = rcp_nr(rL), riR = rcp_nr(rR);
-    const T cL = sqrt_nr(g * (pL + pc) * riL);
-    const T cR = sqrt_nr(g * (pR + pc) * riR);
-    const T EL = eos_energy<T>(rL, uL, aL, bL, pL, gpc, inv_gm1);
-    const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
     const T SL = fmin(uL - cL, uR - cR);
     const T SR = fmax(uL + cL, uR + cR);
     const T dL = rL * (SL - uL), dR = rR * (SR - uR);
@@ -181,11 +178,37 @@ __device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
     }
 }
 
+template <typename T>
+__device__ __forceinline__ void hllc(T rL, T uL, T aL, T bL, T pL,
+                                     T rR, T uR, T aR, T bR, T pR,
+                                     T g, T pc, T gpc, T inv_gm1, T F[5])
+{
+    const T riL = rcp_nr(rL), riR = rcp_nr(rR);
+    const T cL = sqrt_nr(g * (pL + pc) * riL);
+    const T cR = sqrt_nr(g * (pR + pc) * riR);
+    const T EL = eos_energy<T>(rL, uL, aL, bL, pL, gpc, inv_gm1);
+    const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
+    hllc_ce<T>(rL, uL, aL, bL, pL, riL, cL, EL, rR, uR, aR, bR, pR, riR, cR, ER, F);
+}
+
 // ------------------------------------------------ local Lax-Friedrichs ----
 // Appendix "Local Lax-Friedrichs flux" (eq. Lax-Friedrichs), face frame as
 // for hllc: the mean of the physical fluxes minus half the fastest wave
 // speed max(|u_L| + c_L, |u_R| + c_R) times the jump of the conservative
 // state.
+template <typename T>
+__device__ __forceinline__ void llf_ce(T rL, T uL, T aL, T bL, T pL, T cL, T EL, T rR, T uR, T aR, T bR, T pR,
+                                       T cR, T ER, T F[5])
+{
+    const T lm = fmax(fabs(uL) + cL, fabs(uR) + cR);
+    const T mL = rL * uL, mR = rR * uR;
+    F[0] = T(0.5) * (mL + mR) - T(0.5) * lm * (rR - rL);
+    F[1] = T(0.5) * (mL * uL + pL + (mR * uR + pR)) - T(0.5) * lm * (mR - mL);
+    F[2] = T(0.5) * (mL * aL + mR * aR) - T(0.5) * lm * (rR * aR - rL * aL);
+    F[3] = T(0.5) * (mL * bL + mR * bR) - T(0.5) * lm * (rR * bR - rL * bL);
+    F[4] = T(0.5) * ((EL + pL) * uL + (ER + pR) * uR) - T(0.5) * lm * (ER - EL);
+}
+
 template <typename T>
 __device__ __forceinline__ void llf(T rL, T uL, T aL, T bL, T pL, T rR, T uR, T aR, T bR, T pR, T g, T pc,
                                     T gpc, T inv_gm1, T F[5])
@@ -194,13 +217,68 @@ __device__ __forceinline__ void llf(T rL, T uL, T aL, T bL, T pL, T rR, T uR, T 
     const T ER = eos_energy<T>(rR, uR, aR, bR, pR, gpc, inv_gm1);
     const T cL = sqrt_nr(g * (pL + pc) * rcp_nr(rL));
     const T cR = sqrt_nr(g * (pR + pc) * rcp_nr(rR));
-    const T lm = fmax(fabs(uL) + cL, fabs(uR) + cR);
-    const T mL = rL * uL, mR = rR * uR;
-    F[0] = T(0.5) * (mL + mR) - T(0.5) * lm * (rR - rL);
-    F[1] = T(0.5) * (mL * uL + pL + (mR * uR + pR)) - T(0.5) * lm * (mR - mL);
-    F[2] = T(0.5) * (mL * aL + mR * aR) - T(0.5) * lm * (rR * aR - rL * aL);
-    F[3] = T(0.5) * (mL * bL + mR * bR) - T(0.5) * lm * (rR * bR - rL * bL);
-    F[4] = T(0.5) * ((EL + pL) * uL + (ER + pR) * uR) - T(0.5) * lm * (ER - EL);
+    llf_ce<T>(rL, uL, aL, bL, pL, cL, EL, rR, uR, aR, bR, pR, cR, ER, F);
+}
+
+// ------------------------------------------------------- general EOS -----
+// A material with a general EOS (section "Equations of state": NASG,
+// Mie-Grueneisen, JWL; FP64 only).  Conservative -> primitive: returns p.
+__device__ __forceinline__ double geos_prim(const eos::EosK& m, double r, double mx, double my, double mz,
+                                            double E, double& u, double& v, double& w)
+{
+    const double ri = 1.0 / r;
+    u = mx * ri;
+    v = my * ri;
+    w = mz * ri;
+    const double ke = 0.5 * (mx * u + my * v + mz * w);
+    return eos::eos_p(m, ri, (E - ke) * ri);
+}
+
+// Total energy per unit volume of a primitive state.
+__device__ __forceinline__ double geos_energy(const eos::EosK& m, double r, double u, double v, double w, double p)
+{
+    return r * eos::eos_e(m, 1.0 / r, p) + 0.5 * r * (u * u + v * v + w * w);
+}
+
+// c^2 of a state (<= 0 or NaN where the EOS is not hyperbolic).
+__device__ __forceinline__ double geos_c2(const eos::EosK& m, double r, double p)
+{
+    return eos::eos_c2(m, 1.0 / r, p);
+}
+
+// Admissible primitive state: finite, rho > 0, p above the floor, c^2 > 0.
+__device__ __forceinline__ bool geos_ok(const eos::EosK& m, double r, double p)
+{
+    return r > 0.0 && p > m.k[eos::KFLOOR] && geos_c2(m, r, p) > 0.0;
+}
+
+// Numerical flux between two states of one general-EOS material.
+__device__ __forceinline__ void geos_flux(const eos::EosK& m, int flux, double rL, double uL, double aL, double bL,
+                                          double pL, double rR, double uR, double aR, double bR, double pR,
+                                          double F[5])
+{
+    const double riL = 1.0 / rL, riR = 1.0 / rR;
+    const double cL = sqrt(eos::eos_c2(m, riL, pL)), cR = sqrt(eos::eos_c2(m, riR, pR));
+    const double EL = rL * eos::eos_e(m, riL, pL) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+    const double ER = rR * eos::eos_e(m, riR, pR) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+    if (flux == FLUX_LLF) llf_ce<double>(rL, uL, aL, bL, pL, cL, EL, rR, uR, aR, bR, pR, cR, ER, F);
+    else hllc_ce<double>(rL, uL, aL, bL, pL, riL, cL, EL, rR, uR, aR, bR, pR, riR, cR, ER, F);
+}
+
+// Copy of the two materials' general EOS into LDS (per-lane material ids
+// then index LDS); every thread of the block calls it before any exit, and
+// it ends with a barrier.
+__device__ __forceinline__ void geos_stage(const Grid& G, eos::EosK* s)
+{
+    constexpr int W = (int)(sizeof(eos::EosK) / sizeof(double));
+    static_assert(sizeof(eos::EosK) % sizeof(double) == 0, "EosK layout");
+    const double* src = reinterpret_cast<const double*>(G.ek);
+    double* dst = reinterpret_cast<double*>(s);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int t = 0; t < 2 * W; ++t) dst[t] = src[t];
+    }
+    __syncthreads();
 }
 
 // Numerical flux of the configuration (flux uniform over a launch).

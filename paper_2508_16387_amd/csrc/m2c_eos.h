@@ -572,7 +572,8 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
         if (!(vn > lo && vn < hi)) vn = 0.5 * (lo + hi);
         v = vn;
     }
-    if (!ok || !(v > m.k[KVMIN]) || !(v < vK)) return false;
+    // (v = v_K: a shock too weak for the volume to change in FP64)
+    if (!ok || !(v > m.k[KVMIN]) || !(v <= vK)) return false;
     K.vh = v;
     const double dp = p - K.p, dvol = vK - v;
     w.f = sqrt(dp * dvol);
@@ -631,21 +632,18 @@ M2C_HD inline double bisect(double lo, double hi, double base)
     return b > 1e3 * a ? base + sqrt(a * b) : 0.5 * (lo + hi);
 }
 
-// One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials ml, mr;
+// One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials mL, mR;
 // res = (p*, u*, rho*_L, rho*_R) or NaN; returns the Newton steps (negative
 // after a bisection step; 0: no star state or an inadmissible input).
-M2C_HD inline int solve_one(const EosTable& tab, int ml, int mr, const double* q, double rtol, int maxit,
-                            double hmax, double* res)
+M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, double rtol, int maxit, double hmax,
+                             double* res)
 {
     for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
     int its = 0;
     Side L, R;
-    bool ok = ml >= 0 && ml < tab.n && mr >= 0 && mr < tab.n;
-    ok = ok && side_init(tab.m[ok ? ml : 0], q[0], q[2], L);
-    ok = ok && side_init(tab.m[ok ? mr : 0], q[3], q[5], R);
+    bool ok = side_init(mL, q[0], q[2], L);
+    ok = ok && side_init(mR, q[3], q[5], R);
     if (ok) {
-        const EosK& mL = tab.m[ml];
-        const EosK& mR = tab.m[mr];
         const double uL = q[1], uR = q[4], du = uR - uL;
         const double pfl = fmax(L.fl + floor_margin(L), R.fl + floor_margin(R));
         const double base = fmax(L.fl, R.fl);
@@ -707,6 +705,17 @@ M2C_HD inline int solve_one(const EosTable& tab, int ml, int mr, const double* q
         }
     }
     return ok ? its : 0;
+}
+
+// The same for materials ml, mr of a table (0 for an index out of range).
+M2C_HD inline int solve_one(const EosTable& tab, int ml, int mr, const double* q, double rtol, int maxit,
+                            double hmax, double* res)
+{
+    if (ml < 0 || ml >= tab.n || mr < 0 || mr >= tab.n) {
+        for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
+        return 0;
+    }
+    return solve_pair(tab.m[ml], tab.m[mr], q, rtol, maxit, hmax, res);
 }
 
 // Table of prepared constants; false for invalid parameters.

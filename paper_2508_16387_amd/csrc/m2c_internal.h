@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "m2c_eos.h"
+
 namespace m2c {
 
 enum { BC_TRANSMISSIVE = 0, BC_WALL = 1, BC_PERIODIC = 2 };
@@ -47,6 +49,9 @@ struct Grid {
     int limiter, limk;             // slope limiter (M2C_LIM_*) and Van Albada exponent
     int flux;                      // numerical flux (M2C_FLUX_*)
     double ls_band;                // > 0: level set advanced only where |phi| < ls_band
+    int eosg;                      // materials follow ek[] (general EOS)
+    double rds;                    // RK4 step of general-EOS isentropes
+    eos::EosK ek[2];               // prepared general EOS of materials 0 and 1
 };
 
 // Device buffers of one simulation.

@@ -77,6 +77,9 @@ bool stage_tile_supported(int tx, int ty);
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
 // the same with the configured limiter and flux (any, including MC + HLLC)
 hipError_t launch_stage_opts(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
+// general-EOS stage kernels (FP64; tiles 16x16 and 64x2)
+bool stage_tile_supported_eos(int tx, int ty);
+hipError_t launch_stage_eos(int stage, int tx, int ty, const StageArgs& a, hipStream_t s);
 // items: (run, tile) pairs over all runs of a batch
 hipError_t launch_stage_batch(int stage, bool mixed, int tx, int ty, const RunDesc* runs, const int2* items,
                               int nitems, hipStream_t s);

@@ -68,7 +68,7 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 // configured (Van Albada, local Lax-Friedrichs, narrow band); otherwise MC,
 // HLLC and the whole grid, fixed at compile time so that the default kernels
 // carry neither the code nor the registers of the other options.
-template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS>
+template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS, bool EG = false>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
     // Stage kinds: 1 first stage of RK2 / RK3 (W_out = W_in + dt R); 2 last
@@ -97,8 +97,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // scalar register pairs.  Measured faster for the single-grid FP64
     // kernel; the mixed form and the batched kernel (whose register budget
     // it would exceed) keep the selects.
-    constexpr bool LMAT = LM;
+    constexpr bool LMAT = LM && !EG;
     __shared__ double sMat[2][MAT_FIELDS];
+    // EG: general EOS of the two materials (FP64 form only)
+    static_assert(!EG || sizeof(TF) == sizeof(double), "general EOS runs in FP64");
+    __shared__ eos::EosK sEos[EG ? 2 : 1];
 
     // Skip the tile when an earlier kernel of the step failed; the flag is
     // read once per block so that the whole block takes the same branch
@@ -107,6 +110,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     const Grid& G = a.g;
     __syncthreads();
     if (threadIdx.x == 0) sErr = sc->err;
+    if (EG && threadIdx.x == 0) {
+        const double* src = reinterpret_cast<const double*>(a.g.ek);
+        double* dst = reinterpret_cast<double*>(sEos);
+#pragma unroll
+        for (int t = 0; t < (int)(2 * sizeof(eos::EosK) / sizeof(double)); ++t) dst[t] = src[t];
+    }
     if (LMAT && threadIdx.x < 2) {
         const int m = threadIdx.x;
         sMat[m][MAT_GAMMA] = G.gamma[m];
@@ -167,8 +176,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     };
     // Primitives of a raw state, velocities mirrored at wall images.
     auto to_prim = [&](const double w[6], uint8_t x, bool mz, TF q[5]) {
-        double u, vv, ww;
-        const double p = eos_prim(w[0], w[1], w[2], w[3], w[4], mat(x, MAT_GM1), mat(x, MAT_GPC), u, vv, ww);
+        double u, vv, ww, p;
+        if constexpr (EG) p = geos_prim(sEos[x], w[0], w[1], w[2], w[3], w[4], u, vv, ww);
+        else p = eos_prim(w[0], w[1], w[2], w[3], w[4], mat(x, MAT_GM1), mat(x, MAT_GPC), u, vv, ww);
         q[0] = TF(w[0]);
         q[1] = TF(mirx ? -u : u);
         q[2] = TF(miry ? -vv : vv);
@@ -190,13 +200,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                      uint8_t xu, TF F[5]) -> int {
         if (xl == xu) {
             TF Fr[5];
-            const TF g = TF(mat(xl, MAT_GAMMA)), pc = TF(mat(xl, MAT_PC)), gpc = TF(mat(xl, MAT_GPC)),
-                     igm1 = TF(mat(xl, MAT_IGM1));
             // face frame: normal w, tangential u, v
-            num_flux<TF>(flux, ql[0] + TF(0.5) * sl[0], ql[3] + TF(0.5) * sl[3], ql[1] + TF(0.5) * sl[1],
-                     ql[2] + TF(0.5) * sl[2], ql[4] + TF(0.5) * sl[4], qu[0] - TF(0.5) * su[0],
-                     qu[3] - TF(0.5) * su[3], qu[1] - TF(0.5) * su[1], qu[2] - TF(0.5) * su[2],
-                     qu[4] - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
+            if constexpr (EG) {
+                geos_flux(sEos[xl], flux, ql[0] + 0.5 * sl[0], ql[3] + 0.5 * sl[3], ql[1] + 0.5 * sl[1],
+                          ql[2] + 0.5 * sl[2], ql[4] + 0.5 * sl[4], qu[0] - 0.5 * su[0], qu[3] - 0.5 * su[3],
+                          qu[1] - 0.5 * su[1], qu[2] - 0.5 * su[2], qu[4] - 0.5 * su[4], Fr);
+            } else {
+                const TF g = TF(mat(xl, MAT_GAMMA)), pc = TF(mat(xl, MAT_PC)), gpc = TF(mat(xl, MAT_GPC)),
+                         igm1 = TF(mat(xl, MAT_IGM1));
+                num_flux<TF>(flux, ql[0] + TF(0.5) * sl[0], ql[3] + TF(0.5) * sl[3], ql[1] + TF(0.5) * sl[1],
+                             ql[2] + TF(0.5) * sl[2], ql[4] + TF(0.5) * sl[4], qu[0] - TF(0.5) * su[0],
+                             qu[3] - TF(0.5) * su[3], qu[1] - TF(0.5) * su[1], qu[2] - TF(0.5) * su[2],
+                             qu[4] - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
+            }
             F[0] = Fr[0];
             F[3] = Fr[1];
             F[1] = Fr[2];
@@ -382,9 +398,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (hofs[q] >= 0) {
                 const bool mx = (hmir >> (2 * q)) & 1u, my = (hmir >> (2 * q)) & 2u;
                 const uint8_t x = hx[q];
-                double u, vv, ww;
-                const double p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], mat(x, MAT_GM1),
-                                          mat(x, MAT_GPC), u, vv, ww);
+                double u, vv, ww, p;
+                if constexpr (EG) p = geos_prim(sEos[x], hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], u, vv, ww);
+                else p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], mat(x, MAT_GM1), mat(x, MAT_GPC),
+                                  u, vv, ww);
                 const int o = hofs[q];
                 sQ[o] = TF(hw[q][0]);
                 sQ[PL + o] = TF(mx ? -u : u);
@@ -425,8 +442,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     qb[v] = b0 - TF(0.5) * sb;
                 }
                 TF Fr[5];
-                num_flux<TF>(flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], TF(mat(xa, MAT_GAMMA)),
-                         TF(mat(xa, MAT_PC)), TF(mat(xa, MAT_GPC)), TF(mat(xa, MAT_IGM1)), Fr);
+                if constexpr (EG)
+                    geos_flux(sEos[xa], flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], Fr);
+                else
+                    num_flux<TF>(flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4],
+                                 TF(mat(xa, MAT_GAMMA)), TF(mat(xa, MAT_PC)), TF(mat(xa, MAT_GPC)), TF(mat(xa, MAT_IGM1)),
+                                 Fr);
                 sF[t] = Fr[0];
                 sF[nrm * NF + t] = Fr[1];
                 sF[ta * NF + t] = Fr[2];
@@ -533,10 +554,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     wn[v] = c0 * (W0E ? w0[v] : ldf(a.W0 + v * N, c)) + c1 * (wi[v] + dt * (-acc[v]));
                 wn[5] = c0 * (W0E ? w0[5] : ldf(a.W0 + 5 * N, c)) + c1 * (PH[2] + dt * (-Ls));
             }
-            double u, vv, ww;
-            const double p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
-            const bool ok = wn[0] > 0.0 && p + mat(X0, MAT_PC) > 0.0 && isfinite(p) && isfinite(u) && isfinite(vv) &&
-                            isfinite(ww) && isfinite(wn[5]);
+            double u, vv, ww, p;
+            bool adm;
+            if constexpr (EG) {
+                p = geos_prim(sEos[X0], wn[0], wn[1], wn[2], wn[3], wn[4], u, vv, ww);
+                adm = geos_ok(sEos[X0], wn[0], p);
+            } else {
+                p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
+                adm = wn[0] > 0.0 && p + mat(X0, MAT_PC) > 0.0;
+            }
+            const bool ok = adm && isfinite(p) && isfinite(u) && isfinite(vv) && isfinite(ww) && isfinite(wn[5]);
             if (!ok) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, c);
 #pragma unroll
             for (int v = 0; v < 6; ++v) stf(a.Wout + v * N, c, wn[v]);
@@ -547,7 +574,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     const int slot = atomicAdd(&sc->nflip, 1);
                     a.flips[slot] = (int)c;
                 } else if (ok) {
-                    const double cs = sqrt_nr(mat(X0, MAT_GAMMA) * (p + mat(X0, MAT_PC)) * rcp_nr(wn[0]));
+                    double cs;
+                    if constexpr (EG) cs = sqrt(geos_c2(sEos[X0], wn[0], p));
+                    else cs = sqrt_nr(mat(X0, MAT_GAMMA) * (p + mat(X0, MAT_PC)) * rcp_nr(wn[0]));
                     double l = 0.0;
                     if (xact) l += (fabs(u) + cs) * G.rh[0];
                     if (yact) l += (fabs(vv) + cs) * G.rh[1];
@@ -609,23 +638,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk)
 #define M2C_STAGE_BOUNDS(TX, TY, TF) \
     __launch_bounds__(stage_threads(TX, TY), sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES)
 
-template <int STAGE, int TX, int TY, typename TF, bool OPTS>
+template <int STAGE, int TX, int TY, typename TF, bool OPTS, bool EG = false>
 __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
 {
-    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double), OPTS>(a, xcd_tile(blockIdx.x, gridDim.x));
+    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double), OPTS, EG>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Launch of the single-grid kernel of one stage kind over the whole grid.
-template <int TX, int TY, typename TF, bool OPTS>
+template <int TX, int TY, typename TF, bool OPTS, bool EG = false>
 static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
 {
     const int nblk = a.tiles_x * a.tiles_y * a.tiles_z;
     const dim3 g(nblk), b(stage_threads(TX, TY));
     switch (stage) {
-        case 1: hipLaunchKernelGGL((k_stage<1, TX, TY, TF, OPTS>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_stage<2, TX, TY, TF, OPTS>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_stage<3, TX, TY, TF, OPTS>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_stage<4, TX, TY, TF, OPTS>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_stage<1, TX, TY, TF, OPTS, EG>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_stage<2, TX, TY, TF, OPTS, EG>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_stage<3, TX, TY, TF, OPTS, EG>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_stage<4, TX, TY, TF, OPTS, EG>), g, b, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -28,15 +28,23 @@ NAMES = ("rho", "rhou", "rhov", "rhow", "rhoE", "phi")
 TOL_FP64 = 1e-9
 
 
-def conserved_errors(w_gpu, w_ora, prim_ora, gamma, pc, chi_ora, h_min):
-    """e_k for the six fields of two conservative states [6, ...]."""
+def conserved_errors(w_gpu, w_ora, prim_ora, gamma, pc, chi_ora, h_min, eos=None):
+    """e_k for the six fields of two conservative states [6, ...]; eos:
+    general EOS of materials 0 and 1 as (family, params) pairs (then the
+    sound speeds of the momentum floor come from those)."""
     w_gpu = np.asarray(w_gpu).reshape(6, -1)
     w_ora = np.asarray(w_ora).reshape(6, -1)
     prim = np.asarray(prim_ora).reshape(6, -1)
     chi = np.asarray(chi_ora).reshape(-1)
-    g = np.where(chi == 1, gamma[1], gamma[0])
-    p_c = np.where(chi == 1, pc[1], pc[0])
-    c = np.sqrt(g * (prim[4] + p_c) / prim[0])
+    if eos is None:
+        g = np.where(chi == 1, gamma[1], gamma[0])
+        p_c = np.where(chi == 1, pc[1], pc[0])
+        c = np.sqrt(g * (prim[4] + p_c) / prim[0])
+    else:
+        from oracle import riemann_eos as RE
+        mats = [RE.make_eos(f, prm) for f, prm in eos]
+        c = np.array([np.sqrt(max(mats[x].c2(r, mats[x].e(r, p)), 0.0))
+                      for x, r, p in zip(chi, prim[0], prim[4])])
     rc_max = float(np.max(prim[0] * c))
     floors = [1.0, 1e-3 * rc_max, 1e-3 * rc_max, 1e-3 * rc_max, float(np.max(np.abs(w_ora[4]))), h_min]
     out = {}
@@ -53,6 +61,6 @@ def compare_runs(gpu_sim, ora_sim, problem):
     w_o = ora_sim.cons()
     prim_o, chi_o = ora_sim.prim()
     h_min = min(problem.dx())
-    e = conserved_errors(w_g, w_o, prim_o, problem.gamma, problem.pc, chi_o, h_min)
+    e = conserved_errors(w_g, w_o, prim_o, problem.gamma, problem.pc, chi_o, h_min, getattr(problem, "eos", None))
     e["id_mismatch"] = int(np.count_nonzero(chi_g.reshape(-1) != chi_o.reshape(-1)))
     return e

@@ -121,8 +121,59 @@ def test_validate_config_without_gpu(field, value, ok):
     assert (rc == m.M2C_OK) == ok, (field, value, rc)
 
 
+_TNT = (2, [0.3, 3.712e11, 3.231e9, 4.15, 0.95, 1630.0, 0.0])
+_COPPER = (1, [8930.0, 3940.0, 2.0, 1.49, 0.0, -0.1, 0.0])
+
+
+@pytest.mark.parametrize("case,ok", [
+    ("valid", True),
+    ("eos_general 2", False),
+    ("mixed precision", False),
+    ("family 3", False),
+    ("JWL omega 0", False),
+    ("MG eta_min 0", False),
+    ("NASG gamma 1", False),
+    ("riemann_ds 1e-4", False),
+    ("riemann_ds 0.02", True),
+    ("tile 32x8", False),
+    ("tile 64x2", True),
+    ("rk3 llf van albada", True),
+])
+def test_validate_general_eos_config_without_gpu(case, ok):
+    """General-EOS configurations: parameter checks of the families, FP64
+    only, the RK4 step range and the two compiled stage tiles."""
+    import paper_2508_16387_amd as m
+    c = m.config_default()
+    c.eos_general = 1
+    for k, (fam, prm) in enumerate((_TNT, _COPPER)):
+        c.eos[k].family = fam
+        for j, v in enumerate(prm):
+            c.eos[k].prm[j] = v
+    if case == "eos_general 2":
+        c.eos_general = 2
+    elif case == "mixed precision":
+        c.precision = m.M2C_PREC_MIXED
+    elif case == "family 3":
+        c.eos[0].family = 3
+    elif case == "JWL omega 0":
+        c.eos[0].prm[0] = 0.0
+    elif case == "MG eta_min 0":
+        c.eos[1].prm[5] = 0.0
+    elif case == "NASG gamma 1":
+        c.eos[1].family = 0
+        c.eos[1].prm[0] = 1.0
+    elif case.startswith("riemann_ds"):
+        c.riemann_ds = float(case.split()[1])
+    elif case.startswith("tile"):
+        c.tile_x, c.tile_y = map(int, case.split()[1].split("x"))
+    elif case == "rk3 llf van albada":
+        c.rk_order, c.flux, c.limiter, c.limiter_k = 3, m.M2C_FLUX_LLF, m.M2C_LIM_VAN_ALBADA, 4
+    rc = m.lib().m2c_validate_config(C.byref(c))
+    assert (rc == m.M2C_OK) == ok, (case, rc)
+
+
 @pytest.mark.parametrize("field,value", [("rk_order", 3), ("limiter", 1), ("flux", 1), ("ls_band", 0.1),
-                                         ("precision", None)])
+                                         ("precision", None), ("eos_general", 1)])
 def test_batch_create_rejects_unsupported_without_gpu(field, value):
     """The batched kernels are TVD-RK2 with MC and HLLC and one precision;
     anything else is refused before any device call."""

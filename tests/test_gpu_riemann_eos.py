@@ -149,6 +149,27 @@ def test_cavitation_and_inadmissible_inputs(m2c):
     assert _errors(inp[:, [4]], mat[:, [4]], eos, ref, got[:, [4]]).max() <= TOL_EOS
 
 
+def test_near_equal_states(m2c):
+    """States a few ulps apart (as two cells at rest in pressure equilibrium
+    become after some steps): a shock too weak for the specific volume to
+    change in FP64 is a valid wave, and p* is the common pressure."""
+    names = ["water_sg", "air", "copper", "tnt", "glass", "water_nasg"]
+    mats = [W._eos_of(k) for k in names]
+    rows = []
+    for a, b, ra, rb, p0 in ((0, 1, 1000.0, 1.0, 1e5), (2, 3, 8930.0, 1630.0, 1e9), (4, 5, 2204.0, 1000.0, 1e8)):
+        for dl, dr in ((0, 1), (0, -1), (2, 1), (-3, 4), (1e3, 0)):
+            pl = p0 + dl * math.ulp(p0)
+            pr = p0 + dr * math.ulp(p0)
+            rows.append(((ra, 0.0, pl, rb * (1 + 4e-16), 0.0, pr), (a, b)))
+    inp = np.array([r[0] for r in rows]).T.copy()
+    mat = np.array([r[1] for r in rows], dtype=np.int32).T.copy()
+    got, it, rc = _gpu(m2c, inp, mat, mats)
+    print("near-equal p*", got[0], "iters", it, flush=True)
+    assert rc == m2c.M2C_OK and (it != 0).all()
+    assert np.all(np.abs(got[0] / inp[2] - 1.0) <= 1e-12)
+    _compare(inp, mat, mats, got, it, "near-equal")
+
+
 def test_eos_eval_matches_oracle(m2c):
     import torch
     names = sorted(W.EOS_MATERIALS)
