@@ -237,6 +237,19 @@ def reinit_form(m2c, torch, problem, iters=100):
     return res
 
 
+def general_eos_step(m2c, torch, steps=20):
+    """The time step with a general EOS per material: a sphere (r = 0.28)
+    of detonation products (JWL, 1630 kg/m^3, 5 GPa) in NASG water at rest
+    on 128^3 cells, FP64, TVD-RK2 with MC and HLLC.  Interface faces take the
+    general-EOS exact Riemann solve (Hugoniot shocks, closed-form JWL and
+    NASG isentropes)."""
+    import workloads as W
+    p = W.eos_charge(0, n=(128, 128, 128), steps=steps)
+    rate, T = time_sim(m2c, torch, p, m2c.M2C_PREC_FP64, steps, 2)
+    return {"workload": "tnt_sphere_in_water_nasg_128", "steps": steps, "cell_updates_per_stage_per_s": rate,
+            "ms_per_step": T / steps * 1e3}
+
+
 def host_round_trip(m2c, torch, problem, steps):
     """The same FP64 run with the state handed over in host memory: upload
     (primitive -> conservative on the device), `steps` steps, download.  A
@@ -445,6 +458,7 @@ def main():
             "learned_guess_standalone": learned_standalone(m2c, torch),
             "general_eos_riemann": general_eos_standalone(m2c, torch),
             "reinit_128": reinit_form(m2c, torch, p),
+            "general_eos_step_128": general_eos_step(m2c, torch),
             "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
         }
         if args.cloud_steps > 0:

@@ -76,9 +76,10 @@ enum { M2C_LIM_MC = 0,           /* monotonized central, parameter limiter_alpha
  * fluxes (appendix "Numerical flux functions"). */
 enum { M2C_FLUX_HLLC = 0, M2C_FLUX_LLF = 1 };
 
-/* General equations of state.  The two-material Riemann problem of eq. 1DRiemannProblem with its own
- * equation of state p = p(rho, e) on each side (section "Equations of
- * state", eq. eos_all), from the families of that section and its appendix:
+/* General equations of state p = p(rho, e) (section "Equations of state",
+ * eq. eos_all), one per material, for the two-material Riemann problem of
+ * eq. 1DRiemannProblem and the time step with eos_general set; the families
+ * of that section and its appendix:
  *   M2C_EOS_NASG  Noble-Abel stiffened gas, eq. NASG_EOS:
  *                 p = (gamma - 1) rho (e - e_c) / (1 - rho b) - gamma p_c;
  *                 prm = {gamma > 1, p_c >= 0, b >= 0, e_c}
