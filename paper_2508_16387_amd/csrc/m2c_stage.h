@@ -554,11 +554,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     wn[v] = c0 * (W0E ? w0[v] : ldf(a.W0 + v * N, c)) + c1 * (wi[v] + dt * (-acc[v]));
                 wn[5] = c0 * (W0E ? w0[5] : ldf(a.W0 + 5 * N, c)) + c1 * (PH[2] + dt * (-Ls));
             }
-            double u, vv, ww, p;
+            double u, vv, ww, p, c2 = 0.0;
             bool adm;
             if constexpr (EG) {
                 p = geos_prim(sEos[X0], wn[0], wn[1], wn[2], wn[3], wn[4], u, vv, ww);
-                adm = geos_ok(sEos[X0], wn[0], p);
+                c2 = geos_c2(sEos[X0], wn[0], p);
+                adm = wn[0] > 0.0 && p > sEos[X0].k[eos::KFLOOR] && c2 > 0.0;
             } else {
                 p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
                 adm = wn[0] > 0.0 && p + mat(X0, MAT_PC) > 0.0;
@@ -575,7 +576,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     a.flips[slot] = (int)c;
                 } else if (ok) {
                     double cs;
-                    if constexpr (EG) cs = sqrt(geos_c2(sEos[X0], wn[0], p));
+                    if constexpr (EG) cs = sqrt(c2);
                     else cs = sqrt_nr(mat(X0, MAT_GAMMA) * (p + mat(X0, MAT_PC)) * rcp_nr(wn[0]));
                     double l = 0.0;
                     if (xact) l += (fabs(u) + cs) * G.rh[0];
