@@ -400,8 +400,19 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         const bool hg = !EG && a.guess != nullptr;
         int it;
         if constexpr (EG) {
-            const double in[6] = {qa[0], ua, qa[4], qb[0], ub, qb[4]};
-            it = eos::solve_pair(sEos[xa], sEos[xb], in, G.rtol, G.maxit, G.rds, out);
+            // material 0 always on the left: where the lower cell holds
+            // material 1 the mirrored problem is solved (p* unchanged, u*
+            // negated, the star densities swapped), so that every lane of a
+            // wavefront runs the same families' code on each side
+            const bool flip = xa != 0;
+            const double in[6] = {flip ? qb[0] : qa[0], flip ? -ub : ua, flip ? qb[4] : qa[4],
+                                  flip ? qa[0] : qb[0], flip ? -ua : ub, flip ? qa[4] : qb[4]};
+            double o[4];
+            it = eos::solve_pair(sEos[0], sEos[1], in, G.rtol, G.maxit, G.rds, o);
+            out[0] = o[0];
+            out[1] = flip ? -o[1] : o[1];
+            out[2] = flip ? o[3] : o[2];
+            out[3] = flip ? o[2] : o[3];
         } else {
             it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg,
                                hg ? a.guess[q] : 0.0, out, &used);

@@ -13,8 +13,13 @@ bool stage_tile_supported_eos(int tx, int ty) { return (tx == 16 && ty == 16) ||
 
 hipError_t launch_stage_eos(int stage, int tx, int ty, const StageArgs& a, hipStream_t s)
 {
-    if (tx == 16 && ty == 16) return launch_tile<16, 16, double, true, true>(stage, a, s);
-    if (tx == 64 && ty == 2) return launch_tile<64, 2, double, true, true>(stage, a, s);
+    const bool opts = a.g.limiter != LIM_MC || a.g.flux != FLUX_HLLC || a.g.ls_band > 0.0;
+    if (tx == 16 && ty == 16)
+        return opts ? launch_tile<16, 16, double, true, true>(stage, a, s)
+                    : launch_tile<16, 16, double, false, true>(stage, a, s);
+    if (tx == 64 && ty == 2)
+        return opts ? launch_tile<64, 2, double, true, true>(stage, a, s)
+                    : launch_tile<64, 2, double, false, true>(stage, a, s);
     return hipErrorInvalidValue;
 }
 

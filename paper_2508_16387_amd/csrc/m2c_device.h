@@ -223,27 +223,46 @@ __device__ __forceinline__ void llf(T rL, T uL, T aL, T bL, T pL, T rR, T uR, T 
 // ------------------------------------------------------- general EOS -----
 // A material with a general EOS (section "Equations of state": NASG,
 // Mie-Grueneisen, JWL; FP64 only).  Conservative -> primitive: returns p.
+// The NASG forms are written out here with the refined reciprocal (the
+// common case of liquids and gases, and the one whose IEEE divisions would
+// dominate); the other families take the general functions.
+__device__ __forceinline__ double geos_p(const eos::EosK& m, double vi, double e)
+{
+    if (m.fam == M2C_EOS_NASG) return (e - m.k[3]) * rcp_nr((vi - m.k[2]) * m.k[4]) - m.k[5];
+    return eos::eos_p(m, vi, e);
+}
+__device__ __forceinline__ double geos_e(const eos::EosK& m, double vi, double p)
+{
+    if (m.fam == M2C_EOS_NASG) return (p + m.k[5]) * (vi - m.k[2]) * m.k[4] + m.k[3];
+    return eos::eos_e(m, vi, p);
+}
+__device__ __forceinline__ double geos_c2v(const eos::EosK& m, double vi, double p)
+{
+    if (m.fam == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * vi * vi * rcp_nr(vi - m.k[2]);
+    return eos::eos_c2(m, vi, p);
+}
+
 __device__ __forceinline__ double geos_prim(const eos::EosK& m, double r, double mx, double my, double mz,
                                             double E, double& u, double& v, double& w)
 {
-    const double ri = 1.0 / r;
+    const double ri = rcp_nr(r);
     u = mx * ri;
     v = my * ri;
     w = mz * ri;
     const double ke = 0.5 * (mx * u + my * v + mz * w);
-    return eos::eos_p(m, ri, (E - ke) * ri);
+    return geos_p(m, ri, (E - ke) * ri);
 }
 
 // Total energy per unit volume of a primitive state.
 __device__ __forceinline__ double geos_energy(const eos::EosK& m, double r, double u, double v, double w, double p)
 {
-    return r * eos::eos_e(m, 1.0 / r, p) + 0.5 * r * (u * u + v * v + w * w);
+    return r * geos_e(m, rcp_nr(r), p) + 0.5 * r * (u * u + v * v + w * w);
 }
 
 // c^2 of a state (<= 0 or NaN where the EOS is not hyperbolic).
 __device__ __forceinline__ double geos_c2(const eos::EosK& m, double r, double p)
 {
-    return eos::eos_c2(m, 1.0 / r, p);
+    return geos_c2v(m, rcp_nr(r), p);
 }
 
 // Admissible primitive state: finite, rho > 0, p above the floor, c^2 > 0.
@@ -257,10 +276,10 @@ __device__ __forceinline__ void geos_flux(const eos::EosK& m, int flux, double r
                                           double pL, double rR, double uR, double aR, double bR, double pR,
                                           double F[5])
 {
-    const double riL = 1.0 / rL, riR = 1.0 / rR;
-    const double cL = sqrt(eos::eos_c2(m, riL, pL)), cR = sqrt(eos::eos_c2(m, riR, pR));
-    const double EL = rL * eos::eos_e(m, riL, pL) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
-    const double ER = rR * eos::eos_e(m, riR, pR) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+    const double riL = rcp_nr(rL), riR = rcp_nr(rR);
+    const double cL = sqrt_nr(geos_c2v(m, riL, pL)), cR = sqrt_nr(geos_c2v(m, riR, pR));
+    const double EL = rL * geos_e(m, riL, pL) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+    const double ER = rR * geos_e(m, riR, pR) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
     if (flux == FLUX_LLF) llf_ce<double>(rL, uL, aL, bL, pL, cL, EL, rR, uR, aR, bR, pR, cR, ER, F);
     else hllc_ce<double>(rL, uL, aL, bL, pL, riL, cL, EL, rR, uR, aR, bR, pR, riR, cR, ER, F);
 }
