@@ -97,6 +97,19 @@ def test_eos_charge_3d_matches_oracle(m2c):
     assert o.stats()["iface_faces_last"] > 50
 
 
+@pytest.mark.parametrize("inner,outer,p_in,rho_in,rho_out,p_out", [
+    ("copper", "tnt", 1e5, 8930.0, 1630.0, 5e9),      # copper ball struck by detonation products
+    ("air", "glass", 1e5, 1.2, 2204.0, 1e9),          # air pore in compressed glass
+], ids=["copper-in-tnt", "air-in-glass"])
+def test_eos_mie_grueneisen_3d_matches_oracle(m2c, inner, outer, p_in, rho_in, rho_out, p_out):
+    """3D runs with a Mie-Grueneisen material on one side of the interface
+    (RK4 isentropes in the library, adaptive ones in the oracle)."""
+    p = W.eos_charge(6, n=(10, 9, 8), steps=3, inner=inner, outer=outer, p_inner=p_in, rho_inner=rho_in,
+                     rho_outer=rho_out, p_outer=p_out)
+    g, o = _run(m2c, p, 3)
+    assert o.stats()["iface_faces_last"] > 50
+
+
 def test_nasg_as_stiffened_gas_matches_stiffened_gas_path(m2c):
     """NASG with b = e_c = 0 is the stiffened gas: the general-EOS kernels
     reproduce the stiffened-gas kernels on a shock-bubble run (no oracle)."""
