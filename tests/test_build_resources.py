@@ -19,12 +19,11 @@ from paper_2508_16387_amd import build as B
 HIPCC = B.hipcc()
 
 
-@pytest.fixture(scope="module")
-def stage_resources(tmp_path_factory):
+def _resources(tmp_path_factory, source):
     if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
         pytest.skip("hipcc not available")
-    obj = tmp_path_factory.mktemp("res") / "k_stage.o"
-    src = os.path.join(B.CSRC, "k_stage.hip")
+    obj = tmp_path_factory.mktemp("res") / (source + ".o")
+    src = os.path.join(B.CSRC, source)
     r = subprocess.run([HIPCC, *B.FLAGS, "-c", src, "-o", str(obj), "-Rpass-analysis=kernel-resource-usage"],
                        capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
@@ -44,6 +43,16 @@ def stage_resources(tmp_path_factory):
             if m and name:
                 out[name][key] = int(m.group(1))
     return out
+
+
+@pytest.fixture(scope="module")
+def stage_resources(tmp_path_factory):
+    return _resources(tmp_path_factory, "k_stage.hip")
+
+
+@pytest.fixture(scope="module")
+def stage_eos_resources(tmp_path_factory):
+    return _resources(tmp_path_factory, "k_stage_eos.hip")
 
 
 # the 64x2 tile exists for quasi-1D grids only; its budget is not tuned
@@ -66,3 +75,15 @@ def test_mixed_stage_kernels_keep_four_waves(stage_resources):
     for n, r in ks.items():
         assert r["occupancy"] == 4, (n, r)
         assert r["vgpr"] <= 128, (n, r)
+
+
+def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resources):
+    """The general-EOS stage kernels on the 16x16 tile (default scheme and
+    run-time options): no scratch and two waves per SIMD for every stage
+    kind (holding W^n across the plane iteration pushed kinds 2 and 3 to one
+    wave)."""
+    ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi16E" in n}
+    assert len(ks) == 8, sorted(ks)
+    for n, r in ks.items():
+        assert r["scratch"] == 0, (n, r)
+        assert r["occupancy"] >= 2, (n, r)
