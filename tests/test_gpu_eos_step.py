@@ -110,6 +110,16 @@ def test_eos_mie_grueneisen_3d_matches_oracle(m2c, inner, outer, p_in, rho_in, r
     assert o.stats()["iface_faces_last"] > 50
 
 
+def test_eos_3d_walls_band_and_options_match_oracle(m2c):
+    """The run-time option kernels with a general EOS in 3D: wall boundaries,
+    a narrow-band level set, RK3, modified Van Albada and LLF."""
+    p = W.eos_charge(8, n=(10, 9, 8), steps=3)
+    p = dataclasses.replace(p, bc=(1, 1, 1, 1, 1, 1))
+    g, o = _run(m2c, p, 3, rk_order=3, limiter=oracle.LIM_VA_MOD, limiter_k=2, flux=oracle.FLUX_LLF,
+                ls_band=0.15)
+    assert o.stats()["iface_faces_last"] > 50
+
+
 def test_nasg_as_stiffened_gas_matches_stiffened_gas_path(m2c):
     """NASG with b = e_c = 0 is the stiffened gas: the general-EOS kernels
     reproduce the stiffened-gas kernels on a shock-bubble run (no oracle)."""
