@@ -182,7 +182,18 @@ __device__ __forceinline__ void count_body(const IfaceArgs& a, int blk)
     if (threadIdx.x == 0) a.blockcnt[blk] = t;
 }
 
-__global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a) { count_body(a, blockIdx.x); }
+// A step whose predecessor flipped no cell has the material ids the queue
+// was built from (the last stage writes every id, and a flip is exactly a
+// changed id), so the single-grid compaction keeps the queue and the face
+// slots.  The decision is read here before the scan kernel clears the flip
+// count, and the scan records it for the scatter.
+__device__ __forceinline__ bool queue_kept(const DevScalars* sc) { return sc->qvalid && sc->nflip == 0; }
+
+__global__ __launch_bounds__(COMPACT_THREADS) void k_count(const IfaceArgs a)
+{
+    if (queue_kept(a.sc)) return;
+    count_body(a, blockIdx.x);
+}
 
 // One block: exclusive scan of the block counts (in place), total -> qlen.
 // Each thread sums a contiguous segment of the counts, the block scans the
@@ -258,11 +269,19 @@ __device__ __forceinline__ void begin_step_body(DevScalars* sc, double cfl, doub
 __global__ __launch_bounds__(1024) void k_scan(const IfaceArgs a, int end_prev, int begin, double cfl,
                                                double dt_fixed, double dt_imposed)
 {
+    __shared__ int sKeep;
     if (threadIdx.x == 0) {
+        const int keep = queue_kept(a.sc) ? 1 : 0;
+        sKeep = keep;
+        a.sc->qreuse = keep;
         if (end_prev) end_step_body(a.sc, a.g.rk_stages);
         if (begin) begin_step_body(a.sc, cfl, dt_fixed, dt_imposed);
     }
+    __syncthreads();
+    if (sKeep) return;
     scan_body(a);
+    // the scatter that follows completes the queue unless a kernel failed
+    if (threadIdx.x == 0) a.sc->qvalid = a.sc->err == 0 ? 1 : 0;
 }
 
 __global__ void k_end_step(DevScalars* sc, int stages) { end_step_body(sc, stages); }
@@ -332,7 +351,11 @@ __device__ __forceinline__ void scatter_body(const IfaceArgs& a, int blk)
     }
 }
 
-__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a) { scatter_body(a, blockIdx.x); }
+__global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
+{
+    if (a.sc->qreuse) return;
+    scatter_body(a, blockIdx.x);
+}
 
 
 // ---------------------------------------------------------------------------
@@ -629,13 +652,13 @@ hipError_t launch_phase(const PhaseArgs& a, hipStream_t s)
 __global__ __launch_bounds__(COMPACT_THREADS) void k_count_phase(const IfaceArgs a, const PhaseArgs pa)
 {
     phase_body<false>(pa, blockIdx.x, gridDim.x);
-    count_body(a, blockIdx.x);
+    if (!queue_kept(a.sc)) count_body(a, blockIdx.x);
 }
 
 __global__ __launch_bounds__(COMPACT_THREADS) void k_count_phase_eos(const IfaceArgs a, const PhaseArgs pa)
 {
     phase_body<true>(pa, blockIdx.x, gridDim.x);
-    count_body(a, blockIdx.x);
+    if (!queue_kept(a.sc)) count_body(a, blockIdx.x);
 }
 
 hipError_t launch_compact(const IfaceArgs& a, const PhaseArgs* prev_phase, bool end_prev, bool begin,

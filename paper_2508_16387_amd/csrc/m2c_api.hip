@@ -202,6 +202,15 @@ int clear_error(m2c_ctx* c)
     return M2C_OK;
 }
 
+// The next step rebuilds the interface queue (the state, and with it the
+// material ids, was replaced outside the stepping).
+int invalidate_queue(m2c_ctx* c)
+{
+    c->hsc->qvalid = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->sc->qvalid, &c->hsc->qvalid, sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    return M2C_OK;
+}
+
 int pull_scalars(m2c_ctx* c)
 {
     HIPCHK(c, hipMemcpyAsync(c->hsc, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, c->stream));
@@ -396,6 +405,7 @@ int run_steps(m2c_ctx* c, int32_t nsteps, double dt_imposed, double* t_out)
     if (t_out) *t_out = c->hsc->t;
     if (c->hsc->err != 0) {
         c->lam_valid = false;
+        if ((rc = invalidate_queue(c))) return rc;
         const int e = c->hsc->err;
         const int code = e == ST_OVERFLOW ? M2C_ERR_NOMEM : e;
         return set_err(c, code, "step %lld failed: %s (cell %lld)", c->hsc->steps_done + 1, status_name(code),
@@ -411,6 +421,7 @@ int upload_prim(m2c_ctx* c, const double* dprim)
     if (rc) return rc;
     const int q = 1 - c->cur;
     HIPCHK(c, launch_prim_to_cons(c->g, dprim, c->W[q], c->chi[q], c->sc, c->stream));
+    if ((rc = invalidate_queue(c))) return rc;
     rc = pull_scalars(c);
     if (rc) return rc;
     if (c->hsc->err != 0) {
@@ -626,6 +637,8 @@ int m2c_set_conserved(m2c_ctx* c, const double* w6)
     const int q = 1 - c->cur;
     HIPCHK(c, hipMemcpyAsync(c->W[q], w6, 6 * c->g.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_chi_from_phi(c->g, c->W[q], c->chi[q], c->stream));
+    const int rc = invalidate_queue(c);
+    if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->cur = q;
     c->has_state = true;
@@ -649,7 +662,7 @@ int m2c_reinit(m2c_ctx* c, int32_t iters, double band)
     const long long N = c->g.N;
     double* phi = c->W[c->cur] + 5 * N;
     HIPCHK(c, reinit_run(g, phi, c->W1, c->W1 + N, (int32_t*)(c->W1 + 2 * N), iters, band, c->stream));
-    return M2C_OK;
+    return invalidate_queue(c);
 }
 
 int m2c_step_dt(m2c_ctx* c, int32_t nsteps, double dt, double* t_out)
@@ -808,6 +821,7 @@ int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
         c->cur = cur0;
         c->lam_valid = lam0;
         *c->hsc = sc0;
+        c->hsc->qvalid = 0;                    // the trial steps may have changed the queue
         HIPCHK(c, hipMemcpyAsync(c->W[cur0], snapW, 6 * N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->chi[cur0], snapX, N, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(c->sc, c->hsc, sizeof(DevScalars), hipMemcpyHostToDevice, c->stream));

@@ -28,7 +28,8 @@ struct DevScalars {
     long long steps_done;
     long long solves, newton_iters, fallbacks, flips, orphans, mlp_fallbacks;
     double dt_last;
-    int32_t chi_dirty;             // material field changed since the last compaction
+    int32_t qvalid;                // queue and face slots built for the current material ids
+    int32_t qreuse;                // this step keeps them (no cell flipped in the last step)
     int32_t cur;                   // batched runs: index (0/1) of the current full state
 };
 
