@@ -237,6 +237,33 @@ def reinit_form(m2c, torch, problem, iters=100):
     return res
 
 
+def scheme_options(m2c, torch, problem, steps=20):
+    """The paper's other scheme options on the headline workload (FP64):
+    cell-updates/s per RK stage of TVD-RK3, forward Euler, the Van Albada
+    limiter (k = 2), the local Lax-Friedrichs flux and a six-cell
+    narrow-band level set, each with the other choices at their defaults."""
+    h = min(problem.dx())
+    cases = {"rk3": dict(rk_order=3), "forward_euler": dict(rk_order=1),
+             "van_albada_k2": dict(limiter=m2c.M2C_LIM_VAN_ALBADA, limiter_k=2),
+             "llf": dict(flux=m2c.M2C_FLUX_LLF), "ls_band_6h": dict(ls_band=6.0 * h)}
+    out = {}
+    for name, kw in cases.items():
+        sim = m2c.Sim(m2c.config_for(problem, **kw))
+        sim.set_stream(torch.cuda.current_stream())
+        sim.set_state(problem.prim)
+        sim.step(2)
+        sim.set_state(problem.prim)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        T = time.perf_counter() - t0
+        stages = kw.get("rk_order", 2)
+        out[name] = {"cell_updates_per_stage_per_s": problem.ncells * steps * stages / T,
+                     "ms_per_step": T / steps * 1e3}
+    return out
+
+
 def general_eos_step(m2c, torch, steps=20):
     """The time step with a general EOS per material: a sphere (r = 0.28)
     of detonation products (JWL, 1630 kg/m^3, 5 GPa) in NASG water at rest
@@ -459,6 +486,7 @@ def main():
             "general_eos_riemann": general_eos_standalone(m2c, torch),
             "reinit_128": reinit_form(m2c, torch, p),
             "general_eos_step_128": general_eos_step(m2c, torch),
+            "scheme_options_128": scheme_options(m2c, torch, p),
             "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
         }
         if args.cloud_steps > 0:

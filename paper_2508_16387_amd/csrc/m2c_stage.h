@@ -375,7 +375,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         bool mzn = false;
         if (zact) load_raw(k + 3, Wn, Xn, mzn);
         // stage 2: the step-start state of the cell, fetched early
-        constexpr bool W0E = BLEND && sizeof(TF) == sizeof(double) && !EG;
+        constexpr bool W0E = BLEND && sizeof(TF) == sizeof(double) && !EG && !OPTS;
         double w0[6];
         if (W0E && inside) {
             const uint32_t c0 = col + sxy * k;

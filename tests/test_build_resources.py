@@ -19,17 +19,13 @@ from paper_2508_16387_amd import build as B
 HIPCC = B.hipcc()
 
 
-def _resources(tmp_path_factory, source):
-    if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
-        pytest.skip("hipcc not available")
-    obj = tmp_path_factory.mktemp("res") / (source + ".o")
-    src = os.path.join(B.CSRC, source)
-    r = subprocess.run([HIPCC, *B.FLAGS, "-c", src, "-o", str(obj), "-Rpass-analysis=kernel-resource-usage"],
-                       capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-2000:]
+SOURCES = ("k_stage.hip", "k_stage_eos.hip", "k_stage_opts.hip")
+
+
+def _parse(stderr):
     out = {}
     name = None
-    for line in r.stderr.splitlines():
+    for line in stderr.splitlines():
         m = re.search(r"Function Name: (\S+)", line)
         if m:
             name = m.group(1)
@@ -46,13 +42,38 @@ def _resources(tmp_path_factory, source):
 
 
 @pytest.fixture(scope="module")
-def stage_resources(tmp_path_factory):
-    return _resources(tmp_path_factory, "k_stage.hip")
+def all_resources(tmp_path_factory):
+    """The compiler's resource report of the three stage-kernel sources,
+    compiled side by side."""
+    if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    d = tmp_path_factory.mktemp("res")
+    procs = {}
+    for src in SOURCES:
+        procs[src] = subprocess.Popen([HIPCC, *B.FLAGS, "-c", os.path.join(B.CSRC, src), "-o", str(d / (src + ".o")),
+                                       "-Rpass-analysis=kernel-resource-usage"],
+                                      stdout=subprocess.DEVNULL, stderr=subprocess.PIPE, text=True)
+    out = {}
+    for src, p in procs.items():
+        err = p.communicate()[1]
+        assert p.returncode == 0, err[-2000:]
+        out[src] = _parse(err)
+    return out
 
 
 @pytest.fixture(scope="module")
-def stage_eos_resources(tmp_path_factory):
-    return _resources(tmp_path_factory, "k_stage_eos.hip")
+def stage_resources(all_resources):
+    return all_resources["k_stage.hip"]
+
+
+@pytest.fixture(scope="module")
+def stage_eos_resources(all_resources):
+    return all_resources["k_stage_eos.hip"]
+
+
+@pytest.fixture(scope="module")
+def stage_opts_resources(all_resources):
+    return all_resources["k_stage_opts.hip"]
 
 
 # the 64x2 tile exists for quasi-1D grids only; its budget is not tuned
@@ -84,6 +105,16 @@ def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resour
     wave)."""
     ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi16E" in n}
     assert len(ks) == 8, sorted(ks)
+    for n, r in ks.items():
+        assert r["scratch"] == 0, (n, r)
+        assert r["occupancy"] >= 2, (n, r)
+
+
+def test_option_stage_kernels_fit_two_waves_without_spills(stage_opts_resources):
+    """The run-time option kernels (limiter, flux, band) in FP64 on the
+    16x16 tile: two waves per SIMD without scratch for every stage kind."""
+    ks = {n: r for n, r in stage_opts_resources.items() if "k_stage" in n and "Li16ELi16EdLb1" in n}
+    assert len(ks) == 4, sorted(ks)
     for n, r in ks.items():
         assert r["scratch"] == 0, (n, r)
         assert r["occupancy"] >= 2, (n, r)
