@@ -78,8 +78,10 @@ def main():
                          "max_rel_pstar_deviation": dev_l}}
     with open(os.path.join(pkg, "learned_guess.json"), "w") as f:
         json.dump(meta, f, indent=1)
-    out_dir = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out_dir):
+    # optional third argument: a directory that receives a copy of both files
+    out_dir = sys.argv[3] if len(sys.argv) > 3 else None
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
         np.save(os.path.join(out_dir, "learned_guess.npy"), theta)
         with open(os.path.join(out_dir, "learned_guess.json"), "w") as f:
             json.dump(meta, f, indent=1)
