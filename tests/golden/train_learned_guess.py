@@ -7,7 +7,7 @@ log-uniform in [1, 1e4], density ratios log-uniform in [1, 1e3], half of the
 problems with a velocity jump).  Training runs on the GPU with the
 library's own BF16-MFMA forward/backward kernels and Adam.
 
-Run from the repository root on a GPU machine:
+Run from the repository root on a machine with an MI355X:
     python tests/golden/train_learned_guess.py [n_train] [epochs] [copy_dir]
 Writes paper_2508_16387_amd/learned_guess.npy (4801 float32 parameters)
 and learned_guess.json (data set, schedule, loss history) beside it.
