@@ -388,10 +388,14 @@ int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], cons
  * (1 <= nmat <= M2C_EOS_MAX); out = [p*,u*,rho*_L,rho*_R][n], iters
  * (nullable) = star-pressure Newton steps per problem (negative: bisection
  * fallback; 0: no star state or an inadmissible input, out = NaN).
- * Shocks: Hugoniot energy relation solved for the specific volume; rarefactions:
- * the isentrope integrated with classical RK4 over y = ln(p - floor) at steps
- * of at most ds (0: 0.01; else in [1e-3, 0.5]); the error of the RK4 part
- * falls as ds^4 (about 4e-10 relative at 0.01 on the materials of the tests).
+ * Shocks: Hugoniot energy relation solved for the specific volume.
+ * Rarefactions: the isentrope in closed form for NASG, JWL (its Riemann
+ * invariant by Gauss-Legendre quadrature) and the Mie-Grueneisen tension and
+ * cutoff branches; on the Mie-Grueneisen compression branch integrated with
+ * classical RK4 over y = ln(p - floor) at steps of at most ds (0: 0.01; else
+ * in [1e-3, 0.5]); the error of the RK4 part
+ * falls as ds^4 (at most about 2e-10 of the sound speed in u* at 0.01 on the
+ * materials of the tests).
  * FP64 throughout.  rtol: Newton stop |dp| <= rtol (p - floor) on the closer
  * side.  Returns M2C_ERR_RIEMANN if any problem had no star state,
  * M2C_ERR_ARG for invalid arguments or EOS parameters. */
