@@ -120,6 +120,25 @@ def test_eos_3d_walls_band_and_options_match_oracle(m2c):
     assert o.stats()["iface_faces_last"] > 50
 
 
+def test_eos_autotune_restores_state(m2c):
+    """The tile autotuner on a general-EOS context tries only the compiled
+    general-EOS tiles and restores the state (and marks the interface queue
+    stale): the run that follows matches the oracle."""
+    p = W.eos_charge(4, n=(11, 10, 9), steps=4)
+    print("autotune on the general-EOS charge", flush=True)
+    g = m2c.Sim(m2c.config_for(p), p.prim)
+    tile, ms = g.autotune(2)
+    print("tile", tile, "ms", ms, flush=True)
+    assert tile[:2] == (16, 16)
+    o = oracle.OracleSim(p)
+    assert g.step(4) == 0 and o.step(4) == 0
+    e = compare_runs(g, o, p)
+    print(e, flush=True)
+    assert e["id_mismatch"] == 0
+    for k in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+        assert e[k] <= TOL_FP64, (k, e[k])
+
+
 def test_nasg_as_stiffened_gas_matches_stiffened_gas_path(m2c):
     """NASG with b = e_c = 0 is the stiffened gas: the general-EOS kernels
     reproduce the stiffened-gas kernels on a shock-bubble run (no oracle)."""
