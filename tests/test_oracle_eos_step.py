@@ -199,6 +199,12 @@ MUTANTS = [
      "check_tube_star_state"),
     ("general sound speed in HLLC", "double cL = sqrt(ora_eos_c2(e, qL[0], qL[4]))",
      "double cL = 0.5 * sqrt(ora_eos_c2(e, qL[0], qL[4]))", "check_nasg_reduces_to_sg"),
+    ("general primitive -> conservative energy", "double e = ora_eos_e(&c->eos[m], rho, q[4]);",
+     "double e = ora_eos_e(&c->eos[m], rho, q[4]) * 1.0001;", "check_uniform_contact"),
+    ("general conservative -> primitive pressure", "q[4] = ora_eos_p(&c->eos[m], rho, e);",
+     "q[4] = ora_eos_p(&c->eos[m], rho, 1.0001 * e);", "check_uniform_contact"),
+    ("interface materials swapped", "s->c.riemann(xa, xb, in, out)", "s->c.riemann(xb, xa, in, out)",
+     "check_tube_star_state"),
 ]
 
 
