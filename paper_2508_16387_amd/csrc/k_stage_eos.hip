@@ -14,6 +14,10 @@ bool stage_tile_supported_eos(int tx, int ty) { return (tx == 16 && ty == 16) ||
 hipError_t launch_stage_eos(int stage, int tx, int ty, const StageArgs& a, hipStream_t s)
 {
     const bool opts = a.g.limiter != LIM_MC || a.g.flux != FLUX_HLLC || a.g.ls_band > 0.0;
+    // default scheme on the 16x16 tile without a Mie-Grueneisen material:
+    // kernels without its code
+    const bool nomg = a.g.ek[0].fam != M2C_EOS_MG && a.g.ek[1].fam != M2C_EOS_MG;
+    if (tx == 16 && ty == 16 && !opts && nomg) return launch_tile<16, 16, double, false, true, true>(stage, a, s);
     if (tx == 16 && ty == 16)
         return opts ? launch_tile<16, 16, double, true, true>(stage, a, s)
                     : launch_tile<16, 16, double, false, true>(stage, a, s);

@@ -99,12 +99,12 @@ def test_mixed_stage_kernels_keep_four_waves(stage_resources):
 
 
 def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resources):
-    """The general-EOS stage kernels on the 16x16 tile (default scheme and
-    run-time options): no scratch and two waves per SIMD for every stage
-    kind (holding W^n across the plane iteration pushed kinds 2 and 3 to one
-    wave)."""
+    """The general-EOS stage kernels on the 16x16 tile (default scheme,
+    run-time options, default scheme without Mie-Grueneisen code): no scratch
+    and two waves per SIMD for every stage kind (holding W^n across the plane
+    iteration pushed kinds 2 and 3 to one wave)."""
     ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi16E" in n}
-    assert len(ks) == 8, sorted(ks)
+    assert len(ks) == 12, sorted(ks)            # default scheme, options, default without Mie-Grueneisen
     for n, r in ks.items():
         assert r["scratch"] == 0, (n, r)
         assert r["occupancy"] >= 2, (n, r)
