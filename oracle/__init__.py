@@ -20,9 +20,13 @@ Contents
   (upwind Godunov |grad phi|, smoothed sign, fixed first layer, optional
   narrow band), in numpy.
 
-Parity status: the phase-update rule is a reading of an under-specified step
-and is "parity unpinned" beyond the translation and self-consistency tests;
-every other part is pinned by the tests under ``tests/test_oracle_*.py``.
+Parity status: every part is pinned by the tests under
+``tests/test_oracle_*.py``.  The zero-slope rule next to an interface and the
+phase-update rule are readings of under-specified steps; the oracle's
+implementation of each is pinned by a 30-digit hand-written forward-Euler
+step and a single-flip case checked against the independent exact solver
+(``tests/test_oracle_bruteforce.py``), but the choice of rule itself is a
+reading, not something the paper fixes.
 """
 from __future__ import annotations
 

@@ -561,6 +561,26 @@ MUTANTS = [
     ("RK3 level-set last weight", "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 2.0 / 3.0 * dt * L[c]",
      "phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 0.6 * dt * L[c]"),
     ("EOS gamma p_c term", "q[4] = (gamma - 1.0) * rho * e - gamma * pc;", "q[4] = (gamma - 1.0) * rho * e - pc;"),
+    ("HLLC contact speed numerator", "rL * uL * (SL - uL) - rR * uR * (SR - uR)) /",
+     "rL * uL * (SL - uL) + rR * uR * (SR - uR)) /"),
+    # the zero-slope rule next to an interface (reading of section "Spatial
+    # discretization": the projected states of eq. 1DRiemannProblem are the
+    # cell states), dropped on both sides or on one
+    ("slope across the interface, both cells",
+     ("int flat_a = s->X[pa - stride] != xa || s->X[pa + stride] != xa;",
+      "int flat_b = s->X[pb - stride] != xb || s->X[pb + stride] != xb;"),
+     ("int flat_a = 0;", "int flat_b = 0;")),
+    ("slope across the interface, upper cell",
+     "int flat_b = s->X[pb - stride] != xb || s->X[pb + stride] != xb;", "int flat_b = 0;"),
+    ("slope across the interface, lower cell",
+     "int flat_a = s->X[pa - stride] != xa || s->X[pa + stride] != xa;", "int flat_a = 0;"),
+    # the phase update (outline step 6 of section "Code structure")
+    ("phase update keeps the old normal velocity", "q[1 + d] = r->ustar;",
+     "q[1 + d] = side ? r->VR[d] : r->VL[d];"),
+    ("phase update takes the other side's star density", "q[0] = side ? r->rhoR : r->rhoL;",
+     "q[0] = side ? r->rhoL : r->rhoR;"),
+    ("phase update takes the other side's velocity", "for (int a = 0; a < 3; ++a) q[1 + a] = side ? r->VR[a] : r->VL[a];",
+     "for (int a = 0; a < 3; ++a) q[1 + a] = side ? r->VL[a] : r->VR[a];"),
 ]
 
 
@@ -571,23 +591,34 @@ def mutant_dir():
     shutil.rmtree(d, ignore_errors=True)
 
 
+def _all_checks():
+    """The pins of this file, then the high-precision brute-force pins
+    (slower; a mutant is reported caught at its first failing check)."""
+    from tests import test_oracle_bruteforce as BF
+    return [*CHECKS.items(), *BF.CHECKS.items()]
+
+
 @pytest.mark.parametrize("label,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_planted_mistakes(label, old, new, mutant_dir):
     src = open(os.path.join(os.path.dirname(oracle.__file__), "m2c_oracle.c")).read()
-    assert src.count(old) == 1, label
-    mdir = os.path.join(mutant_dir, label.replace(" ", "_"))
+    olds, news = (old, new) if isinstance(old, tuple) else ((old,), (new,))
+    for o, n in zip(olds, news):
+        assert src.count(o) == 1, (label, o)
+        src = src.replace(o, n)
+    mdir = os.path.join(mutant_dir, label.replace(" ", "_").replace("'", ""))
     os.makedirs(mdir, exist_ok=True)
     shutil.copy(os.path.join(os.path.dirname(oracle.__file__), "m2c_oracle.h"), mdir)
     with open(os.path.join(mdir, "m2c_oracle.c"), "w") as f:
-        f.write(src.replace(old, new))
+        f.write(src)
     so = os.path.join(mdir, "libmut.so")
     subprocess.run(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-o", so,
                     os.path.join(mdir, "m2c_oracle.c"), "-lm"], check=True)
     lib = oracle.load(so)
-    caught = []
-    for name, chk in CHECKS.items():
+    caught = None
+    for name, chk in _all_checks():
         try:
             chk(lib)
         except (AssertionError, ValueError):
-            caught.append(name)
+            caught = name
+            break
     assert caught, f"planted mistake '{label}' passed every pin"
