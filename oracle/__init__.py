@@ -43,16 +43,24 @@ _SRC = os.path.join(_HERE, "m2c_oracle.c")
 OK, ERR_ARG, ERR_NONPHYSICAL, ERR_RIEMANN, ERR_NOMEM = 0, -1, -2, -3, -7
 
 
-def build(force: bool = True, extra_flags=()):
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA)."""
-    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= os.path.getmtime(_SRC):
-        return _SO
-    tmp = _SO + ".tmp"
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build(force: bool = True, extra_flags=(), openmp: bool = False):
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA); with
+    ``openmp`` the all-core build (same source, -fopenmp), which gives
+    bit-identical results."""
+    so = _SO_OMP if openmp else _SO
+    hdr = os.path.join(_HERE, "m2c_oracle.h")
+    if (not force and os.path.exists(so)
+            and os.path.getmtime(so) >= max(os.path.getmtime(_SRC), os.path.getmtime(hdr))):
+        return so
+    tmp = so + ".tmp"
     cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
-           *extra_flags, "-o", tmp, _SRC, "-lm"]
+           *(["-fopenmp"] if openmp else []), *extra_flags, "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _SO)
-    return _SO
+    os.replace(tmp, so)
+    return so
 
 
 def build_variant(path: str, defines=()):
@@ -166,10 +174,13 @@ def load(path: str | None = None):
         getattr(lib, name).argtypes = [C.POINTER(EosC), C.c_double, C.c_double]
     lib.ora_eos_floor.restype = C.c_double
     lib.ora_eos_floor.argtypes = [C.POINTER(EosC)]
+    lib.ora_num_threads.restype = C.c_int32
+    lib.ora_num_threads.argtypes = []
     return lib
 
 
 _lib = None
+_lib_omp = None
 
 
 def lib():
@@ -177,6 +188,16 @@ def lib():
     if _lib is None:
         _lib = load()
     return _lib
+
+
+def lib_openmp():
+    """The all-core (OpenMP) build; threads from OMP_NUM_THREADS."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_SO_OMP):
+            build(openmp=True)
+        _lib_omp = load(_SO_OMP)
+    return _lib_omp
 
 
 def make_cfg(problem, alpha=1.2, rk_order=2, rtol=1e-12, maxit=50, limiter=LIM_MC, limiter_k=2,

@@ -9,16 +9,37 @@
  *
  * Parity pins: every part of this file is pinned by tests that do not retype
  * its formulas (closed forms, conservation, invariants, exact Riemann
- * solutions from an independent bisection solver); the phase-update rule
- * (after the level-set sign of a cell flips) is a reading of an under-specified
- * step and is "parity unpinned" beyond the translation and self-consistency
- * tests.
+ * solutions from an independent bisection solver, a 30-digit hand-written
+ * forward-Euler step and single-face fluxes).  The zero-slope rule next to an
+ * interface and the phase-update rule are readings of under-specified steps:
+ * the code is pinned to the readings as stated, the readings themselves are
+ * choices the paper does not fix.
+ *
+ * Threads: built with -fopenmp (the all-core CPU baseline), the cell and
+ * line loops run in parallel.  Every cell's arithmetic and its order are the
+ * same as in the serial build (sums over a cell's faces stay in axis order,
+ * the time step is a maximum, error cells are the first in loop order), so
+ * both builds give bit-identical results; only the storage order of the
+ * interface star records differs, and they are read through the face map.
  */
 #include "m2c_oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the oracle's loops use (1 in the serial build). */
+int32_t ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Stiffened-gas EOS: eq. NASG_EOS with b = 0 and e_c = 0 (section
@@ -628,6 +649,7 @@ void ora_get_stats(const ora_sim* s, ora_stats* st) { *st = s->st; }
 static double dt_of(const ora_sim* s, double* const W[5], const uint8_t* chi)
 {
     double lmax = 0.0;
+#pragma omp parallel for schedule(static) reduction(max : lmax)
     for (int64_t c = 0; c < s->N; ++c) {
         double w[5], q[5];
         for (int v = 0; v < 5; ++v) w[v] = W[v][c];
@@ -711,6 +733,7 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
     int rc = ORA_OK;
 
     /* primitives of every interior cell, then ghosts */
+#pragma omp parallel for schedule(static)
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
@@ -726,24 +749,28 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
             }
     fill_ghosts(s);
 
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < s->N; ++c) {
         for (int v = 0; v < 5; ++v) R[v][c] = 0.0;
         L[c] = 0.0;
     }
     if (record) clear_records(s);
 
-    int maxn = n[0] > n[1] ? n[0] : n[1];
-    if (n[2] > maxn) maxn = n[2];
-    double (*FL)[5] = (double(*)[5])malloc((maxn + 1) * sizeof(double[5]));
-    double (*FU)[5] = (double(*)[5])malloc((maxn + 1) * sizeof(double[5]));
-
     for (int d = 0; d < 3; ++d) {
         if (!s->act[d]) continue;
         int a1 = (d + 1) % 3, a2 = (d + 2) % 3;
         int64_t stride = (d == 0) ? 1 : (d == 1) ? s->g[0] : (int64_t)s->g[0] * s->g[1];
         int64_t cstride = (d == 0) ? 1 : (d == 1) ? n[0] : (int64_t)n[0] * n[1];
-        for (int t2 = 0; t2 < n[a2]; ++t2)
-            for (int t1 = 0; t1 < n[a1]; ++t1) {
+        /* lines along d, in the serial order (t2 outer, t1 inner); each line
+         * writes only its own cells.  A general EOS calls back into the
+         * caller's solver, which is not asked to be thread-safe. */
+        const int64_t nlines = (int64_t)n[a1] * n[a2];
+        int64_t solves = 0, iters = 0, fallbacks = 0;
+        int64_t bad_line = nlines, bad_cell = -1;
+#pragma omp parallel for schedule(static) reduction(+ : solves, iters, fallbacks) if (!s->c.eos_general)
+        for (int64_t line = 0; line < nlines; ++line) {
+                const int t1 = (int)(line % n[a1]), t2 = (int)(line / n[a1]);
+                double FL[n[d] + 1][5], FU[n[d] + 1][5];
                 int ib[3];
                 ib[d] = 0; ib[a1] = t1; ib[a2] = t2;
                 int64_t p0 = pidx(s, ib[0], ib[1], ib[2]);      /* line start  */
@@ -796,14 +823,19 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                         int32_t it = 0;
                         int e = s->c.eos_general ? s->c.riemann(xa, xb, in, out)
                                                  : ora_riemann(in, eos, s->c.rtol, s->c.maxit, out, &it);
-                        s->st.riemann_solves++;
-                        s->st.newton_iters += it < 0 ? -it : it;
-                        if (it < 0) s->st.bisection_fallbacks++;
+                        solves++;
+                        iters += it < 0 ? -it : it;
+                        if (it < 0) fallbacks++;
                         if (e != ORA_OK) {
-                            rc = e;
-                            if (s->st.err_cell < 0) {
-                                int ic[3]; ic[d] = m < n[d] ? m : n[d] - 1; ic[a1] = t1; ic[a2] = t2;
-                                s->st.err_cell = ic[0] + (int64_t)n[0] * (ic[1] + (int64_t)n[1] * ic[2]);
+                            /* the first failing face in loop order names the cell */
+#pragma omp critical(ora_residual_error)
+                            {
+                                rc = e;
+                                if (line < bad_line) {
+                                    int ic[3]; ic[d] = m < n[d] ? m : n[d] - 1; ic[a1] = t1; ic[a2] = t2;
+                                    bad_line = line;
+                                    bad_cell = ic[0] + (int64_t)n[0] * (ic[1] + (int64_t)n[1] * ic[2]);
+                                }
                             }
                             for (int v = 0; v < 5; ++v) Fr_l[v] = Fr_u[v] = 0.0;
                         } else {
@@ -819,6 +851,7 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                                     r.VR[a] = s->P[1 + a][pb];
                                 }
                                 int64_t ca = c0 + (int64_t)(m - 1) * cstride;
+#pragma omp critical(ora_records)
                                 add_record(s, 3 * ca + d, &r);
                             }
                         }
@@ -840,9 +873,12 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
                     L[c] += Vd * ora_ls_derivative(f, Vd, s->h[d]);
                 }
             }
+        s->st.riemann_solves += solves;
+        s->st.newton_iters += iters;
+        s->st.bisection_fallbacks += fallbacks;
+        if (bad_cell >= 0 && s->st.err_cell < 0) s->st.err_cell = bad_cell;
     }
-    free(FL);
-    free(FU);
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < s->N; ++c) {
         for (int v = 0; v < 5; ++v) R[v][c] = -R[v][c];
         L[c] = -L[c];
@@ -858,15 +894,20 @@ static int residual(ora_sim* s, double* const W[5], const double* phi, const uin
  * material ids) and all values are finite. */
 static int check_state(ora_sim* s, double* const W[5], const double* phi, const uint8_t* chi)
 {
+    int64_t bad = s->N;                 /* first failing cell */
+#pragma omp parallel for schedule(static) reduction(min : bad)
     for (int64_t c = 0; c < s->N; ++c) {
         double w[5], q[5];
         for (int v = 0; v < 5; ++v) w[v] = W[v][c];
         uint8_t m = chi[c];
         mat_cons_to_prim(&s->c, m, w, q);
         if (!physical(&s->c, m, q) || !isfinite(phi[c])) {
-            if (s->st.err_cell < 0) s->st.err_cell = c;
-            return ORA_ERR_NONPHYSICAL;
+            if (c < bad) bad = c;
         }
+    }
+    if (bad < s->N) {
+        if (s->st.err_cell < 0) s->st.err_cell = bad;
+        return ORA_ERR_NONPHYSICAL;
     }
     return ORA_OK;
 }
@@ -886,15 +927,18 @@ static int phase_update(ora_sim* s)
     int64_t cstr[3] = {1, n[0], (int64_t)n[0] * n[1]};
     uint8_t* newchi = (uint8_t*)malloc(s->N);
     int rc = ORA_OK;
+#pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < s->N; ++c) newchi[c] = material_of(s->phi[c]);
 
+    int64_t flips = 0, orphans = 0, bad = s->N;    /* bad: first non-physical cell */
+#pragma omp parallel for schedule(static) reduction(+ : flips, orphans) reduction(min : bad)
     for (int k = 0; k < n[2]; ++k)
         for (int j = 0; j < n[1]; ++j)
             for (int i = 0; i < n[0]; ++i) {
                 int64_t c = i + (int64_t)n[0] * (j + (int64_t)n[1] * k);
                 uint8_t A = s->chi[c], B = newchi[c];
                 if (A == B) continue;
-                s->st.flips++;
+                flips++;
                 int ijk[3] = {i, j, k};
                 double sum[5] = {0, 0, 0, 0, 0};
                 int cnt = 0;
@@ -927,15 +971,18 @@ static int phase_update(ora_sim* s)
                 } else {
                     for (int v = 0; v < 5; ++v) w[v] = s->W[v][c];
                     mat_cons_to_prim(&s->c, A, w, q);
-                    s->st.orphans++;
+                    orphans++;
                 }
-                if (!physical(&s->c, B, q)) {
-                    if (s->st.err_cell < 0) s->st.err_cell = c;
-                    rc = ORA_ERR_NONPHYSICAL;
-                }
+                if (!physical(&s->c, B, q) && c < bad) bad = c;
                 mat_prim_to_cons(&s->c, B, q, w);
                 for (int v = 0; v < 5; ++v) s->W[v][c] = w[v];
             }
+    s->st.flips += flips;
+    s->st.orphans += orphans;
+    if (bad < s->N) {
+        if (s->st.err_cell < 0) s->st.err_cell = bad;
+        rc = ORA_ERR_NONPHYSICAL;
+    }
     memcpy(s->chi, newchi, s->N);
     free(newchi);
     return rc;
@@ -973,6 +1020,7 @@ static int one_step(ora_sim* s, double dt_imposed)
     rc = residual(s, W0, phi0, s->chi, R, L, order == 1);
     s->st.iface_faces_last = s->st.riemann_solves - solves0;
     if (rc == ORA_OK) {
+#pragma omp parallel for schedule(static)
         for (int64_t c = 0; c < N; ++c) {
             for (int v = 0; v < 5; ++v) W1[v][c] = W0[v][c] + dt * R[v][c];
             phi1[c] = phi0[c] + dt * L[c];
@@ -983,7 +1031,8 @@ static int one_step(ora_sim* s, double dt_imposed)
         /* W^{n+1} = 1/2 W^n + 1/2 (W(1) + dt R(W(1))) */
         rc = residual(s, W1, phi1, s->chi, R, L, 1);
         if (rc == ORA_OK) {
-            for (int64_t c = 0; c < N; ++c) {
+    #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c) {
                 for (int v = 0; v < 5; ++v) W2[v][c] = 0.5 * W0[v][c] + 0.5 * (W1[v][c] + dt * R[v][c]);
                 phi2[c] = 0.5 * phi0[c] + 0.5 * (phi1[c] + dt * L[c]);
             }
@@ -994,7 +1043,8 @@ static int one_step(ora_sim* s, double dt_imposed)
          * W^{n+1} = 1/3 W^n + 2/3 W(2) + 2/3 dt R(W(2)) */
         rc = residual(s, W1, phi1, s->chi, R, L, 0);
         if (rc == ORA_OK) {
-            for (int64_t c = 0; c < N; ++c) {
+    #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c) {
                 for (int v = 0; v < 5; ++v) W2[v][c] = 0.75 * W0[v][c] + 0.25 * W1[v][c] + 0.25 * dt * R[v][c];
                 phi2[c] = 0.75 * phi0[c] + 0.25 * phi1[c] + 0.25 * dt * L[c];
             }
@@ -1002,7 +1052,8 @@ static int one_step(ora_sim* s, double dt_imposed)
         }
         if (rc == ORA_OK) rc = residual(s, W2, phi2, s->chi, R, L, 1);
         if (rc == ORA_OK) {
-            for (int64_t c = 0; c < N; ++c) {
+    #pragma omp parallel for schedule(static)
+        for (int64_t c = 0; c < N; ++c) {
                 for (int v = 0; v < 5; ++v)
                     W2[v][c] = W0[v][c] / 3.0 + 2.0 / 3.0 * W2[v][c] + 2.0 / 3.0 * dt * R[v][c];
                 phi2[c] = phi0[c] / 3.0 + 2.0 / 3.0 * phi2[c] + 2.0 / 3.0 * dt * L[c];

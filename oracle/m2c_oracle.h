@@ -109,6 +109,8 @@ void     ora_get_stats(const ora_sim* s, ora_stats* st);
  * f = 3*c + d (face between cell c and its +d neighbour).  Returns count;
  * writes at most cap ids. */
 int64_t  ora_interface_faces(const ora_sim* s, int32_t* out, int64_t cap);
+/* Threads the loops use: omp_get_max_threads() in the OpenMP build, else 1. */
+int32_t  ora_num_threads(void);
 
 /* ---- point functions ---------------------------------------------------- */
 /* Stiffened-gas primitive -> conservative and back (one cell). */
