@@ -346,6 +346,22 @@ int m2c_mlp_train(m2c_mlp* m, int64_t n, const float* X8, const float* t, const 
  * guess is taken without consulting the network. */
 int m2c_riemann_solve_learned(const m2c_mlp* m, int64_t n, const double* in, const double* eos, double rtol,
                               int32_t maxit, double* out, int32_t* iters, int64_t* n_fallback, void* hip_stream);
+/* The same solves as m2c_riemann_solve_learned (m = NULL: the acoustic
+ * guess), for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * allocates nothing and does not synchronise: the learned guesses go to a
+ * library-owned device buffer of M2C_NOALLOC_MAX_PROBLEMS doubles per GPU
+ * (8 MiB, held until the process ends), and the call only enqueues the
+ * kernels on hip_stream.  Layouts, out and iters are those of
+ * m2c_riemann_solve_learned (iters[i] = 0 and NaN out: no admissible star
+ * pressure); the vacuum and acoustic-start counts are not reported.  Every
+ * call on a GPU shares that GPU's buffer, so calls that overlap on one GPU
+ * (other streams or threads) race.  M2C_ERR_ARG for n > M2C_NOALLOC_MAX_PROBLEMS
+ * or invalid arguments, M2C_ERR_DEVICE if a launch fails. */
+#define M2C_NOALLOC_MAX_PROBLEMS (1 << 20)
+int m2c_riemann_solve_learned_noalloc(const m2c_mlp* m, int64_t n, const double* in, const double* eos,
+                                      double rtol, int32_t maxit, double* out, int32_t* iters,
+                                      void* hip_stream);
 /* Use a copy of the network for every interface Riemann problem of later
  * steps (NULL: back to the acoustic guess). */
 int m2c_set_guess(m2c_ctx* ctx, const m2c_mlp* m);

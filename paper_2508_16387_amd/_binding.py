@@ -33,6 +33,7 @@ EXPORTS = [
     "m2c_batch_get_stats", "m2c_batch_set_tile", "m2c_batch_get_tile", "m2c_batch_autotune",
     "m2c_train_opts_default", "m2c_mlp_create", "m2c_mlp_destroy", "m2c_mlp_get_params", "m2c_mlp_features",
     "m2c_mlp_forward", "m2c_mlp_grad", "m2c_mlp_train", "m2c_riemann_solve_learned", "m2c_set_guess",
+    "m2c_riemann_solve_learned_noalloc",
     "m2c_riemann_solve_eos", "m2c_eos_eval", "m2c_reinit", "m2c_reinit_workspace", "m2c_reinit_field",
 ]
 _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
@@ -161,6 +162,7 @@ def _declare(L):
     L.m2c_mlp_train.argtypes = [vp, i64, vp, vp, C.POINTER(TrainOpts), vp, vp]
     L.m2c_riemann_solve_learned.argtypes = [vp, i64, vp, vp, d, i32, vp, vp, C.POINTER(i64), vp]
     L.m2c_set_guess.argtypes = [vp, vp]
+    L.m2c_riemann_solve_learned_noalloc.argtypes = [vp, i64, vp, vp, d, i32, vp, vp, vp]
     L.m2c_riemann_solve_eos.argtypes = [i64, vp, vp, i32, vp, d, i32, d, vp, vp, vp]
     L.m2c_eos_eval.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp, vp]
     L.m2c_reinit.argtypes = [vp, i32, d]
@@ -635,3 +637,24 @@ def riemann_solve_learned(mlp, inp, eos, rtol=1e-12, maxit=50, stream=None):
     if rc not in (M2C_OK, M2C_ERR_RIEMANN):
         raise M2CError(rc, "m2c_riemann_solve_learned failed")
     return out, iters, rc, nfb.value
+
+
+NOALLOC_MAX_PROBLEMS = 1 << 20
+
+
+def riemann_solve_learned_async(mlp, inp, eos, out=None, iters=None, rtol=1e-12, maxit=50, stream=None):
+    """The allocation-free, non-synchronising form of
+    :func:`riemann_solve_learned` (mlp None: acoustic guess); the kernels are
+    only enqueued.  Returns (out [4, n], iters [n]); iters 0 marks a problem
+    without admissible star pressure.  At most NOALLOC_MAX_PROBLEMS problems."""
+    import torch
+    n = inp.shape[1]
+    if out is None:
+        out = torch.empty((4, n), dtype=torch.float64, device=inp.device)
+    if iters is None:
+        iters = torch.empty((n,), dtype=torch.int32, device=inp.device)
+    rc = lib().m2c_riemann_solve_learned_noalloc(None if mlp is None else mlp.h, n, _ptr(inp), _ptr(eos), rtol,
+                                                 maxit, _ptr(out), _ptr(iters), _stream_of(inp, stream))
+    if rc != M2C_OK:
+        raise M2CError(rc, "m2c_riemann_solve_learned_noalloc failed: " + lib().m2c_strerror(rc).decode())
+    return out, iters

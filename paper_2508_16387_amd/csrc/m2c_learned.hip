@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -22,6 +23,40 @@ struct m2c_mlp {
 };
 
 const MlpDev* m2c_mlp_dev(const m2c_mlp* m) { return m ? &m->d : nullptr; }
+
+// Scratch of the allocation-free solver: one learned guess per problem and
+// the two counters the solve kernel updates (no admissible star pressure,
+// acoustic starts).  One copy per GPU, held until the process ends; every
+// call on a GPU shares its copy, so calls that overlap on one GPU race.
+constexpr long long NOALLOC_MAX = M2C_NOALLOC_MAX_PROBLEMS;
+static __device__ __align__(256) double scratch[NOALLOC_MAX + 2];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch (the array's name is only a
+// host-side handle).  Looked up once per device, with that device current.
+hipError_t scratch_of_current_device(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
 
 namespace {
 
@@ -212,6 +247,25 @@ int m2c_riemann_solve_learned(const m2c_mlp* m, int64_t n, const double* in, con
     if (n_fallback) *n_fallback = (int64_t)hfb;
     if (rc == M2C_OK && hv > 0) rc = M2C_ERR_RIEMANN;
     return rc;
+}
+
+int m2c_riemann_solve_learned_noalloc(const m2c_mlp* m, int64_t n, const double* in, const double* eos, double rtol,
+                                      int32_t maxit, double* out, int32_t* iters, void* stream)
+{
+    if (n < 0 || n > NOALLOC_MAX || (n > 0 && (!in || !eos || !out))) return M2C_ERR_ARG;
+    if (!(rtol > 0.0) || maxit < 1) return M2C_ERR_ARG;
+    if (n == 0) return M2C_OK;
+    hipStream_t s = (hipStream_t)stream;
+    double* ws = nullptr;
+    if (scratch_of_current_device(&ws) != hipSuccess) return M2C_ERR_DEVICE;
+    // guesses in ws[0, n); the counters after the largest guess array are
+    // written by the solve kernel and read by no one, so they need no clearing
+    int32_t* dvac = reinterpret_cast<int32_t*>(ws + NOALLOC_MAX);
+    unsigned long long* dfb = reinterpret_cast<unsigned long long*>(ws + NOALLOC_MAX + 1);
+    if ((m && launch_points_guess(n, in, eos, m->d, ws, s) != hipSuccess) ||
+        launch_riemann_points(n, in, eos, m ? ws : nullptr, rtol, maxit, out, iters, dvac, dfb, s) != hipSuccess)
+        return M2C_ERR_DEVICE;
+    return M2C_OK;
 }
 
 }  // extern "C"
