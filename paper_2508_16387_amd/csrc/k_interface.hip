@@ -20,6 +20,7 @@
 #include "m2c_device.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
+#include "m2c_mlp_infer.h"
 
 namespace m2c {
 
@@ -385,10 +386,18 @@ __device__ __forceinline__ void cell_prim(const Grid& G, const eos::EosK* sEos, 
 
 // EG: general EOS per material (the Riemann solve of section "Equations of
 // state" with Hugoniot and isentrope wave curves, fluxes with each side's
-// EOS).
-template <bool EG>
-__device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk)
+// EOS).  LG: learned star-pressure guess (stiffened gases): each face first
+// takes the near-equilibrium test, and only a wavefront holding a face that
+// fails it loads the network and evaluates it (on the matrix cores, 64 faces
+// per pass); every other face starts Newton from the acoustic guess at no
+// extra cost.  The queue is then walked in whole wavefronts, since the
+// network needs every lane of one; its operands are read from memory as
+// they are needed, so that the kernel keeps the acoustic kernel's registers.
+template <bool EG, bool LG = false>
+__device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk,
+                                           const MlpDev* m = nullptr)
 {
+    static_assert(!(EG && LG), "the learned guess is for stiffened gases");
     __shared__ unsigned long long sCnt[3][4];
     __shared__ int sErr;
     __shared__ eos::EosK sEos[EG ? 2 : 1];
@@ -407,11 +416,15 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
     const Grid& G = a.g;
     const int n = sc->qlen;
     long long iters = 0, fallbacks = 0, mlp_fb = 0;
-    for (int q = blk * blockDim.x + threadIdx.x; q < n; q += nblk * blockDim.x) {
-        uint32_t c, cn;
-        int d;
-        face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], c, cn, d);
-        const int xa = a.chi[c], xb = a.chi[cn];
+    const int stride = nblk * blockDim.x;
+    // LG: wave-uniform trip count (q may pass n in the last pass)
+    const int qend = LG ? (n + 63) / 64 * 64 : n;
+    for (int q = blk * blockDim.x + threadIdx.x; q < qend; q += stride) {
+        const bool live = !LG || q < n;
+        uint32_t c = 0, cn = 0;
+        int d = 0;
+        if (live) face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], c, cn, d);
+        const int xa = live ? a.chi[c] : 0, xb = live ? a.chi[cn] : 0;
         double qa[5], qb[5];
         cell_prim<EG>(G, sEos, a.Win, c, xa, qa);
         cell_prim<EG>(G, sEos, a.Win, cn, xb, qb);
@@ -420,7 +433,19 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
         double out[4];
         bool used = false;
-        const bool hg = !EG && a.guess != nullptr;
+        bool hg = false;
+        double gs = 0.0;
+        if constexpr (LG) {
+            const bool skip = !live || acoustic_suffices(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB);
+            if (__ballot(!skip) != 0ull) {                       // wave-uniform
+                float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                double plo = 0.0, P = 1.0;
+                if (!skip) mlp_features(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, x, plo, P);
+                gs = guess64_mem(*m, x, plo, P, skip);
+                hg = !skip;
+            }
+            if (!live) continue;
+        }
         int it;
         if constexpr (EG) {
             // material 0 always on the left: where the lower cell holds
@@ -437,10 +462,12 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
             out[2] = flip ? o[3] : o[2];
             out[3] = flip ? o[2] : o[3];
         } else {
-            it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg,
-                               hg ? a.guess[q] : 0.0, out, &used);
+            it = riemann_solve(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB, G.rtol, G.maxit, hg, gs, out,
+                               &used);
         }
-        mlp_fb += hg && !used && it != 0;
+        // faces that started from the acoustic guess (near equilibrium, or
+        // the judge preferred it)
+        mlp_fb += LG && !used && it != 0;
         if (it == 0) {
             report_error(&sc->err, &sc->err_cell, ST_RIEMANN, c);
             continue;
@@ -515,13 +542,20 @@ __global__ __launch_bounds__(256) void k_fiver_eos(const IfaceArgs a, int record
     fiver_body<true>(a, record, blockIdx.x, gridDim.x);
 }
 
-hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s)
+__global__ __launch_bounds__(256) void k_fiver_learned(const IfaceArgs a, int record, const MlpDev m)
+{
+    fiver_body<false, true>(a, record, blockIdx.x, gridDim.x, &m);
+}
+
+hipError_t launch_fiver(const IfaceArgs& a, bool record, const MlpDev* mlp, hipStream_t s)
 {
     long long nb = (a.qcap + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
     if (a.g.eosg)
         hipLaunchKernelGGL(k_fiver_eos, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
+    else if (mlp)
+        hipLaunchKernelGGL(k_fiver_learned, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0, *mlp);
     else
         hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
     return hipGetLastError();
@@ -696,7 +730,6 @@ __device__ __forceinline__ IfaceArgs iface_of_run(const RunDesc& R, int stage)
     a.qcap = R.qcap;
     a.nblk = R.nblk_compact;
     a.sc = R.sc;
-    a.guess = nullptr;
     return a;
 }
 

@@ -17,24 +17,9 @@
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
 #include "m2c_mlp.h"
+#include "m2c_mlp_infer.h"
 
 namespace m2c {
-
-typedef __attribute__((__vector_size__(4 * sizeof(short)))) short bf16x4;
-typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
-
-// FP32 -> BF16, round to nearest even (finite inputs).
-__device__ __forceinline__ short to_bf16(float f)
-{
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-
-__device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
 
 // Sum over the 16 lanes of this lane's group (lanes with equal lane/16).
 __device__ __forceinline__ float group16_sum(float v)
@@ -394,169 +379,6 @@ __global__ void k_mlp_sync_bf16(const float* __restrict__ P, uint16_t* __restric
 hipError_t launch_mlp_sync(const MlpDev& m, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mlp_sync_bf16, dim3(18), dim3(256), 0, s, m.master, m.wbf);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Inference for the guess kernels.  A wave keeps the weights in registers
-// (the A operands of layers 1 and 2, and its lanes' biases and output
-// weights in the D layout) and evaluates 64 samples per pass: each lane
-// computes the features of one sample once, and the four 16-sample MFMA
-// tiles take their B operands from the owning lanes by shuffles.
-struct MlpRegs {
-    bf16x4 a1[4], a2[4][4];
-    float b1[4][4], b2[4][4], w3[4][4], b3;
-};
-
-__device__ __forceinline__ void mlp_load_regs(const float* __restrict__ P, const uint16_t* __restrict__ wbf,
-                                              MlpRegs& w)
-{
-    const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int k = 4 * g + e, h = 16 * t + 4 * g + e;
-            w.a1[t][e] = k < MLP_IN ? (short)wbf[MLP_OFF_W1 + (16 * t + r) * MLP_IN + k] : (short)0;
-            w.b1[t][e] = P[MLP_OFF_B1 + h];
-            w.b2[t][e] = P[MLP_OFF_B2 + h];
-            w.w3[t][e] = P[MLP_OFF_W3 + h];
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) w.a2[t][c][e] = (short)wbf[512 + (16 * t + r) * MLP_H + 16 * c + 4 * g + e];
-    }
-    w.b3 = P[MLP_OFF_B3];
-}
-
-// tanh through the hardware exponential and reciprocal: 1 - 2/(e^{2x} + 1)
-// (about 1e-7 absolute error, far below the BF16 rounding of the operands;
-// saturates correctly for large |x|).
-__device__ __forceinline__ float tanh_fast(float x)
-{
-    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * x) + 1.0f);
-}
-
-// y of the 16 samples whose layer-1 B operand is xb (sample l%16 in every
-// lane of that sample).
-__device__ __forceinline__ float mlp_infer16(const MlpRegs& w, bf16x4 xb)
-{
-    bf16x4 hb[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const f32x4 z = mfma(w.a1[t], xb, f32x4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-        for (int e = 0; e < 4; ++e) hb[t][e] = to_bf16(tanh_fast(z[e] + w.b1[t][e]));
-    }
-    float part = 0.f;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        f32x4 z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) z = mfma(w.a2[u][c], hb[c], z);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) part += w.w3[u][e] * tanh_fast(z[e] + w.b2[u][e]);
-    }
-    part += __shfl_xor(part, 16);
-    part += __shfl_xor(part, 32);
-    return part + w.b3;
-}
-
-// A problem whose two states differ by less than 1e-3 in pressure (relative
-// to the smaller p + p_c) and in normal velocity (relative to the smaller
-// sound speed): the acoustic guess is then exact to about 1e-6, far closer
-// than the network's, and is taken directly (the guess is left non-finite,
-// which the solver reads as "no candidate").
-__device__ __forceinline__ bool acoustic_suffices(double rL, double uL, double pL, double gL, double pcL, double rR,
-                                                  double uR, double pR, double gR, double pcR)
-{
-    const double aL = pL + pcL, aR = pR + pcR, du = uL - uR;
-    const double c2 = fmin(gL * aL / rL, gR * aR / rR);
-    return fabs(pL - pR) <= 1e-3 * fmin(aL, aR) && du * du <= 1e-6 * c2;
-}
-
-// Guesses of the wave's 64 samples (one per lane): features x, p_lo, P and
-// `skip` (no network: invalid lane or acoustic_suffices).  Tiles whose 16
-// samples all skip are not evaluated.
-__device__ __forceinline__ double guess64(const MlpRegs& w, const float x[8], double plo, double P, bool skip)
-{
-    const int l = threadIdx.x & 63, g = l >> 4, r = l & 15;
-    const uint64_t need = __ballot(!skip);
-    float y = 0.f;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (((need >> (16 * t)) & 0xffffull) == 0ull) continue;     // wave-uniform
-        float v[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = __shfl(x[k], 16 * t + r);
-        bf16x4 xb;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) xb[e] = g == 0 ? to_bf16(v[e]) : (g == 1 ? to_bf16(v[4 + e]) : (short)0);
-        const float yt = mlp_infer16(w, xb);
-        const float mine = __shfl(yt, r);
-        if (g == t) y = mine;
-    }
-    return skip ? __builtin_nan("") : plo + P * exp((double)y);
-}
-
-// Learned guesses for the FIVER work queue of one stage: features from the
-// two cells' own states, guess[q] = p_lo + P exp(y) (non-finite when the
-// network output is, or when the acoustic guess suffices).
-__device__ __forceinline__ void guess_body(const IfaceArgs& a, const MlpDev m, int blk, int nblk)
-{
-    DevScalars* sc = a.sc;
-    if (sc->err != 0) return;
-    const Grid& G = a.g;
-    const int n = sc->qlen;
-    const int l = threadIdx.x & 63;
-    const int wave = (blk * blockDim.x + threadIdx.x) >> 6, nw = (nblk * blockDim.x) >> 6;
-    if (wave * 64 >= n) return;                                   // wave-uniform
-    MlpRegs w;
-    bool loaded = false;                                          // weights fetched on first use
-    const uint32_t N = (uint32_t)G.N;
-    for (int c = wave; c * 64 < n; c += nw) {
-        const int q = c * 64 + l;
-        float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        double plo = 0.0, P = 1.0;
-        bool skip = true;
-        if (q < n) {
-            uint32_t cc, cn;
-            int d;
-            face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], cc, cn, d);
-            const int xa = a.chi[cc], xb = a.chi[cn];
-            double ua, va, wa, ub, vb, wb;
-            const double* W = a.Win;
-            const double pa = eos_prim(ldf(W, cc), ldf(W + N, cc), ldf(W + 2 * N, cc), ldf(W + 3 * N, cc),
-                                       ldf(W + 4 * N, cc), pick(G.gamma, xa) - 1.0, pick(G.gpc, xa), ua, va, wa);
-            const double pb = eos_prim(ldf(W, cn), ldf(W + N, cn), ldf(W + 2 * N, cn), ldf(W + 3 * N, cn),
-                                       ldf(W + 4 * N, cn), pick(G.gamma, xb) - 1.0, pick(G.gpc, xb), ub, vb, wb);
-            const double una = d == 0 ? ua : (d == 1 ? va : wa), unb = d == 0 ? ub : (d == 1 ? vb : wb);
-            const double ra = ldf(W, cc), rb = ldf(W, cn);
-            const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
-            skip = acoustic_suffices(ra, una, pa, gA, pcA, rb, unb, pb, gB, pcB);
-            if (!skip) mlp_features(ra, una, pa, gA, pcA, rb, unb, pb, gB, pcB, x, plo, P);
-        }
-        if (!loaded && __ballot(!skip) != 0ull) {                 // wave-uniform
-            mlp_load_regs(m.master, m.wbf, w);
-            loaded = true;
-        }
-        const double gs = guess64(w, x, plo, P, skip);
-        if (q < n) a.guess[q] = gs;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_fiver_guess(const IfaceArgs a, const MlpDev m)
-{
-    guess_body(a, m, blockIdx.x, gridDim.x);
-}
-
-hipError_t launch_fiver_guess(const IfaceArgs& a, const MlpDev& m, hipStream_t s)
-{
-    long long nb = (a.qcap + 255) / 256;
-    if (nb > 1024) nb = 1024;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_fiver_guess, dim3((unsigned)nb), dim3(256), 0, s, a, m);
     return hipGetLastError();
 }
 

@@ -63,7 +63,6 @@ struct m2c_ctx {
     long long prof_seq = 0;         // steps enqueued since profiling was switched on
     MlpDev mlp{};                   // context copy of the learned guess (null: acoustic)
     bool use_mlp = false;
-    double* guessbuf = nullptr;     // [qcap] learned guesses of the stage in flight
     std::vector<hipEvent_t> evpool;  // profiling: EV_STRIDE events per timed step
     int ev_steps = 0;               // steps recorded in the pool, not yet harvested
     double ms_stage = 0, ms_fiver = 0, ms_other = 0;
@@ -232,7 +231,6 @@ IfaceArgs iface_args(m2c_ctx* c, const double* Win)
     a.qcap = c->qcap;
     a.nblk = c->nblk_compact;
     a.sc = c->sc;
-    a.guess = nullptr;
     return a;
 }
 
@@ -342,11 +340,7 @@ int enqueue_step(m2c_ctx* c, int p, double dt_imposed, const PhaseArgs* prev, Ph
     for (int k = 0; k < S; ++k) {
         if (ev) HIPCHK(c, hipEventRecord(ev[1 + 2 * k], s));
         ia.Win = st[k].win;
-        if (c->use_mlp) {
-            ia.guess = c->guessbuf;
-            HIPCHK(c, launch_fiver_guess(ia, c->mlp, s));
-        }
-        HIPCHK(c, launch_fiver(ia, k == S - 1, s));
+        HIPCHK(c, launch_fiver(ia, k == S - 1, c->use_mlp ? &c->mlp : nullptr, s));
         if (ev) HIPCHK(c, hipEventRecord(ev[2 + 2 * k], s));
         sa.Win = st[k].win;
         sa.W0 = c->W[p];
@@ -502,7 +496,6 @@ void m2c_destroy(m2c_ctx* c)
     (void)hipFree(c->sc);
     (void)hipFree(c->mlp.master);
     (void)hipFree(c->mlp.wbf);
-    (void)hipFree(c->guessbuf);
     if (c->hsc) (void)hipHostFree(c->hsc);
     for (auto& e : c->evpool) (void)hipEventDestroy(e);
     delete c;
@@ -897,7 +890,6 @@ int m2c_set_guess(m2c_ctx* c, const m2c_mlp* m)
     if (!c->mlp.master) {
         HIPCHK(c, hipMalloc((void**)&c->mlp.master, MLP_NPARAM * sizeof(float)));
         HIPCHK(c, hipMalloc((void**)&c->mlp.wbf, MLP_NBF * sizeof(uint16_t)));
-        HIPCHK(c, hipMalloc((void**)&c->guessbuf, c->qcap * sizeof(double)));
     }
     HIPCHK(c, hipMemcpyAsync(c->mlp.master, src->master, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToDevice,
                              c->stream));

@@ -56,7 +56,6 @@ struct IfaceArgs {
     long long qcap;
     int nblk;                      // compaction blocks
     DevScalars* sc;
-    double* guess;                 // [qcap] learned star-pressure guesses, or null (acoustic)
 };
 
 struct PhaseArgs {
@@ -95,7 +94,8 @@ constexpr int COMPACT_CELLS_PER_BLOCK = COMPACT_THREADS * COMPACT_CELLS_PER_THRE
 hipError_t launch_compact(const IfaceArgs& a, const PhaseArgs* prev_phase, bool end_prev, bool begin,
                           double dt_imposed, hipStream_t s);
 hipError_t launch_end_step(DevScalars* sc, int stages, hipStream_t s);
-hipError_t launch_fiver(const IfaceArgs& a, bool record, hipStream_t s);
+// mlp: the learned guess (null: acoustic).
+hipError_t launch_fiver(const IfaceArgs& a, bool record, const MlpDev* mlp, hipStream_t s);
 hipError_t launch_phase(const PhaseArgs& a, hipStream_t s);
 // Batched forms: cmap maps each compaction block to (run, block of run).
 hipError_t launch_compact_batch(const RunDesc* runs, int nruns, const int2* cmap, int ncblocks, hipStream_t s);
@@ -113,7 +113,6 @@ hipError_t launch_fill_f32(float* p, long long n, float v, hipStream_t s);
 hipError_t launch_adam(const MlpDev& md, float* m, float* v, float* grad, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_mlp_sync(const MlpDev& m, hipStream_t s);
-hipError_t launch_fiver_guess(const IfaceArgs& a, const MlpDev& m, hipStream_t s);
 hipError_t launch_points_guess(long long n, const double* in, const double* eos, const MlpDev& m, double* guess,
                                hipStream_t s);
 
