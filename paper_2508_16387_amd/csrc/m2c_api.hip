@@ -522,14 +522,24 @@ int m2c_create(const m2c_config* cfg, m2c_ctx** out)
     if (c->qcap > 65536 && c->qcap > N) c->qcap = N > 65536 ? N : 65536;
     c->nblk_compact = (int)((N + COMPACT_CELLS_PER_BLOCK - 1) / COMPACT_CELLS_PER_BLOCK);
 
-    // stage tiles: (tile_x, tile_y) or 16x16; planes per block tile_z or 8
+    // stage tiles: (tile_x, tile_y), else 16x15 (its 511 in-plane faces are
+    // exactly two rounds of the block's 256 threads; the general-EOS kernels
+    // come in 16x16), 64x2 for quasi-1D grids.  Planes per block: tile_z,
+    // else 16 when that still leaves at least 4096 blocks (16 rounds of two
+    // blocks per CU: the prologue of a block's march is amortised over more
+    // planes), otherwise 8.
     c->tx = cfg->tile_x ? cfg->tile_x : 16;
-    c->ty = cfg->tile_y ? cfg->tile_y : 16;
+    c->ty = cfg->tile_y ? cfg->tile_y : (c->g.eosg ? 16 : 15);
     if (!cfg->tile_x && c->g.ny == 1) {
         c->tx = 64;
         c->ty = 2;
     }
-    c->kz = cfg->tile_z ? cfg->tile_z : 8;
+    if (cfg->tile_z) {
+        c->kz = cfg->tile_z;
+    } else {
+        const long long txy = (long long)((c->g.nx + c->tx - 1) / c->tx) * ((c->g.ny + c->ty - 1) / c->ty);
+        c->kz = txy * ((c->g.nz + 15) / 16) >= 4096 ? 16 : 8;
+    }
     if (c->kz > c->g.nz) c->kz = c->g.nz;
     c->tiles[0] = (c->g.nx + c->tx - 1) / c->tx;
     c->tiles[1] = (c->g.ny + c->ty - 1) / c->ty;
@@ -790,11 +800,12 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
 
 int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
 {
-    static const int cands_sg[][3] = {{16, 16, 8}, {16, 16, 4}, {32, 8, 8}, {16, 15, 8}, {32, 7, 8}, {16, 15, 4}};
+    static const int cands_sg[][3] = {{16, 15, 8},  {16, 15, 16}, {16, 16, 8}, {16, 16, 16},
+                                      {16, 16, 4},  {32, 8, 8},   {32, 7, 8},  {16, 15, 4}};
     static const int cands_eos[][3] = {{16, 16, 8}, {16, 16, 4}};
     if (!c || steps < 1) return M2C_ERR_ARG;
     const int(*cands)[3] = c->g.eosg ? cands_eos : cands_sg;
-    const int ncand = c->g.eosg ? 2 : 6;
+    const int ncand = c->g.eosg ? 2 : 8;
     if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
     HIPCHK(c, hipSetDevice(c->device));
     int rc = pull_scalars(c);

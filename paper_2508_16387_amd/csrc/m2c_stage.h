@@ -284,8 +284,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 
     // Halo ring of a plane (x-halo: 4 columns x TY rows; y-halo: 4 rows x TX
     // columns), HPT cells per thread at most; its raw state is loaded one
-    // plane ahead (during the residual of the previous plane) and turned
-    // into primitives when the plane is staged.
+    // plane ahead (in the single-grid default kernels right after the
+    // previous plane's halo is staged, so that the face work hides its
+    // latency; otherwise after the face work) and turned into primitives
+    // when the plane is staged.
     constexpr int HPT = (4 * TX + 4 * TY + NT - 1) / NT;
     const int nxh = xact ? 4 * TY : 0, nyh = yact ? 4 * TX : 0;
     auto halo_pos = [&](int h, int& li, int& lj) {
@@ -412,6 +414,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 sX[o] = x;
             }
         }
+        // halo of the next plane: its registers are free once this plane's
+        // halo is staged, and the face work below covers the load latency
+        // (the batched, option and general-EOS kernels, whose register
+        // budget this would exceed, load it after the face work)
+        constexpr bool EARLY_HALO = PF && LM && !OPTS && !EG;
+        if (EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         __syncthreads();
 
         // (3) x- and y-faces of the tile as one work list, one code path (the
@@ -482,7 +490,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (inside) qzhi = zface(k, Q0, S0, X0, Q1, S1, X1, Fzhi);
         }
         __syncthreads();
-        if (PF && k + 1 < kz1) halo_load(k + 1);
+        if (PF && !EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
 
         // (5) residual and stage update of cell (gi, gj, k)
         if (inside) {
