@@ -128,6 +128,20 @@ __device__ __forceinline__ T lim_slope(int limiter, int k, T dm, T dp, T alpha)
     return va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
 }
 
+// The limited slope, or 0 where the cell's stencil along the axis reaches
+// the other material (flat).  For the MC limiter the flag joins the
+// limiter's own sign test, so the slope stays one select and never becomes
+// a divergent branch per variable.
+template <typename T>
+__device__ __forceinline__ T lim_slope_flat(int limiter, int k, T dm, T dp, T alpha, bool flat)
+{
+    if (limiter == LIM_MC) {
+        const T a = fmin(alpha * fmin(fabs(dm), fabs(dp)), T(0.5) * fabs(dm + dp));
+        return ((!flat) & (dm * dp > T(0))) ? copysign(a, dp) : T(0);
+    }
+    return flat ? T(0) : va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
+}
+
 // --------------------------------------------------------------- HLLC ------
 // Flux through a face with normal +n in the face frame: state = (rho, u_n,
 // v_t1, v_t2, p).  Davis wave speeds, contact speed S_*, and the star state

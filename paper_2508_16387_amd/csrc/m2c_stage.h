@@ -49,7 +49,10 @@
 #define M2C_STAGE_WAVES 1
 #endif
 #ifndef M2C_STAGE_WAVES_MIXED
-#define M2C_STAGE_WAVES_MIXED 4
+// Mixed form: three waves per SIMD fit without private-memory spills
+// (142-144 VGPRs); four needed ~60 B of scratch per lane and measured slower
+// on the 384^3 cloud (3.62 against 3.31 ms per stage launch).
+#define M2C_STAGE_WAVES_MIXED 3
 #endif
 
 namespace m2c {
@@ -191,7 +194,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                       TF s[5]) {
         const bool flat = (xm != x0) || (xp != x0);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) s[v] = flat ? TF(0) : lim_slope<TF>(lim, limk, q0[v] - qm[v], qp[v] - q0[v], alpha);
+        for (int v = 0; v < 5; ++v) s[v] = lim_slope_flat<TF>(lim, limk, q0[v] - qm[v], qp[v] - q0[v], alpha, flat);
     };
     // z-face between planes k (lower) and k+1.  A single-material face gets
     // its HLLC flux in F and slot -1; an interface face returns the queue
@@ -444,8 +447,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 for (int v = 0; v < 5; ++v) {
                     const TF* s = sQ + comp[v] * PL;
                     const TF m1 = s[oA - step], a0 = s[oA], b0 = s[oB], p1 = s[oB + step];
-                    const TF sa = flatA ? TF(0) : lim_slope<TF>(lim, limk, a0 - m1, b0 - a0, alpha);
-                    const TF sb = flatB ? TF(0) : lim_slope<TF>(lim, limk, b0 - a0, p1 - b0, alpha);
+                    const TF sa = lim_slope_flat<TF>(lim, limk, a0 - m1, b0 - a0, alpha, flatA);
+                    const TF sb = lim_slope_flat<TF>(lim, limk, b0 - a0, p1 - b0, alpha, flatB);
                     qa[v] = a0 + TF(0.5) * sa;
                     qb[v] = b0 - TF(0.5) * sb;
                 }
@@ -503,13 +506,25 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             // (lower face: the flux seen by its upper cell, i.e. this one;
             // upper face: the flux seen by its lower cell)
             const long long Q = a.qcap;
+            // (the interface fluxes are fetched under one branch per face, not
+            // one per variable: most wavefronts hold no interface face)
             auto axis = [&](int qlo, int qhi, const TF* flo, const TF* fhi, int stride, double rh) {
+                double lo[5], hi[5];
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
-                    const double lo = qlo >= 0 ? a.fluxF[(5 + v) * Q + qlo] : (double)flo[v * stride];
-                    const double hi = qhi >= 0 ? a.fluxF[v * Q + qhi] : (double)fhi[v * stride];
-                    acc[v] += (hi - lo) * rh;
+                    lo[v] = (double)flo[v * stride];
+                    hi[v] = (double)fhi[v * stride];
                 }
+                if (qlo >= 0) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) lo[v] = a.fluxF[(5 + v) * Q + qlo];
+                }
+                if (qhi >= 0) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) hi[v] = a.fluxF[v * Q + qhi];
+                }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[v] += (hi[v] - lo[v]) * rh;
             };
             if (xact) {
                 const int fl = ty * (TX + 1) + tx, fr = fl + 1;
@@ -521,9 +536,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             }
             if (zact) axis(qzlo, qzhi, Fzlo, Fzhi, 1, G.rh[2]);
             // level set: third-order upwind-biased differences, upwinded by V_d of the cell
+            // (both one-sided differences are formed and one is selected, so
+            // the five level-set values are read up front rather than inside
+            // a divergent branch per axis)
             auto ls_term = [&](double V, double f0, double f1, double f2, double f3, double f4, double rh6) {
-                const double D = V > 0.0 ? (2.0 * f3 + 3.0 * f2 - 6.0 * f1 + f0) * rh6
-                               : (V < 0.0 ? (-f4 + 6.0 * f3 - 3.0 * f2 - 2.0 * f1) * rh6 : 0.0);
+                double Dm = (2.0 * f3 + 3.0 * f2 - 6.0 * f1 + f0) * rh6;
+                double Dp = (-f4 + 6.0 * f3 - 3.0 * f2 - 2.0 * f1) * rh6;
+                // keep both in the straight-line code (the compiler would
+                // otherwise sink each, with its LDS reads, into a branch)
+                asm volatile("" : "+v"(Dm), "+v"(Dp));
+                const double D = V > 0.0 ? Dm : (V < 0.0 ? Dp : 0.0);
                 return V * D;
             };
             // stage-input state of the cell (FP64)

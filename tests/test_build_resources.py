@@ -1,7 +1,8 @@
 """Register and LDS budget of the stage kernels (compile-time, no GPU).
 
 The FP64 stage kernels are sized for two waves per SIMD without private-
-memory spills; the mixed-precision ones for four waves per SIMD.  A change
+memory spills; the mixed-precision ones for three waves per SIMD, also
+without spills.  A change
 that silently pushes a kernel past its budget (spills to scratch, or a drop
 in occupancy) costs far more than it saves, so the compiler's own resource
 report is checked here."""
@@ -90,12 +91,13 @@ def test_fp64_stage_kernels_fit_two_waves_without_spills(stage_resources):
         assert 2 * r["lds"] <= 160 * 1024, (n, r)
 
 
-def test_mixed_stage_kernels_keep_four_waves(stage_resources):
+def test_mixed_stage_kernels_keep_three_waves_without_spills(stage_resources):
     ks = {n: r for n, r in stage_resources.items() if "k_stage" in n and "Ef" in n and any(t in n for t in TUNED)}
     assert len(ks) == 24, sorted(ks)
     for n, r in ks.items():
-        assert r["occupancy"] == 4, (n, r)
-        assert r["vgpr"] <= 128, (n, r)
+        assert r["scratch"] == 0, (n, r)
+        assert r["occupancy"] >= 3, (n, r)
+        assert r["vgpr"] + r["agpr"] <= 168, (n, r)
 
 
 def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resources):
