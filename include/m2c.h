@@ -304,9 +304,11 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
  * weights on the matrix cores, FP32 accumulation) maps eight dimensionless
  * features of a problem to y = ln((p* - p_lo)/P), p_lo = -min(pc_L, pc_R),
  * P = sqrt((p_L - p_lo)(p_R - p_lo)).  The solver starts Newton from the
- * learned guess p_lo + P exp(y) only when it is finite, admissible and has a
- * smaller |g| than the acoustic guess ("fallback and judge"), then iterates
- * to the same tolerance, so the star state does not depend on the network.
+ * learned guess p_lo + P exp(y) only when it is finite, admissible and its
+ * |g| is no larger than the value the tangent of g there predicts at the
+ * acoustic guess; otherwise from the acoustic guess ("fallback and judge").
+ * It then iterates to the same tolerance, so the star state does not depend
+ * on the network.
  * Parameters: 4801 FP32 values, W1 (64x8 row-major), b1 (64), W2 (64x64
  * row-major), b2 (64), w3 (64), b3 (1).  Device pointers below are in the
  * given stream's device memory; n-long arrays are SoA. */

@@ -400,8 +400,9 @@ __device__ __forceinline__ double rside_star_rho(const RSide& s, double g, doubl
 }
 
 // Safeguarded Newton from the acoustic guess, or from a candidate guess
-// when one is given and its |g| is smaller (the candidate must be finite and
-// above p_lo); then bisection if maxit steps did not meet
+// when one is given and its |g| is no larger than the tangent at it predicts
+// for the acoustic guess (the candidate must be finite and above p_lo); then
+// bisection if maxit steps did not meet
 // |dp| <= rtol (p - p_lo).  Returns the Newton step count (negative:
 // bisection fallback, 0: no admissible root).  out = (p*, u*, rho*_L,
 // rho*_R); *used (nullable) tells whether the candidate was the start.
@@ -424,23 +425,23 @@ __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, do
     const double ZL = L.rc, ZR = R.rc;
     const double pac = (ZR * pL + ZL * pR + ZL * ZR * (uL - uR)) / (ZL + ZR);
     double p = fmax(pac, plo + 1e-6 * fmin(pL - plo, pR - plo));
-    // judged start: g and g' of both candidates; the chosen pair is the
-    // first Newton step's (the same values the loop would compute)
+    // judged start: g and g' at the candidate (they are the first Newton
+    // step's when it is kept); the acoustic start's |g| is predicted from the
+    // tangent there, and the candidate is kept unless the acoustic start is
+    // predicted closer to the root.  (g is increasing and concave, so the
+    // tangent bounds g from above and Newton converges from either start.)
     bool first = false;
     double g0 = 0.0, d0 = 1.0;
     if (have_guess && isfinite(guess) && guess > plo) {
-        double dgL, dgR, daL, daR;
+        double dgL, dgR;
         const double gg = rside_f(L, guess, dgL) + rside_f(R, guess, dgR) + du;
-        const double ga = rside_f(L, p, daL) + rside_f(R, p, daR) + du;
-        first = true;
-        if (fabs(gg) < fabs(ga)) {
+        const double dg = dgL + dgR;
+        if (fabs(gg) <= fabs(gg + dg * (p - guess))) {
+            first = true;
             p = guess;
             g0 = gg;
-            d0 = dgL + dgR;
+            d0 = dg;
             if (used) *used = true;
-        } else {
-            g0 = ga;
-            d0 = daL + daR;
         }
     }
     int it = 0;

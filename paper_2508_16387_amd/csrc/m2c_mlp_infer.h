@@ -101,9 +101,10 @@ __device__ __forceinline__ float mlp_infer16(const MlpRegs& w, bf16x4 xb)
 __device__ __forceinline__ bool acoustic_suffices(double rL, double uL, double pL, double gL, double pcL, double rR,
                                                   double uR, double pR, double gR, double pcR)
 {
-    const double aL = pL + pcL, aR = pR + pcR, du = uL - uR;
-    const double c2 = fmin(gL * aL / rL, gR * aR / rR);
-    return fabs(pL - pR) <= 1e-3 * fmin(aL, aR) && du * du <= 1e-6 * c2;
+    // du^2 <= 1e-6 min(c_L^2, c_R^2), with c_K^2 = g_K a_K / r_K, written
+    // without divisions
+    const double aL = pL + pcL, aR = pR + pcR, du = uL - uR, du2 = du * du;
+    return fabs(pL - pR) <= 1e-3 * fmin(aL, aR) && du2 * rL <= 1e-6 * (gL * aL) && du2 * rR <= 1e-6 * (gR * aR);
 }
 
 // Guesses of the wave's 64 samples (one per lane): features x, p_lo, P and

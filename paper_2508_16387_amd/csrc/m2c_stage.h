@@ -548,10 +548,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 const double D = V > 0.0 ? Dm : (V < 0.0 ? Dp : 0.0);
                 return V * D;
             };
-            // stage-input state of the cell (FP64)
+            // stage-input state of the cell (FP64).  The FP64 stiffened-gas
+            // kernels rebuild it from the cell's primitives in the column
+            // window (a few roundings from the stored values: the update of
+            // the conservative state stays conservative to round-off), which
+            // saves re-reading 40 B per cell that the cache no longer holds
+            // three planes after the lead load; the other forms re-read it.
             double wi[5];
+            if constexpr (sizeof(TF) == sizeof(double) && !EG) {
+                const double r = Q0[0];
+                wi[0] = r;
+                wi[1] = r * Q0[1];
+                wi[2] = r * Q0[2];
+                wi[3] = r * Q0[3];
+                wi[4] = eos_energy<double>(r, Q0[1], Q0[2], Q0[3], Q0[4], mat(X0, MAT_GPC), mat(X0, MAT_IGM1));
+            } else {
 #pragma unroll
-            for (int v = 0; v < 5; ++v) wi[v] = ldf(Win + v * N, c);
+                for (int v = 0; v < 5; ++v) wi[v] = ldf(Win + v * N, c);
+            }
             // cell velocity for the level-set upwinding, in FP64
             double Vc[3];
             if constexpr (sizeof(TF) == sizeof(double)) {
