@@ -2,10 +2,13 @@
 
 One benchmark step is one full time step of the hot path (CFL time step,
 interface compaction, two TVD-RK2 stages each with FIVER interface fluxes
-and the fused bulk stage kernel, phase update) on the 128^3 shock-bubble
-workload: unit box, air bubble of radius 0.15 at a seed-jittered centre in
-water at 1e5 Pa, planar water shock of 1e8 Pa at x = 0.1, transmissive
-boundaries, CFL 0.4.  The state is resident in HBM before the timed region.
+and the fused bulk stage kernel, phase update).  The default workload is the
+largest single-GPU configuration: the 384^3 cloud of 32 air bubbles (radii
+U[0.02, 0.06], seed-drawn non-overlapping centres) in water at 1e5 Pa with a
+5e7 Pa water slab at x < 0.05, transmissive boundaries, CFL 0.4, FP64, all
+50 steps of the workload timed by default.  ``--workload shock_bubble_128``
+selects the 128^3 shock-bubble instead.  The state is resident in HBM before
+the timed region.
 
 Prints one JSON line; see ``--help``.
 """
@@ -30,36 +33,44 @@ BYTES_STAGE1, BYTES_STAGE2 = 97, 145
 
 PROFILE_EVERY = 10
 
+# Workloads the headline can run on: builder, default step count (the
+# workload's own length).
+WORKLOADS = {
+    "cloud_384": "bubble_cloud_384^3",
+    "shock_bubble_128": "shock_bubble_128^3",
+}
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=50,
+                    help="timed steps (default 50: the whole 384^3 cloud workload)")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=128, help="grid edge (default 128)")
+    ap.add_argument("--workload", choices=list(WORKLOADS), default="cloud_384")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4,
-                    help="oracle steps timed for the CPU baseline (bounded sample)")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the mixed-precision, batched and standalone-FIVER measurements")
+                    help="skip the other forms (mixed, batched, standalone solvers, options, ...)")
     ap.add_argument("--batch-steps", type=int, default=100)
-    ap.add_argument("--cloud-steps", type=int, default=10,
-                    help="steps timed on the 384^3 bubble cloud (0 skips it)")
+    ap.add_argument("--in-situ-advance", type=int, default=400,
+                    help="untimed steps of the 384^3 cloud before the in-situ learned-guess "
+                         "comparison (the slab's shock reaches the first bubbles)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (reference "
                          "for scaling hardware byte counters to bytes)")
     return ap.parse_args()
 
 
-def measured_traffic(precision):
-    """HBM bytes per stage launch from the committed rocprofv3 counter
-    summary, if it was taken on the stage-kernel sources as they are now."""
+def _profile_record(kind, workload, precision):
+    """A committed per-launch counter record (HBM bytes or VALU
+    instructions) of the stage kernel on this workload, if it was taken on
+    the stage-kernel sources as they are now."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "k_stage_traffic.json")
-    if precision != "fp64" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"k_stage_{workload}_{precision}_{kind}.json")
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     m = hashlib.sha256()
@@ -67,7 +78,14 @@ def measured_traffic(precision):
         m.update(open(os.path.join(ROOT, src), "rb").read())
     if m.hexdigest()[:16] != rec["source_sha256_16"]:
         return None
-    return rec["bytes_per_launch_mean"]
+    return rec
+
+
+def measured_traffic(workload, precision):
+    """Counted HBM bytes per stage launch (FETCH_SIZE and WRITE_SIZE scaled by
+    the copy calibration)."""
+    rec = _profile_record("traffic", workload, precision)
+    return None if rec is None else rec["bytes_per_launch_mean"]
 
 
 # VALU issue peak: one wave64 VALU instruction per CU per clock (a SIMD
@@ -77,9 +95,8 @@ VALU_PEAK = 256 * 2.4e9 * 64
 
 
 def valu_line(instr_per_cell, cells, launch_ms):
-    """The stage kernel against the VALU issue roof (the bound it meets
-    first in FP64): instructions per cell from the counters, rate from the
-    live launch time."""
+    """The stage kernel against the VALU issue roof: instructions per cell
+    from the counters, rate from the live launch time."""
     if instr_per_cell is None:
         return None
     rate = instr_per_cell * cells / (launch_ms * 1e-3)
@@ -87,21 +104,40 @@ def valu_line(instr_per_cell, cells, launch_ms):
             "unit": "lane-instructions/s", "frac": rate / VALU_PEAK}
 
 
-def measured_valu(precision):
-    """VALU lane-instructions per cell-update of the stage kernel from the
-    committed SQ counter summary, if it was taken on the current sources."""
-    import hashlib
+def measured_valu(workload, precision):
+    """VALU lane-instructions per cell-update of the stage kernel."""
+    rec = _profile_record("valu", workload, precision)
+    return None if rec is None else rec["valu_instr_per_cell_mean"]
 
-    path = os.path.join(ROOT, "profiles", "k_stage_valu.json")
-    if precision != "fp64" or not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    m = hashlib.sha256()
-    for src in rec["sources"]:
-        m.update(open(os.path.join(ROOT, src), "rb").read())
-    if m.hexdigest()[:16] != rec["source_sha256_16"]:
-        return None
-    return rec["valu_instr_per_cell_mean"]
+
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_problem(workload, seed):
+    import workloads as W
+    if workload == "cloud_384":
+        return W.bubble_cloud(seed)
+    return W.shock_bubble(seed, n=128)
+
+
+def device_ms(torch, fn, reps, warm=2):
+    """Median device time of fn() over reps launches, from events recorded
+    on the current stream around each call (fn must not synchronise)."""
+    for _ in range(warm):
+        fn()
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        fn()
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times.sort()
+    return times[len(times) // 2], times
 
 
 def time_sim(m2c, torch, problem, precision, steps, warmup, tile=None):
@@ -162,23 +198,21 @@ def batched_forms(m2c, torch, steps):
     return out
 
 
-def fiver_standalone(m2c, torch, n=1_000_000):
-    """Exact two-material Riemann solves/s on n water/air problems."""
+def fiver_standalone(m2c, torch, n=1_000_000, reps=20):
+    """Exact two-material Riemann solves/s on n water/air problems (acoustic
+    guess), device time as the median of ``reps`` launches."""
     import workloads as W
 
     inp, eos = W.riemann_problem_set(1, n)
     di = torch.tensor(inp.T.copy(), device="cuda")
     de = torch.tensor(eos.T.copy(), device="cuda")
-    m2c.riemann_solve(di, de)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out, iters, rc = m2c.riemann_solve(di, de)
-    torch.cuda.synchronize()
-    T = time.perf_counter() - t0
-    it = iters.abs().double()
-    ok = (iters != 0)
-    return {"problems": n, "solves_per_s": n / T, "ms": T * 1e3,
-            "newton_iters_per_solve": float(it[ok].mean()), "vacuum": int((~ok).sum())}
+    out = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    it = torch.empty((n,), dtype=torch.int32, device="cuda")
+    ms, _ = device_ms(torch, lambda: m2c.riemann_solve_learned_async(None, di, de, out=out, iters=it), reps)
+    itd = it.abs().double()
+    ok = (it != 0)
+    return {"problems": n, "launches": reps, "solves_per_s": n / (ms * 1e-3), "ms": ms,
+            "newton_iters_per_solve": float(itd[ok].mean()), "vacuum": int((~ok).sum())}
 
 
 def general_eos_standalone(m2c, torch, n=1 << 20):
@@ -297,52 +331,65 @@ def host_round_trip(m2c, torch, problem, steps):
             "download_ms": (t3 - t2) * 1e3, "value_pcie_inclusive": problem.ncells * steps * 2 / (t3 - t0)}
 
 
-def cloud_forms(m2c, torch, steps):
-    """384^3 cloud of 32 air bubbles in water (50 steps in the workload; a
-    bounded number of them timed here): FP64 vs mixed precision, and the
-    learned star-pressure guess against the acoustic one on the FP64 path."""
+def mixed_vs_fp64(m2c, torch, problem, steps, warmup, value_fp64):
+    """The mixed-precision form on the same workload and steps."""
+    v, T = time_sim(m2c, torch, problem, m2c.M2C_PREC_MIXED, steps, warmup)
+    return {"value": v, "ms_per_step": T * 1e3 / steps, "speedup_mixed_vs_fp64": v / value_fp64}
+
+
+def second_workload(m2c, torch, name, seed, steps):
+    """FP64 and mixed on the other workload, over its whole length."""
+    p = make_problem(name, seed)
+    out = {"workload": WORKLOADS[name], "steps": steps}
+    for prec, key in ((m2c.M2C_PREC_FP64, "fp64"), (m2c.M2C_PREC_MIXED, "mixed")):
+        v, T = time_sim(m2c, torch, p, prec, steps, 2)
+        out[key] = {"value": v, "ms_per_step": T * 1e3 / steps}
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    return out
+
+
+def in_situ_guess(m2c, torch, problem, advance, steps):
+    """The learned star-pressure guess in the grid step against the acoustic
+    one, timed after ``advance`` untimed steps (by then the slab's shock has
+    reached bubbles, so interface faces see real waves): FIVER kernel time
+    per launch from the library's events, Newton steps per solve, faces that
+    took the acoustic start."""
     import numpy as np
 
-    import workloads as W
-
-    p = W.bubble_cloud(0)
-    out = {"workload": "bubble_cloud_384^3: 32 air bubbles r~U[0.02,0.06] in water, 5e7 Pa slab at x<0.05",
-           "cells": p.ncells, "steps_timed": steps}
     net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess.npy")))
-    runs = (("fp64", m2c.M2C_PREC_FP64, None), ("mixed", m2c.M2C_PREC_MIXED, None),
-            ("fp64_learned_guess", m2c.M2C_PREC_FP64, net))
-    for name, prec, guess in runs:
-        sim = m2c.Sim(m2c.config_for(p, precision=prec))
-        sim.set_stream(torch.cuda.current_stream())
-        sim.set_state(p.prim)
-        if guess is not None:
-            sim.set_guess(guess)
-        sim.step(1)
-        sim.set_state(p.prim)
+    sim = m2c.Sim(m2c.config_for(problem))
+    sim.set_stream(torch.cuda.current_stream())
+    sim.set_state(problem.prim)
+    sim.step(advance)
+    w0 = sim.get_conserved()
+    out = {"advance_steps": advance, "steps_timed": steps}
+    for name, guess in (("acoustic", None), ("learned", net)):
+        sim.set_conserved(w0)
+        sim.set_guess(guess)
         sim.reset_stats()
-        sim.set_profiling(True)
+        sim.set_profiling(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         sim.step(steps)
         torch.cuda.synchronize()
         T = time.perf_counter() - t0
         st = sim.stats()
-        out[name] = {"value": p.ncells * steps * 2 / T, "ms_per_step": T * 1e3 / steps,
-                     "stage_ms_per_launch": st["ms_stage"] / max(st["stage_launches"], 1),
+        out[name] = {"ms_per_step": T * 1e3 / steps,
                      "fiver_ms_per_launch": st["ms_fiver"] / max(st["fiver_launches"], 1),
                      "riemann_solves": st["riemann_solves"],
                      "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1),
-                     "learned_guess_rejected": st["mlp_fallbacks"] if guess is not None else None}
-        sim.close()
-    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    out["fiver_speedup_learned_vs_acoustic"] = (out["fp64"]["fiver_ms_per_launch"] /
-                                                out["fp64_learned_guess"]["fiver_ms_per_launch"])
+                     "acoustic_starts": st["mlp_fallbacks"] if guess is not None else None}
+    sim.set_profiling(0)
+    sim.close()
+    out["fiver_speedup_learned_vs_acoustic"] = (out["acoustic"]["fiver_ms_per_launch"] /
+                                                out["learned"]["fiver_ms_per_launch"])
     return out
 
 
-def learned_standalone(m2c, torch, n=1_000_000):
+def learned_standalone(m2c, torch, n=1_000_000, reps=20):
     """Held-out water/air Riemann problems: Newton steps and solves/s with the
-    judged learned guess against the acoustic guess."""
+    judged learned guess against the acoustic guess, device time as the
+    median of ``reps`` launches."""
     import numpy as np
 
     import workloads as W
@@ -351,32 +398,75 @@ def learned_standalone(m2c, torch, n=1_000_000):
     di = torch.tensor(inp.T.copy(), device="cuda")
     de = torch.tensor(eos.T.copy(), device="cuda")
     net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess.npy")))
-    res = {"problems": n}
+    res = {"problems": n, "launches": reps}
     for name, guess in (("acoustic", None), ("learned", net)):
-        m2c.riemann_solve_learned(guess, di, de)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out, it, rc, nfb = m2c.riemann_solve_learned(guess, di, de)
-        torch.cuda.synchronize()
-        T = time.perf_counter() - t0
-        it = it.abs().double()
-        ok = it > 0
-        res[name] = {"solves_per_s": n / T, "newton_iters_per_solve": float(it[ok].mean()),
+        out = torch.empty((4, n), dtype=torch.float64, device="cuda")
+        it = torch.empty((n,), dtype=torch.int32, device="cuda")
+        ms, _ = device_ms(torch, lambda: m2c.riemann_solve_learned_async(guess, di, de, out=out, iters=it), reps)
+        _, _, _, nfb = m2c.riemann_solve_learned(guess, di, de)
+        itd = it.abs().double()
+        ok = itd > 0
+        res[name] = {"solves_per_s": n / (ms * 1e-3), "ms": ms, "newton_iters_per_solve": float(itd[ok].mean()),
                      "acoustic_starts": int(nfb) if guess is not None else None}
     res["speedup_learned_vs_acoustic"] = res["learned"]["solves_per_s"] / res["acoustic"]["solves_per_s"]
     return res
 
 
-def cpu_baseline(problem, steps):
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "nproc": avail, "os_cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _slab(problem, nz):
+    """The first nz z-planes of a problem as a problem of its own
+    (transmissive at the cut)."""
+    import copy
+    q = copy.copy(problem)
+    q.n = (problem.n[0], problem.n[1], nz)
+    q.hi = (problem.hi[0], problem.hi[1], problem.lo[2] + (problem.hi[2] - problem.lo[2]) * nz / problem.n[2])
+    q.prim = problem.prim[:, :nz].copy()
+    return q
+
+
+def cpu_baseline(problem, workload, steps=1):
+    """The oracle on the host cores: the all-core (OpenMP) build on the whole
+    grid and the single-threaded build on a slab of it, `steps` steps each,
+    in the GPU metric's unit."""
     import oracle
 
     oracle.build(force=False)
-    s = oracle.OracleSim(problem)
+    oracle.build(force=False, openmp=True)
+    N = problem.ncells
+    lib_omp = oracle.lib_openmp()
+    threads = int(lib_omp.ora_num_threads())
+    s = oracle.OracleSim(problem, lib_handle=lib_omp)
     t0 = time.perf_counter()
     rc = s.step(steps)
-    t = time.perf_counter() - t0
+    t_all = time.perf_counter() - t0
     assert rc == 0
-    N = problem.ncells
+    del s
+    progress(f"cpu baseline: all-core oracle step done ({t_all:.1f} s on {threads} threads)")
+    nz1 = max(1, problem.n[2] // 8)
+    q = _slab(problem, nz1)
+    s1 = oracle.OracleSim(q)
+    t0 = time.perf_counter()
+    rc = s1.step(steps)
+    t_one = time.perf_counter() - t0
+    assert rc == 0
+    del s1
+    nx, ny, nz = problem.n
     # the general-EOS Riemann oracle on a sample of the mixed problem set
     import workloads as W
     from oracle import riemann_eos as RE
@@ -387,10 +477,14 @@ def cpu_baseline(problem, steps):
     t0 = time.perf_counter()
     RE.solve(inp, mat, eos)
     te = time.perf_counter() - t0
-    return {"value": N * steps * 2 / t, "unit": "cell-updates/s per RK stage", "cores": 1,
+    return {"value": N * steps * 2 / t_all, "unit": "cell-updates/s per RK stage", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {steps} steps of the same {problem.n[0]}x{problem.n[1]}x{problem.n[2]} "
-                      f"shock-bubble run, single-threaded C oracle ({t:.1f} s)",
+            "sample": f"first {steps} step(s) of the {nx}x{ny}x{nz} {WORKLOADS[workload]} run, C oracle built "
+                      f"with OpenMP on {threads} threads ({t_all:.1f} s)",
+            "single_core": {"value": q.ncells * steps * 2 / t_one, "cores": 1,
+                            "sample": f"first {steps} step(s) of the {nx}x{ny}x{nz1} bottom slab of the same "
+                                      f"initial state, serial C oracle ({t_one:.1f} s)"},
+            "host": host_info(),
             "general_eos_riemann": {"solves_per_s": ne / te, "cores": 1,
                                     "sample": f"first {ne} problems of the mixed general-EOS set, Python/scipy "
                                               f"oracle ({te:.1f} s)"}}
@@ -415,9 +509,10 @@ def main():
         return
 
     import paper_2508_16387_amd as m2c
-    import workloads as W
 
-    p = W.shock_bubble(args.seed, n=args.n)
+    t_ic = time.perf_counter()
+    p = make_problem(args.workload, args.seed)
+    progress(f"initial state of {WORKLOADS[args.workload]} built ({time.perf_counter() - t_ic:.1f} s)")
     prec = m2c.M2C_PREC_MIXED if args.precision == "mixed" else m2c.M2C_PREC_FP64
     sim = m2c.Sim(m2c.config_for(p, precision=prec))
     stream = torch.cuda.current_stream()
@@ -436,14 +531,30 @@ def main():
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     st = sim.stats()
+    sim.set_profiling(0)
     N = p.ncells
     value = N * args.steps * 2 / T
 
     stage_ms = st["ms_stage"] / max(st["stage_launches"], 1)
     fiver_ms = st["ms_fiver"] / max(st["fiver_launches"], 1)
     bytes_per_launch = N * (BYTES_STAGE1 + BYTES_STAGE2) / 2
-    traffic = measured_traffic(args.precision)
+    traffic = measured_traffic(args.workload, args.precision)
     achieved = bytes_per_launch / (stage_ms * 1e-3) / 1e9
+    valu = valu_line(measured_valu(args.workload, args.precision), N, stage_ms)
+    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_launch": bytes_per_launch, "traffic": traffic,
+           "traffic_frac": (None if traffic is None else traffic / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)}
+    # the roof the stage kernel comes closest to: VALU issue (counted
+    # instructions) when the counter record matches the sources, else HBM
+    if valu is not None and valu["frac"] > (hbm["traffic_frac"] or hbm["frac"]):
+        roof = {"bound": "alu", "achieved": valu["achieved"], "peak": VALU_PEAK, "unit": "lane-instructions/s",
+                "frac": valu["frac"], "traffic": traffic, "valu_instr_per_cell": valu["instr_per_cell"], "hbm": hbm}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_frac": hbm["traffic_frac"],
+                "valu": valu}
+    roof.update({"kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
+                 "algorithmic_bytes_per_launch": bytes_per_launch})
     out = {
         "metric": "cell-updates/s per RK stage",
         "value": value,
@@ -457,42 +568,49 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == m2c.M2C_PREC_FP64 else "f64+f32",
         "data": "synthetic",
-        "config": {"workload": f"shock_bubble_{args.n}^3", "grid": [args.n] * 3, "steps": args.steps,
-                   "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl, "seed": args.seed},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_frac": (None if traffic is None
-                                      else traffic / (stage_ms * 1e-3) / 1e9 / HBM_PEAK_GBS),
-                     "valu": valu_line(measured_valu(args.precision), N, stage_ms),
-                     "kernel": "k_stage (both RK stages)", "avg_launch_ms": stage_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "config": {"workload": WORKLOADS[args.workload], "grid": list(p.n), "steps": args.steps,
+                   "workload_steps": p.steps, "precision": args.precision, "rk": "TVD-RK2", "cfl": p.cfl,
+                   "seed": args.seed},
+        "roofline": roof,
         "fiver": {"solves": st["riemann_solves"], "ms_per_launch": fiver_ms,
                   "solves_per_s": st["riemann_solves"] / (2 * args.steps) / max(fiver_ms * 1e-3, 1e-12),
                   "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1)},
         "time_split_ms_per_step": {k: st[f"ms_{k}"] * 2 / max(st["stage_launches"], 1)
                                    for k in ("stage", "fiver", "other")},
     }
+    progress(f"headline {WORKLOADS[args.workload]}: {value:.4g} cell-updates/s per stage, "
+             f"stage kernel {stage_ms:.3f} ms per launch")
     if not args.no_forms:
-        other = m2c.M2C_PREC_MIXED if prec == m2c.M2C_PREC_FP64 else m2c.M2C_PREC_FP64
-        v_other, _ = time_sim(m2c, torch, p, other, args.steps, args.warmup)
-        v64, vmx = (value, v_other) if prec == m2c.M2C_PREC_FP64 else (v_other, value)
-        out["forms"] = {
-            "fp64": v64,
-            "mixed": vmx,
-            "speedup_mixed_vs_fp64": vmx / v64,
-            "batched": batched_forms(m2c, torch, args.batch_steps),
-            "fiver_standalone": fiver_standalone(m2c, torch),
-            "learned_guess_standalone": learned_standalone(m2c, torch),
-            "general_eos_riemann": general_eos_standalone(m2c, torch),
-            "reinit_128": reinit_form(m2c, torch, p),
-            "general_eos_step_128": general_eos_step(m2c, torch),
-            "scheme_options_128": scheme_options(m2c, torch, p),
-            "host_round_trip": host_round_trip(m2c, torch, p, args.steps),
-        }
-        if args.cloud_steps > 0:
-            out["forms"]["cloud_384"] = cloud_forms(m2c, torch, args.cloud_steps)
+        other = "shock_bubble_128" if args.workload == "cloud_384" else "cloud_384"
+        forms = {}
+
+        def form(name, fn, *a):
+            t = time.perf_counter()
+            forms[name] = fn(*a)
+            progress(f"form {name} done ({time.perf_counter() - t:.1f} s)")
+
+        if prec == m2c.M2C_PREC_FP64:
+            form("mixed", mixed_vs_fp64, m2c, torch, p, args.steps, args.warmup, value)
+        form("host_round_trip", host_round_trip, m2c, torch, p, args.steps)
+        if args.workload == "cloud_384" and args.in_situ_advance > 0:
+            form("in_situ_learned_guess", in_situ_guess, m2c, torch, p, args.in_situ_advance, 20)
+        sim.close()
+        form(other, second_workload, m2c, torch, other, args.seed, 100 if other == "shock_bubble_128" else 50)
+        p128 = make_problem("shock_bubble_128", args.seed)
+        form("batched", batched_forms, m2c, torch, args.batch_steps)
+        form("fiver_standalone", fiver_standalone, m2c, torch)
+        form("learned_guess_standalone", learned_standalone, m2c, torch)
+        form("general_eos_riemann", general_eos_standalone, m2c, torch)
+        form("reinit_128", reinit_form, m2c, torch, p128)
+        form("general_eos_step_128", general_eos_step, m2c, torch)
+        form("scheme_options_128", scheme_options, m2c, torch, p128)
+        out["forms"] = forms
+    else:
+        sim.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_steps)
+        t = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(p, args.workload)
+        progress(f"cpu baseline done ({time.perf_counter() - t:.1f} s)")
     print(json.dumps(out), flush=True)
 
 
