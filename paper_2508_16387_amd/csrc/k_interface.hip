@@ -485,19 +485,25 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
             num_flux<double>(G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], gB, pcB,
                              pick(G.gpc, xb), pick(G.inv_gm1, xb), Fu);
         }
-        const long long Q = a.qcap;
-        // face frame (mass, normal, t1, t2, energy) -> global components
-        a.fluxF[0 * Q + q] = Fl[0];
-        a.fluxF[(1 + d) * Q + q] = Fl[1];
-        a.fluxF[t1 * Q + q] = Fl[2];
-        a.fluxF[t2 * Q + q] = Fl[3];
-        a.fluxF[4 * Q + q] = Fl[4];
-        a.fluxF[5 * Q + q] = Fu[0];
-        a.fluxF[(6 + d) * Q + q] = Fu[1];
-        a.fluxF[(5 + t1) * Q + q] = Fu[2];
-        a.fluxF[(5 + t2) * Q + q] = Fu[3];
-        a.fluxF[9 * Q + q] = Fu[4];
+        // face frame (mass, normal, t1, t2, energy) -> global components;
+        // the ten fluxes of a face are contiguous (one address per face for
+        // the stage kernel that reads them)
+        double* const fq = a.fluxF + 10 * (long long)q;
+        double fo[10];
+        fo[0] = Fl[0];
+        fo[1 + d] = Fl[1];
+        fo[t1] = Fl[2];
+        fo[t2] = Fl[3];
+        fo[4] = Fl[4];
+        fo[5] = Fu[0];
+        fo[6 + d] = Fu[1];
+        fo[5 + t1] = Fu[2];
+        fo[5 + t2] = Fu[3];
+        fo[9] = Fu[4];
+#pragma unroll
+        for (int v = 0; v < 10; ++v) fq[v] = fo[v];
         if (record) {
+            const long long Q = a.qcap;
             a.star[0 * Q + q] = ps;
             a.star[1 * Q + q] = us;
             a.star[2 * Q + q] = out[2];

@@ -62,7 +62,7 @@ struct Bufs {
     uint8_t* chi[2];               // material ids of the two states
     int32_t* queue;                // interface face ids, ascending
     int32_t* fslot;                // [3N] face id -> queue index, or -1
-    double* fluxF;                 // [10][qcap]: flux for the lower cell (5), upper cell (5)
+    double* fluxF;                 // [qcap][10]: flux for the lower cell (5), upper cell (5)
     double* star;                  // [8][qcap]: p*, u*, rho*_L, rho*_R, vt1_L, vt2_L, vt1_R, vt2_R
     int32_t* flips;                // [N] flipped cells of the step in flight
     int32_t* blockcnt;             // compaction partial counts

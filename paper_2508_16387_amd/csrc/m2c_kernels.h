@@ -36,7 +36,7 @@ struct StageArgs {
     uint8_t* chi_next;             // last stage: ids of the new level set
     int32_t* flips;                // last stage: flipped cells (append)
     const int32_t* fslot;          // [3N] face -> queue slot or -1
-    const double* fluxF;           // [10][qcap] one-sided interface fluxes
+    const double* fluxF;           // [qcap][10] one-sided interface fluxes
     long long qcap;
     DevScalars* sc;
     int tiles_x, tiles_y, tiles_z, kz;
@@ -50,7 +50,7 @@ struct IfaceArgs {
     const uint8_t* chi;            // ids frozen for the step
     int32_t* queue;
     int32_t* fslot;
-    double* fluxF;                 // [10][qcap]
+    double* fluxF;                 // [qcap][10]
     double* star;                  // [8][qcap]
     int32_t* blockcnt;
     long long qcap;

@@ -504,8 +504,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             // flux difference across one axis: single-material fluxes from LDS
             // (or registers for z), interface faces from the FP64 FIVER buffer
             // (lower face: the flux seen by its upper cell, i.e. this one;
-            // upper face: the flux seen by its lower cell)
-            const long long Q = a.qcap;
+            // upper face: the flux seen by its lower cell; the ten fluxes of
+            // an interface face are contiguous: lower cell's 5, upper cell's 5)
             // (the interface fluxes are fetched under one branch per face, not
             // one per variable: most wavefronts hold no interface face)
             auto axis = [&](int qlo, int qhi, const TF* flo, const TF* fhi, int stride, double rh) {
@@ -516,12 +516,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     hi[v] = (double)fhi[v * stride];
                 }
                 if (qlo >= 0) {
+                    const double* f = a.fluxF + 10 * (long long)qlo + 5;
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) lo[v] = a.fluxF[(5 + v) * Q + qlo];
+                    for (int v = 0; v < 5; ++v) lo[v] = f[v];
                 }
                 if (qhi >= 0) {
+                    const double* f = a.fluxF + 10 * (long long)qhi;
 #pragma unroll
-                    for (int v = 0; v < 5; ++v) hi[v] = a.fluxF[v * Q + qhi];
+                    for (int v = 0; v < 5; ++v) hi[v] = f[v];
                 }
 #pragma unroll
                 for (int v = 0; v < 5; ++v) acc[v] += (hi[v] - lo[v]) * rh;
