@@ -366,15 +366,16 @@ __global__ __launch_bounds__(COMPACT_THREADS) void k_scatter(const IfaceArgs a)
 //   F_lower = HLLC(W_L, W*_L; EOS of the lower cell)
 //   F_upper = HLLC(W*_R, W_R; EOS of the upper cell)
 // with the arguments ordered along the face normal.
-template <bool EG>
+// FS: the set of the materials' families (EG; eos::fam_set)
+template <bool EG, int FS = eos::FAM_ALL>
 __device__ __forceinline__ void cell_prim(const Grid& G, const eos::EosK* sEos, const double* __restrict__ W,
                                           uint32_t c, int x, double q[5])
 {
     const uint32_t N = (uint32_t)G.N;
     double u, v, w;
     if constexpr (EG)
-        q[4] = geos_prim(sEos[x], ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
-                         u, v, w);
+        q[4] = geos_prim<FS>(sEos[x], ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c),
+                             ldf(W + 4 * N, c), u, v, w);
     else
         q[4] = eos_prim(ldf(W, c), ldf(W + N, c), ldf(W + 2 * N, c), ldf(W + 3 * N, c), ldf(W + 4 * N, c),
                         pick(G.gamma, x) - 1.0, pick(G.gpc, x), u, v, w);
@@ -393,7 +394,10 @@ __device__ __forceinline__ void cell_prim(const Grid& G, const eos::EosK* sEos, 
 // extra cost.  The queue is then walked in whole wavefronts, since the
 // network needs every lane of one; its operands are read from memory as
 // they are needed, so that the kernel keeps the acoustic kernel's registers.
-template <bool EG, bool LG = false>
+// F0, F1 (EG): families of materials 0 and 1 fixed at compile time, so that
+// a kernel carries the wave curves and EOS forms of those two families only
+// (-1: dispatched at run time).
+template <bool EG, bool LG = false, int F0 = -1, int F1 = -1>
 __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk,
                                            const MlpDev* m = nullptr)
 {
@@ -414,6 +418,7 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
     __syncthreads();
     if (sErr != 0) return;
     const Grid& G = a.g;
+    constexpr int FS = eos::fam_set(F0) | eos::fam_set(F1);
     const int n = sc->qlen;
     long long iters = 0, fallbacks = 0, mlp_fb = 0;
     const int stride = nblk * blockDim.x;
@@ -426,8 +431,8 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         if (live) face_cells(G.nx, G.ny, G.nz, (uint32_t)a.queue[q], c, cn, d);
         const int xa = live ? a.chi[c] : 0, xb = live ? a.chi[cn] : 0;
         double qa[5], qb[5];
-        cell_prim<EG>(G, sEos, a.Win, c, xa, qa);
-        cell_prim<EG>(G, sEos, a.Win, cn, xb, qb);
+        cell_prim<EG, FS>(G, sEos, a.Win, c, xa, qa);
+        cell_prim<EG, FS>(G, sEos, a.Win, cn, xb, qb);
         const int t1 = 1 + (d + 1) % 3, t2 = 1 + (d + 2) % 3;
         const double ua = qa[1 + d], ub = qb[1 + d];
         const double gA = pick(G.gamma, xa), pcA = pick(G.pc, xa), gB = pick(G.gamma, xb), pcB = pick(G.pc, xb);
@@ -456,7 +461,7 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
             const double in[6] = {flip ? qb[0] : qa[0], flip ? -ub : ua, flip ? qb[4] : qa[4],
                                   flip ? qa[0] : qb[0], flip ? -ua : ub, flip ? qa[4] : qb[4]};
             double o[4];
-            it = eos::solve_pair(sEos[0], sEos[1], in, G.rtol, G.maxit, G.rds, o);
+            it = eos::solve_pair<eos::fam_set(F0), eos::fam_set(F1)>(sEos[0], sEos[1], in, G.rtol, G.maxit, G.rds, o);
             out[0] = o[0];
             out[1] = flip ? -o[1] : o[1];
             out[2] = flip ? o[3] : o[2];
@@ -477,8 +482,8 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         const double ps = out[0], us = out[1];
         double Fl[5], Fu[5];
         if constexpr (EG) {
-            geos_flux(sEos[xa], G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, Fl);
-            geos_flux(sEos[xb], G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], Fu);
+            geos_flux<FS>(sEos[xa], G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, Fl);
+            geos_flux<FS>(sEos[xb], G.flux, out[3], us, qb[t1], qb[t2], ps, qb[0], ub, qb[t1], qb[t2], qb[4], Fu);
         } else {
             num_flux<double>(G.flux, qa[0], ua, qa[t1], qa[t2], qa[4], out[2], us, qa[t1], qa[t2], ps, gA, pcA,
                              pick(G.gpc, xa), pick(G.inv_gm1, xa), Fl);
@@ -543,10 +548,23 @@ __global__ __launch_bounds__(256) void k_fiver(const IfaceArgs a, int record)
     fiver_body<false>(a, record, blockIdx.x, gridDim.x);
 }
 
+template <int F0, int F1>
 __global__ __launch_bounds__(256) void k_fiver_eos(const IfaceArgs a, int record)
 {
-    fiver_body<true>(a, record, blockIdx.x, gridDim.x);
+    fiver_body<true, false, F0, F1>(a, record, blockIdx.x, gridDim.x);
 }
+
+template <int F0, int F1>
+void launch_fiver_eos(const IfaceArgs& a, unsigned nb, int record, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fiver_eos<F0, F1>), dim3(nb), dim3(256), 0, s, a, record);
+}
+using FiverEosLaunch = void (*)(const IfaceArgs&, unsigned, int, hipStream_t);
+// by 3 family(material 0) + family(material 1), families NASG, MG, JWL = 0, 1, 2
+constexpr FiverEosLaunch kFiverEos[9] = {launch_fiver_eos<0, 0>, launch_fiver_eos<0, 1>, launch_fiver_eos<0, 2>,
+                                         launch_fiver_eos<1, 0>, launch_fiver_eos<1, 1>, launch_fiver_eos<1, 2>,
+                                         launch_fiver_eos<2, 0>, launch_fiver_eos<2, 1>, launch_fiver_eos<2, 2>};
+static_assert(M2C_EOS_NASG == 0 && M2C_EOS_MG == 1 && M2C_EOS_JWL == 2, "family-pair table order");
 
 __global__ __launch_bounds__(256) void k_fiver_learned(const IfaceArgs a, int record, const MlpDev m)
 {
@@ -558,9 +576,11 @@ hipError_t launch_fiver(const IfaceArgs& a, bool record, const MlpDev* mlp, hipS
     long long nb = (a.qcap + 255) / 256;
     if (nb > 1024) nb = 1024;
     if (nb < 1) nb = 1;
-    if (a.g.eosg)
-        hipLaunchKernelGGL(k_fiver_eos, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);
-    else if (mlp)
+    if (a.g.eosg) {
+        const int f0 = a.g.ek[0].fam, f1 = a.g.ek[1].fam;
+        if (f0 < 0 || f0 > 2 || f1 < 0 || f1 > 2) return hipErrorInvalidValue;
+        kFiverEos[3 * f0 + f1](a, (unsigned)nb, record ? 1 : 0, s);
+    } else if (mlp)
         hipLaunchKernelGGL(k_fiver_learned, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0, *mlp);
     else
         hipLaunchKernelGGL(k_fiver, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0);

@@ -8,7 +8,14 @@
 // JWL, RK4 walks for Mie-Grueneisen), and a wavefront runs as long as its
 // slowest lane, so a set that mixes material pairs is first grouped by pair
 // (a counting sort over the at most 64 pair keys) and solved through that
-// permutation: the lanes of a wavefront then share their materials.
+// permutation: the lanes of a wavefront then share their materials.  The
+// keys are laid out family pair by family pair (NASG, Mie-Grueneisen, JWL on
+// each side).  A set of one family pair is solved by a kernel compiled for
+// exactly those two families, which carries neither the code nor the
+// registers of the others; a set of several family pairs takes one launch of
+// the kernel that dispatches on the families at run time, so that the groups
+// run side by side (launches per group, one after another on the stream,
+// would each wait for the slowest wavefront of the one before).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -44,14 +51,42 @@ __global__ __launch_bounds__(256) void k_pair_count(long long n, const int32_t* 
         if (h[k]) atomicAdd(&counts[k], h[k]);
 }
 
-// cursor = exclusive prefix sum of counts (one thread; NKEY entries)
-__global__ void k_pair_scan(const int32_t* __restrict__ counts, int32_t* __restrict__ cursor)
+// Family-pair group of every key: 3 min(famL, famR) + max(famL, famR) for
+// the keys of the table (a problem whose right family is the lower one is
+// solved mirrored), NFP - 1 for the key of indices outside it.
+constexpr int NFP = 10;
+struct KeyGroups {
+    int32_t g[NKEY];
+};
+
+// Order of the groups in the permutation: the costliest first (both sides
+// Mie-Grueneisen, whose rarefactions walk the isentrope by RK4, then one
+// side, then JWL, then NASG), so that a launch over a mixed set starts its
+// slowest wavefronts first instead of ending on them.  The groups 3 MG +
+// NASG, 3 JWL + NASG and 3 JWL + MG stay empty.
+constexpr int kGroupOrder[NFP] = {3 * M2C_EOS_MG + M2C_EOS_MG,    3 * M2C_EOS_NASG + M2C_EOS_MG,
+                                  3 * M2C_EOS_MG + M2C_EOS_JWL,   3 * M2C_EOS_JWL + M2C_EOS_JWL,
+                                  3 * M2C_EOS_NASG + M2C_EOS_JWL, 3 * M2C_EOS_NASG + M2C_EOS_NASG,
+                                  3 * M2C_EOS_MG + M2C_EOS_NASG,  3 * M2C_EOS_JWL + M2C_EOS_NASG,
+                                  3 * M2C_EOS_JWL + M2C_EOS_MG,   NFP - 1};
+
+// cursor = exclusive prefix sum of counts with the keys taken group by group
+// in kGroupOrder, so that each family pair's problems occupy one range of
+// slots: range[2 f] .. range[2 f + 1] (one thread; NKEY x NFP steps)
+__global__ void k_pair_scan(const int32_t* __restrict__ counts, int32_t* __restrict__ cursor, const KeyGroups kg,
+                            int32_t* __restrict__ range)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         int32_t acc = 0;
-        for (int k = 0; k < NKEY; ++k) {
-            cursor[k] = acc;
-            acc += counts[k];
+        for (int o = 0; o < NFP; ++o) {
+            const int f = kGroupOrder[o];
+            range[2 * f] = acc;
+            for (int k = 0; k < NKEY; ++k)
+                if (kg.g[k] == f) {
+                    cursor[k] = acc;
+                    acc += counts[k];
+                }
+            range[2 * f + 1] = acc;
         }
     }
 }
@@ -77,19 +112,49 @@ __global__ __launch_bounds__(256) void k_pair_place(long long n, const int32_t* 
     if (i < n) perm[base[key] + rank] = (int32_t)i;
 }
 
-// perm (nullable): thread t solves problem perm[t]
-__global__ __launch_bounds__(256) void k_riemann_eos(long long n, const double* __restrict__ in,
-                                                     const int32_t* __restrict__ mat, const EosTable tab,
-                                                     double rtol, int maxit, double hmax,
-                                                     double* __restrict__ out, int32_t* __restrict__ iters,
-                                                     int32_t* __restrict__ nbad, const int32_t* __restrict__ perm)
+// Waves per SIMD the compiler fits a family pair's kernel to: two where
+// neither side is Mie-Grueneisen (a few registers spilled at most), one with
+// its branch-point walks and for the run-time dispatch (no spills there).
+template <int FA, int FB>
+constexpr int kWavesPerSimd = (FA >= 0 && FB >= 0 && FA != M2C_EOS_MG && FB != M2C_EOS_MG) ? 2 : 1;
+
+// Slots range[0] .. range[1] of the permutation perm (whole set without
+// them: thread t solves problem t).  FA <= FB: every problem of the range
+// has one material of family FA and one of family FB, in either order,
+// inside the table (the grouping guarantees it); one with FB on the left is
+// solved mirrored (x -> -x: the sides swap and the velocities change sign),
+// which leaves p* and negates u*.  FA = FB = -1: any materials, indices
+// checked, families dispatched at run time.
+template <int FA, int FB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<FA, FB>))) void k_riemann_eos(
+    long long n, const double* __restrict__ in, const int32_t* __restrict__ mat, const EosTable tab, double rtol,
+    int maxit, double hmax, double* __restrict__ out, int32_t* __restrict__ iters, int32_t* __restrict__ nbad,
+    const int32_t* __restrict__ perm, const int32_t* __restrict__ range)
 {
+    static_assert(FA <= FB, "family pair in canonical order");
+    const long long lo = range ? (long long)range[0] : 0, hi = range ? (long long)range[1] : n;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+    for (long long t = lo + (long long)blockIdx.x * blockDim.x + threadIdx.x; t < hi; t += stride) {
         const long long i = perm ? (long long)perm[t] : t;
         double q[6], res[4];
         for (int k = 0; k < 6; ++k) q[k] = in[k * n + i];
-        const int its = solve_one(tab, mat[i], mat[n + i], q, rtol, maxit, hmax, res);
+        const int ml = mat[i], mr = mat[n + i];
+        int its;
+        if constexpr (FA >= 0) {
+            const bool flip = FA != FB && tab.m[ml].fam != FA;
+            const double qm[6] = {flip ? q[3] : q[0], flip ? -q[4] : q[1], flip ? q[5] : q[2],
+                                  flip ? q[0] : q[3], flip ? -q[1] : q[4], flip ? q[2] : q[5]};
+            its = solve_pair<fam_set(FA), fam_set(FB)>(tab.m[flip ? mr : ml], tab.m[flip ? ml : mr], qm, rtol, maxit,
+                                                       hmax, res);
+            if (flip) {
+                const double r = res[2];
+                res[1] = -res[1];
+                res[2] = res[3];
+                res[3] = r;
+            }
+        } else {
+            its = solve_one(tab, ml, mr, q, rtol, maxit, hmax, res);
+        }
         if (its == 0) atomicAdd(nbad, 1);
         for (int k = 0; k < 4; ++k) out[k * n + i] = res[k];
         if (iters) iters[i] = its;
@@ -124,6 +189,35 @@ unsigned grid_for(long long n)
     return (unsigned)(b < 1 ? 1 : (b > 65536 ? 65536 : b));
 }
 
+struct SolveArgs {
+    long long n;
+    const double* in;
+    const int32_t* mat;
+    EosTable tab;
+    double rtol;
+    int maxit;
+    double hmax;
+    double* out;
+    int32_t* iters;
+    int32_t* nbad;
+    const int32_t* perm;
+};
+
+template <int FL, int FR>
+void launch_solve(const SolveArgs& a, unsigned grid, const int32_t* range, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_riemann_eos<FL, FR>), dim3(grid), dim3(256), 0, s, a.n, a.in, a.mat, a.tab, a.rtol,
+                       a.maxit, a.hmax, a.out, a.iters, a.nbad, a.perm, range);
+}
+
+using SolveLaunch = void (*)(const SolveArgs&, unsigned, const int32_t*, hipStream_t);
+// by family-pair group 3 FA + FB, FA <= FB (families M2C_EOS_NASG, _MG, _JWL
+// = 0, 1, 2; the other groups stay empty)
+constexpr SolveLaunch kSolvePair[9] = {launch_solve<0, 0>, launch_solve<0, 1>, launch_solve<0, 2>,
+                                       nullptr,            launch_solve<1, 1>, launch_solve<1, 2>,
+                                       nullptr,            nullptr,            launch_solve<2, 2>};
+static_assert(M2C_EOS_NASG == 0 && M2C_EOS_MG == 1 && M2C_EOS_JWL == 2, "family-pair table order");
+
 }  // namespace
 }  // namespace m2c
 
@@ -141,33 +235,60 @@ extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t*
     if (!prepare(nmat, eos, tab)) return M2C_ERR_ARG;
     if (n == 0) return M2C_OK;
     hipStream_t s = (hipStream_t)hip_stream;
-    // grouping by material pair pays once the set is large and mixes pairs
-    const bool group = nmat > 1 && n >= 4096 && n < (1LL << 31);
-    // workspace (int32): failure count, key counts, key cursors, permutation
-    const long long words = 1 + 2 * NKEY + (group ? n : 0);
+    // grouped by material pair, and within that by family pair (32-bit slots)
+    const bool group = n < (1LL << 31);
+    // workspace (int32): failure count, key counts, key cursors, family-pair
+    // ranges, permutation
+    const long long words = 1 + 2 * NKEY + 2 * NFP + (group ? n : 0);
     int32_t* dbad = nullptr;
     if (hipMalloc((void**)&dbad, words * sizeof(int32_t)) != hipSuccess) return M2C_ERR_NOMEM;
     int32_t* counts = dbad + 1;
     int32_t* cursor = counts + NKEY;
-    int32_t* perm = group ? cursor + NKEY : nullptr;
+    int32_t* range = cursor + NKEY;
+    int32_t* perm = group ? range + 2 * NFP : nullptr;
     int32_t hb = 0;
     int rc = M2C_OK;
+    const SolveArgs sa{(long long)n, in, mat, tab, rtol, (int)maxit, ds, out, iters, dbad, perm};
     if (hipMemsetAsync(dbad, 0, (1 + NKEY) * sizeof(int32_t), s) != hipSuccess) rc = M2C_ERR_DEVICE;
     if (rc == M2C_OK && group) {
+        KeyGroups kg;
+        for (int k = 0; k < NKEY; ++k) {
+            kg.g[k] = NFP - 1;
+            if (k >= nmat * nmat) continue;
+            const int fl = tab.m[k / (int)nmat].fam, fr = tab.m[k % (int)nmat].fam;
+            kg.g[k] = fl < fr ? 3 * fl + fr : 3 * fr + fl;
+        }
         const unsigned nb = (unsigned)((n + 255) / 256);
+        int32_t hr[2 * NFP] = {};
         hipLaunchKernelGGL(k_pair_count, dim3(nb), dim3(256), 0, s, (long long)n, mat, (int)nmat, counts);
-        hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(64), 0, s, counts, cursor);
+        hipLaunchKernelGGL(k_pair_scan, dim3(1), dim3(64), 0, s, counts, cursor, kg, range);
         hipLaunchKernelGGL(k_pair_place, dim3(nb), dim3(256), 0, s, (long long)n, mat, (int)nmat, cursor, perm);
-        if (hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
-    }
-    if (rc == M2C_OK) {
-        hipLaunchKernelGGL(k_riemann_eos, dim3(grid_for(n)), dim3(256), 0, s, (long long)n, in, mat, tab, rtol,
-                           (int)maxit, ds, out, iters, dbad, (const int32_t*)perm);
+        // the group sizes decide the launch (one read-back; the call
+        // synchronises at its end anyway)
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(&hb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(hr, range, sizeof(hr), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             rc = M2C_ERR_DEVICE;
+        int only = -1, nonempty = 0;
+        for (int f = 0; f < NFP; ++f)
+            if (hr[2 * f + 1] > hr[2 * f]) {
+                only = f;
+                ++nonempty;
+            }
+        if (rc == M2C_OK && nonempty == 1 && only < NFP - 1 && kSolvePair[only]) {
+            kSolvePair[only](sa, grid_for(hr[2 * only + 1] - hr[2 * only]), range + 2 * only, s);
+        } else if (rc == M2C_OK) {
+            launch_solve<-1, -1>(sa, grid_for(n), nullptr, s);
+        }
+        if (rc == M2C_OK && hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
+    } else if (rc == M2C_OK) {
+        launch_solve<-1, -1>(sa, grid_for(n), nullptr, s);
+        if (hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
     }
+    if (rc == M2C_OK &&
+        (hipMemcpyAsync(&hb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipStreamSynchronize(s) != hipSuccess))
+        rc = M2C_ERR_DEVICE;
     (void)hipFree(dbad);
     if (rc == M2C_OK && hb > 0) rc = M2C_ERR_RIEMANN;
     return rc;

@@ -70,6 +70,27 @@ struct EosTable {
 };
 constexpr int KVMIN = 10, KFLOOR = 11;
 
+// Sets of families as bit masks (bit f for family f = M2C_EOS_NASG, _MG,
+// _JWL): the code below is compiled for a set S of families that the
+// material may have.  A kernel that knows its materials' families keeps only
+// their code; ALL dispatches on the material's tag at run time.
+constexpr int FAM_ALL = 7;
+constexpr int fam_set(int f) { return f < 0 ? FAM_ALL : 1 << f; }
+
+// Family of material m as the code dispatches on it: a constant for a
+// one-family set, a choice between the two families of a two-family set
+// (so the compiler drops the third family's branch), the tag otherwise.
+template <int S>
+M2C_HD inline int fam_of(const EosK& m)
+{
+    static_assert(S >= 1 && S <= FAM_ALL, "family set");
+    if constexpr (S == 1 || S == 2 || S == 4) return S == 1 ? 0 : (S == 2 ? 1 : 2);
+    else if constexpr (S == 3) return m.fam == 1 ? 1 : 0;
+    else if constexpr (S == 5) return m.fam == 2 ? 2 : 0;
+    else if constexpr (S == 6) return m.fam == 2 ? 2 : 1;
+    else return m.fam;
+}
+
 // Mie-Grueneisen reference curves and their eta-derivatives.
 struct Ref {
     double pR, eR, dpR, deR;
@@ -125,10 +146,11 @@ M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
 }
 
 // e(v, p)
+template <int S = FAM_ALL>
 M2C_HD double eos_e(const EosK& m, double v, double p)
 {
-    if (m.fam == M2C_EOS_NASG) return (p + m.k[5]) * (v - m.k[2]) * m.k[4] + m.k[3];
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_NASG) return (p + m.k[5]) * (v - m.k[2]) * m.k[4] + m.k[3];
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         return r.eR + (p - r.pR) * m.k[8];
     }
@@ -138,10 +160,11 @@ M2C_HD double eos_e(const EosK& m, double v, double p)
 }
 
 // p(v, e)
+template <int S = FAM_ALL>
 M2C_HD double eos_p(const EosK& m, double v, double e)
 {
-    if (m.fam == M2C_EOS_NASG) return (e - m.k[3]) / ((v - m.k[2]) * m.k[4]) - m.k[5];
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_NASG) return (e - m.k[3]) / ((v - m.k[2]) * m.k[4]) - m.k[5];
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         return r.pR + m.k[6] * (e - r.eR);
     }
@@ -151,10 +174,11 @@ M2C_HD double eos_p(const EosK& m, double v, double e)
 }
 
 // c^2(v, p)
+template <int S = FAM_ALL>
 M2C_HD double eos_c2(const EosK& m, double v, double p)
 {
-    if (m.fam == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v / (v - m.k[2]);
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v / (v - m.k[2]);
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         return m.k[0] * v * v * (r.dpR - m.k[6] * r.deR + m.k[1] * p);
     }
@@ -164,22 +188,24 @@ M2C_HD double eos_c2(const EosK& m, double v, double p)
 }
 
 // c^2(v, p) with the Mie-Grueneisen branch given (other families: eos_c2).
+template <int S = FAM_ALL>
 M2C_HD double eos_c2_on(const EosK& m, double v, double p, int br)
 {
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref_on(m, 1.0 - m.k[0] * v, br);
         return m.k[0] * v * v * (r.dpR - m.k[6] * r.deR + m.k[1] * p);
     }
-    return eos_c2(m, v, p);
+    return eos_c2<S>(m, v, p);
 }
 
 // de/dv at constant p, and de/dp at constant v.
+template <int S = FAM_ALL>
 M2C_HD void eos_ederiv(const EosK& m, double v, double p, double& ev, double& ep)
 {
-    if (m.fam == M2C_EOS_NASG) {
+    if (fam_of<S>(m) == M2C_EOS_NASG) {
         ev = (p + m.k[5]) * m.k[4];
         ep = (v - m.k[2]) * m.k[4];
-    } else if (m.fam == M2C_EOS_MG) {
+    } else if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         ev = r.dpR / m.k[1] - m.k[0] * r.deR;
         ep = m.k[8];
@@ -207,6 +233,7 @@ struct Wave {
 // One classical RK4 step of the isentrope over y = ln(p - floor), from
 // (y, s, f) to y + h: ds/dy = (p - floor)/(rho c^2), df/dy = c ds/dy.
 // False where c^2 <= 0 (outside the convex part of the EOS).
+template <int S = FAM_ALL>
 M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, double& f)
 {
     double ks[4], kf[4];
@@ -215,9 +242,9 @@ M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, d
     // overshoot it, and a step may start on one.  The branch is the one a
     // quarter step ahead (s moves with y, ds/dy > 0).
     int br = 0;
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         const double rho0 = K.rho * exp(s), q0 = exp(y);
-        const double c20 = eos_c2(m, 1.0 / rho0, K.fl + q0);
+        const double c20 = eos_c2<S>(m, 1.0 / rho0, K.fl + q0);
         if (!(c20 > 0.0)) return false;
         const double probe = s + 0.25 * h * q0 / (rho0 * c20);
         br = mg_branch(m, 1.0 - m.k[0] / (K.rho * exp(probe)));
@@ -226,7 +253,7 @@ M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, d
         const double a = j == 0 ? 0.0 : (j == 3 ? h : 0.5 * h);
         const double ss = j == 0 ? s : s + a * ks[j - 1];
         const double q = exp(y + a), rho = K.rho * exp(ss);
-        const double c2 = eos_c2_on(m, 1.0 / rho, K.fl + q, br);
+        const double c2 = eos_c2_on<S>(m, 1.0 / rho, K.fl + q, br);
         if (!(c2 > 0.0) || !isfinite(c2)) return false;
         ks[j] = q / (rho * c2);
         kf[j] = ks[j] * sqrt(c2);
@@ -241,17 +268,18 @@ M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, d
 // (eta = 0 and eta = eta_min, where the slope of c^2 jumps) are stepped onto
 // exactly -- a Newton iteration on the length of the step that ends there --
 // so that no RK4 step spans one and each keeps its order.
+template <int S = FAM_ALL>
 M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
 {
     double kink[2] = {INFINITY, INFINITY};
-    if (m.fam == M2C_EOS_MG) {
+    if (fam_of<S>(m) == M2C_EOS_MG) {
         kink[0] = log(m.k[0] / K.rho);
         kink[1] = log(m.k[0] / ((1.0 - m.k[4]) * K.rho));
     }
     for (int guard = 0; guard < 100000; ++guard) {
         const double rem = Y - K.y;
         if (rem == 0.0) return true;
-        if (m.fam == M2C_EOS_MG) {
+        if (fam_of<S>(m) == M2C_EOS_MG) {
             // below eta_min the isentrope is known in closed form: there
             // c^2 = rho_0 Gamma_0 (p - p_min) v^2, so ds/dy = rho/(rho_0
             // Gamma_0), i.e. exp(-s) falls linearly in y, and df/dy =
@@ -350,7 +378,7 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
         const int n = (int)ceil(fabs(rem) / hmax);
         const double h = rem / (double)n;
         double s = K.s, f = K.f;
-        if (!rk4_y(m, K, K.y, h, s, f)) return false;
+        if (!rk4_y<S>(m, K, K.y, h, s, f)) return false;
         int crossed = -1;
         for (int j = 0; j < 2; ++j)
             if ((K.s - kink[j]) * (s - kink[j]) < 0.0) crossed = j;
@@ -371,7 +399,7 @@ M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
             hk = (a * gb - b * ga) / (gb - ga);
             sk_got = K.s;
             fk_got = K.f;
-            if (!rk4_y(m, K, K.y, hk, sk_got, fk_got)) return false;
+            if (!rk4_y<S>(m, K, K.y, hk, sk_got, fk_got)) return false;
             const double g = sk_got - sk;
             if (fabs(g) <= 1e-14 * (1.0 + fabs(sk)) || fabs(b - a) <= 1e-15 * fabs(h)) break;
             if ((g < 0.0) == (gb < 0.0)) {
@@ -497,9 +525,10 @@ M2C_HD bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
 }
 
 // f_K(p) for p <= p_K: the isentrope walked to y = ln(p - floor).
+template <int S = FAM_ALL>
 M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
-    if (m.fam == M2C_EOS_JWL) {
+    if (fam_of<S>(m) == M2C_EOS_JWL) {
         if (p == K.p) {
             w.f = 0.0;
             w.rho = K.rho;
@@ -508,7 +537,7 @@ M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
         }
         return jwl_rarefaction(m, K, p, w);
     }
-    if (m.fam == M2C_EOS_NASG) {
+    if (fam_of<S>(m) == M2C_EOS_NASG) {
         // closed form: along the isentrope (p + p_c)(v - b)^gamma is
         // constant, and integrating dp/(rho c) with c^2 = gamma (p + p_c)
         // v^2/(v - b) gives f = 2 c_K (1 - b rho_K)/(gamma - 1)
@@ -525,12 +554,12 @@ M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
         return true;
     }
     const Side good = K;
-    if (!walk(m, K, log(p - K.fl), hmax)) {
+    if (!walk<S>(m, K, log(p - K.fl), hmax)) {
         K = good;
         return false;
     }
     const double r = K.rho * exp(K.s);
-    const double c2 = eos_c2(m, 1.0 / r, p);
+    const double c2 = eos_c2<S>(m, 1.0 / r, p);
     if (!(c2 > 0.0)) {
         K = good;
         return false;
@@ -543,6 +572,7 @@ M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 
 // f_K(p) for p > p_K: Hugoniot volume by Newton in v, bracketed by
 // (v_min, v_K].
+template <int S = FAM_ALL>
 M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
 {
     const double vK = K.v, half = 0.5 * (p + K.p);
@@ -554,9 +584,9 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
     }
     bool ok = false;
     for (int it = 0; it < 100; ++it) {
-        const double H = eos_e(m, v, p) - K.e - half * (vK - v);
+        const double H = eos_e<S>(m, v, p) - K.e - half * (vK - v);
         double ev, ep;
-        eos_ederiv(m, v, p, ev, ep);
+        eos_ederiv<S>(m, v, p, ev, ep);
         if (H > 0.0) hi = v; else lo = v;
         const double step = H / (ev + half);
         // a converged Newton step is taken before the bracket is consulted
@@ -580,16 +610,17 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
     w.rho = 1.0 / v;
     // slope of f along the Hugoniot: v'(p) = -H_p / H_v
     double ev, ep;
-    eos_ederiv(m, v, p, ev, ep);
+    eos_ederiv<S>(m, v, p, ev, ep);
     const double vp = -(ep - 0.5 * dvol) / (ev + half);
     // (the acoustic slope where the shock is too weak for the quotient)
     w.df = dp > 1e-10 * (K.p - K.fl) ? (dvol - dp * vp) / (2.0 * w.f) : 1.0 / (K.rho * K.c);
     return true;
 }
 
+template <int S = FAM_ALL>
 M2C_HD inline bool wave(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
-    return p > K.p ? shock(m, K, p, w) : rarefaction(m, K, p, hmax, w);
+    return p > K.p ? shock<S>(m, K, p, w) : rarefaction<S>(m, K, p, hmax, w);
 }
 
 M2C_HD inline double floor_margin(const Side& K)
@@ -597,6 +628,7 @@ M2C_HD inline double floor_margin(const Side& K)
     return 1e-12 * (K.p - K.fl) + 1e-6 * fabs(K.fl);
 }
 
+template <int S = FAM_ALL>
 M2C_HD bool side_init(const EosK& m, double rho, double p, Side& K)
 {
     K.fl = m.k[KFLOOR];
@@ -606,16 +638,16 @@ M2C_HD bool side_init(const EosK& m, double rho, double p, Side& K)
     K.p = p;
     if (!(K.v > m.k[KVMIN])) return false;
     if (!(p - K.fl > floor_margin(K))) return false;
-    const double c2 = eos_c2(m, K.v, p);
+    const double c2 = eos_c2<S>(m, K.v, p);
     if (!(c2 > 0.0) || !isfinite(c2)) return false;
     K.c = sqrt(c2);
-    K.e = eos_e(m, K.v, p);
+    K.e = eos_e<S>(m, K.v, p);
     K.s = 0.0;
     K.y = log(p - K.fl);
     K.f = 0.0;
     K.vh = 0.0;
     K.jC = 0.0;
-    if (m.fam == M2C_EOS_JWL) {
+    if (fam_of<S>(m) == M2C_EOS_JWL) {
         const double vK = K.v;
         K.jC = (p - m.k[1] * exp(-m.k[3] * vK) - m.k[2] * exp(-m.k[4] * vK)) * exp((1.0 + m.k[0]) * log(vK));
     }
@@ -635,14 +667,15 @@ M2C_HD inline double bisect(double lo, double hi, double base)
 // One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials mL, mR;
 // res = (p*, u*, rho*_L, rho*_R) or NaN; returns the Newton steps (negative
 // after a bisection step; 0: no star state or an inadmissible input).
+template <int SL = FAM_ALL, int SR = FAM_ALL>
 M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, double rtol, int maxit, double hmax,
                              double* res)
 {
     for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
     int its = 0;
     Side L, R;
-    bool ok = side_init(mL, q[0], q[2], L);
-    ok = ok && side_init(mR, q[3], q[5], R);
+    bool ok = side_init<SL>(mL, q[0], q[2], L);
+    ok = ok && side_init<SR>(mR, q[3], q[5], R);
     if (ok) {
         const double uL = q[1], uR = q[4], du = uR - uL;
         const double pfl = fmax(L.fl + floor_margin(L), R.fl + floor_margin(R));
@@ -656,7 +689,7 @@ M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, do
         Wave wl, wr;
         ok = false;
         for (its = 1; its <= maxit; ++its) {
-            if (!wave(mL, L, p, hmax, wl) || !wave(mR, R, p, hmax, wr)) {
+            if (!wave<SL>(mL, L, p, hmax, wl) || !wave<SR>(mR, R, p, hmax, wr)) {
                 // p lies below where an isentrope ends (c^2 reaches zero
                 // before the floor): it bounds the bracket from below
                 lo = p;
@@ -687,7 +720,7 @@ M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, do
                     // there a star state above the floor at all?
                     floor_checked = true;
                     Wave a, b;
-                    if (!wave(mL, L, pfl, hmax, a) || !wave(mR, R, pfl, hmax, b)) break;
+                    if (!wave<SL>(mL, L, pfl, hmax, a) || !wave<SR>(mR, R, pfl, hmax, b)) break;
                     if (a.f + b.f + du > 0.0) break;          // cavitation
                 }
                 pn = isinf(hi) ? p + fmax(p - pfl, fabs(p) + 1.0) : bisect(lo, hi, base);
@@ -695,7 +728,7 @@ M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, do
             }
             p = pn;
         }
-        if (conv && wave(mL, L, p, hmax, wl) && wave(mR, R, p, hmax, wr)) {
+        if (conv && wave<SL>(mL, L, p, hmax, wl) && wave<SR>(mR, R, p, hmax, wr)) {
             res[0] = p;
             res[1] = 0.5 * (uL - wl.f + uR + wr.f);
             res[2] = wl.rho;

@@ -70,8 +70,11 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 // an LDS table (see below).  OPTS: limiter, flux and level-set band as
 // configured (Van Albada, local Lax-Friedrichs, narrow band); otherwise MC,
 // HLLC and the whole grid, fixed at compile time so that the default kernels
-// carry neither the code nor the registers of the other options.
-template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS, bool EG = false, bool NM = false>
+// carry neither the code nor the registers of the other options.  EG: a
+// general EOS per material; FS: the set of the two materials' families (bit
+// mask, eos::fam_set), so that the kernel carries only their code
+// (eos::FAM_ALL: dispatched on the materials' tags at run time).
+template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
     // Stage kinds: 1 first stage of RK2 / RK3 (W_out = W_in + dt R); 2 last
@@ -180,7 +183,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // Primitives of a raw state, velocities mirrored at wall images.
     auto to_prim = [&](const double w[6], uint8_t x, bool mz, TF q[5]) {
         double u, vv, ww, p;
-        if constexpr (EG) p = geos_prim<NM>(sEos[x], w[0], w[1], w[2], w[3], w[4], u, vv, ww);
+        if constexpr (EG) p = geos_prim<FS>(sEos[x], w[0], w[1], w[2], w[3], w[4], u, vv, ww);
         else p = eos_prim(w[0], w[1], w[2], w[3], w[4], mat(x, MAT_GM1), mat(x, MAT_GPC), u, vv, ww);
         q[0] = TF(w[0]);
         q[1] = TF(mirx ? -u : u);
@@ -205,7 +208,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             TF Fr[5];
             // face frame: normal w, tangential u, v
             if constexpr (EG) {
-                geos_flux<NM>(sEos[xl], flux, ql[0] + 0.5 * sl[0], ql[3] + 0.5 * sl[3], ql[1] + 0.5 * sl[1],
+                geos_flux<FS>(sEos[xl], flux, ql[0] + 0.5 * sl[0], ql[3] + 0.5 * sl[3], ql[1] + 0.5 * sl[1],
                           ql[2] + 0.5 * sl[2], ql[4] + 0.5 * sl[4], qu[0] - 0.5 * su[0], qu[3] - 0.5 * su[3],
                           qu[1] - 0.5 * su[1], qu[2] - 0.5 * su[2], qu[4] - 0.5 * su[4], Fr);
             } else {
@@ -404,7 +407,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 const bool mx = (hmir >> (2 * q)) & 1u, my = (hmir >> (2 * q)) & 2u;
                 const uint8_t x = hx[q];
                 double u, vv, ww, p;
-                if constexpr (EG) p = geos_prim<NM>(sEos[x], hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], u, vv, ww);
+                if constexpr (EG) p = geos_prim<FS>(sEos[x], hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], u, vv, ww);
                 else p = eos_prim(hw[q][0], hw[q][1], hw[q][2], hw[q][3], hw[q][4], mat(x, MAT_GM1), mat(x, MAT_GPC),
                                   u, vv, ww);
                 const int o = hofs[q];
@@ -454,7 +457,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 }
                 TF Fr[5];
                 if constexpr (EG)
-                    geos_flux<NM>(sEos[xa], flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], Fr);
+                    geos_flux<FS>(sEos[xa], flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4], Fr);
                 else
                     num_flux<TF>(flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4],
                                  TF(mat(xa, MAT_GAMMA)), TF(mat(xa, MAT_PC)), TF(mat(xa, MAT_GPC)), TF(mat(xa, MAT_IGM1)),
@@ -603,8 +606,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             double u, vv, ww, p, c2 = 0.0;
             bool adm;
             if constexpr (EG) {
-                p = geos_prim<NM>(sEos[X0], wn[0], wn[1], wn[2], wn[3], wn[4], u, vv, ww);
-                c2 = geos_c2<NM>(sEos[X0], wn[0], p);
+                p = geos_prim<FS>(sEos[X0], wn[0], wn[1], wn[2], wn[3], wn[4], u, vv, ww);
+                c2 = geos_c2<FS>(sEos[X0], wn[0], p);
                 adm = wn[0] > 0.0 && p > sEos[X0].k[eos::KFLOOR] && c2 > 0.0;
             } else {
                 p = eos_prim(wn[0], wn[1], wn[2], wn[3], wn[4], mat(X0, MAT_GM1), mat(X0, MAT_GPC), u, vv, ww);
@@ -685,23 +688,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk)
 #define M2C_STAGE_BOUNDS(TX, TY, TF) \
     __launch_bounds__(stage_threads(TX, TY), sizeof(TF) == 4 ? M2C_STAGE_WAVES_MIXED : M2C_STAGE_WAVES)
 
-template <int STAGE, int TX, int TY, typename TF, bool OPTS, bool EG = false, bool NM = false>
+template <int STAGE, int TX, int TY, typename TF, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
 __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
 {
-    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double), OPTS, EG, NM>(a, xcd_tile(blockIdx.x, gridDim.x));
+    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double), OPTS, EG, FS>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Launch of the single-grid kernel of one stage kind over the whole grid.
-template <int TX, int TY, typename TF, bool OPTS, bool EG = false, bool NM = false>
+template <int TX, int TY, typename TF, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
 static hipError_t launch_tile(int stage, const StageArgs& a, hipStream_t s)
 {
     const int nblk = a.tiles_x * a.tiles_y * a.tiles_z;
     const dim3 g(nblk), b(stage_threads(TX, TY));
     switch (stage) {
-        case 1: hipLaunchKernelGGL((k_stage<1, TX, TY, TF, OPTS, EG, NM>), g, b, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((k_stage<2, TX, TY, TF, OPTS, EG, NM>), g, b, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((k_stage<3, TX, TY, TF, OPTS, EG, NM>), g, b, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((k_stage<4, TX, TY, TF, OPTS, EG, NM>), g, b, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((k_stage<1, TX, TY, TF, OPTS, EG, FS>), g, b, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((k_stage<2, TX, TY, TF, OPTS, EG, FS>), g, b, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((k_stage<3, TX, TY, TF, OPTS, EG, FS>), g, b, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((k_stage<4, TX, TY, TF, OPTS, EG, FS>), g, b, 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -20,7 +20,8 @@ from paper_2508_16387_amd import build as B
 HIPCC = B.hipcc()
 
 
-SOURCES = ("k_stage.hip", "k_stage_eos.hip", "k_stage_opts.hip")
+SOURCES = ("k_stage.hip", "k_stage_eos.hip", "k_stage_eos_nasg.hip", "k_stage_eos_other.hip", "k_stage_opts.hip",
+           "k_riemann_eos.hip")
 
 
 def _parse(stderr):
@@ -69,7 +70,10 @@ def stage_resources(all_resources):
 
 @pytest.fixture(scope="module")
 def stage_eos_resources(all_resources):
-    return all_resources["k_stage_eos.hip"]
+    out = {}
+    for src in ("k_stage_eos.hip", "k_stage_eos_nasg.hip", "k_stage_eos_other.hip"):
+        out.update(all_resources[src])
+    return out
 
 
 @pytest.fixture(scope="module")
@@ -101,15 +105,29 @@ def test_mixed_stage_kernels_keep_three_waves_without_spills(stage_resources):
 
 
 def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resources):
-    """The general-EOS stage kernels on the 16x16 tile (default scheme,
-    run-time options, default scheme without Mie-Grueneisen code): no scratch
-    and two waves per SIMD for every stage kind (holding W^n across the plane
-    iteration pushed kinds 2 and 3 to one wave)."""
+    """The general-EOS stage kernels on the 16x16 tile (the default scheme
+    for each of the six sets of one or two families, and the run-time
+    options): no scratch and two waves per SIMD for every stage kind (holding
+    W^n across the plane iteration pushed kinds 2 and 3 to one wave)."""
     ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi16E" in n}
-    assert len(ks) == 12, sorted(ks)            # default scheme, options, default without Mie-Grueneisen
+    assert len(ks) == 4 * (6 + 1), sorted(ks)   # 4 stage kinds x (6 family sets + run-time options)
     for n, r in ks.items():
         assert r["scratch"] == 0, (n, r)
         assert r["occupancy"] >= 2, (n, r)
+
+
+def test_general_eos_point_solvers_per_family_pair(all_resources):
+    """The point solver compiled per unordered family pair: no spills but 32
+    bytes per lane for Mie-Grueneisen on both sides (the run-time dispatching
+    kernel, kept for sets of several family pairs, spills), two waves per
+    SIMD without Mie-Grueneisen."""
+    ks = {n: r for n, r in all_resources["k_riemann_eos.hip"].items() if "k_riemann_eosILi" in n and "Lin1" not in n}
+    assert len(ks) == 6, sorted(ks)
+    for n, r in ks.items():
+        mg = "Li1E" in n
+        assert r["scratch"] <= (32 if mg else 28), (n, r)
+        if not mg:
+            assert r["occupancy"] >= 2, (n, r)
 
 
 def test_option_stage_kernels_fit_two_waves_without_spills(stage_opts_resources):

@@ -110,6 +110,33 @@ def test_eos_mie_grueneisen_3d_matches_oracle(m2c, inner, outer, p_in, rho_in, r
     assert o.stats()["iface_faces_last"] > 50
 
 
+# one 3D case per ordered pair of families (material 0 = outer, material 1 =
+# the sphere): the interface kernels are compiled per family pair and the
+# stage kernels per family set, so each of them runs at least once here
+FAMILY_PAIRS = {
+    # (outer, inner, p_inner, rho_inner, rho_outer, p_outer)
+    "nasg-nasg": ("water_nasg", "gas_nasg", 5e6, 5.0, 1000.0, 1e5),
+    "nasg-mg": ("water_nasg", "glass", 1e5, 2220.0, 1000.0, 1e9),
+    "nasg-jwl": ("water_nasg", "tnt", 5e9, 1630.0, 1000.0, 1e5),
+    "mg-nasg": ("glass", "air", 1e5, 1.2, 2204.0, 1e9),
+    "mg-mg": ("copper", "tantalum", 5e9, 16650.0, 8930.0, 1e5),
+    "mg-jwl": ("copper", "tnt", 5e9, 1630.0, 8930.0, 1e5),
+    "jwl-nasg": ("tnt", "water_nasg", 1e5, 1000.0, 1630.0, 1e9),
+    "jwl-mg": ("tnt", "copper", 1e5, 8930.0, 1630.0, 5e9),
+    "jwl-jwl": ("tnt", "tnt", 5e9, 1630.0, 1630.0, 1e9),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FAMILY_PAIRS))
+def test_eos_every_family_pair_3d_matches_oracle(m2c, name):
+    outer, inner, p_in, rho_in, rho_out, p_out = FAMILY_PAIRS[name]
+    p = W.eos_charge(9, n=(10, 9, 8), steps=3, inner=inner, outer=outer, p_inner=p_in, rho_inner=rho_in,
+                     rho_outer=rho_out, p_outer=p_out)
+    g, o = _run(m2c, p, 3)
+    assert g.tile()[:2] == (16, 16)
+    assert o.stats()["iface_faces_last"] > 50
+
+
 def test_eos_3d_walls_band_and_options_match_oracle(m2c):
     """The run-time option kernels with a general EOS in 3D: wall boundaries,
     a narrow-band level set, RK3, modified Van Albada and LLF."""

@@ -94,6 +94,34 @@ def test_riemann_eos_matches_oracle(m2c, pair):
     assert e.max() <= TOL_EOS, e.max(axis=1)
 
 
+def test_riemann_eos_jwl_both_sides_matches_oracle(m2c):
+    """Detonation products on both sides (the JWL / JWL kernel)."""
+    inp, mat, mats, names = W.general_eos_problem_set(140, 40, pairs=[("tnt", "tnt")])
+    got, it, rc = _gpu(m2c, inp, mat, mats)
+    e, ok = _compare(inp, mat, mats, got, it, "tnt-tnt")
+    assert ok.sum() >= 30
+    assert e.max() <= TOL_EOS, e.max(axis=1)
+
+
+@pytest.mark.parametrize("pair", [("air", "glass"), ("copper", "tnt"), ("tnt", "water_sg")],
+                         ids=["air-glass", "copper-tnt", "tnt-water_sg"])
+def test_riemann_eos_mirror_symmetry(m2c, pair):
+    """Reflection x -> -x of every problem (sides swapped, velocities
+    negated) gives p* unchanged, u* negated and the star densities swapped,
+    bit for bit: each problem is solved with the lower family on the left,
+    so a problem and its mirror image take the same arithmetic."""
+    inp, mat, mats, _ = W.general_eos_problem_set(150 + len(pair[0]), 500, pairs=[pair])
+    mir = np.stack([inp[3], -inp[4], inp[5], inp[0], -inp[1], inp[2]])
+    got, it, rc = _gpu(m2c, inp, mat, mats)
+    gm, im, rcm = _gpu(m2c, np.ascontiguousarray(mir), np.ascontiguousarray(mat[::-1]), mats)
+    assert rc == rcm and np.array_equal(it, im)
+    ok = np.isfinite(got[0])
+    assert ok.sum() >= 400
+    assert np.array_equal(got[0][ok], gm[0][ok])
+    assert np.array_equal(got[1][ok], -gm[1][ok])
+    assert np.array_equal(got[2][ok], gm[3][ok]) and np.array_equal(got[3][ok], gm[2][ok])
+
+
 def test_rk4_step_size_order(m2c):
     """Rarefaction-dominated Mie-Grueneisen problems (the family whose
     isentropes are integrated by RK4; NASG and JWL use closed forms) at two
