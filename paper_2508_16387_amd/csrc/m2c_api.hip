@@ -525,9 +525,10 @@ int m2c_create(const m2c_config* cfg, m2c_ctx** out)
     // stage tiles: (tile_x, tile_y), else 16x15 (its 511 in-plane faces are
     // exactly two rounds of the block's 256 threads; the general-EOS kernels
     // come in 16x16), 64x2 for quasi-1D grids.  Planes per block: tile_z,
-    // else 16 when that still leaves at least 4096 blocks (16 rounds of two
-    // blocks per CU: the prologue of a block's march is amortised over more
-    // planes), otherwise 8.
+    // else the most of 32, 16 that still leaves at least 4096 blocks (16
+    // rounds of two blocks per CU: the prologue of a block's march and the
+    // re-read halo planes are amortised over more planes; 32 measured 1.5%
+    // faster than 16 on 384^3), otherwise 8.
     c->tx = cfg->tile_x ? cfg->tile_x : 16;
     c->ty = cfg->tile_y ? cfg->tile_y : (c->g.eosg ? 16 : 15);
     if (!cfg->tile_x && c->g.ny == 1) {
@@ -538,7 +539,7 @@ int m2c_create(const m2c_config* cfg, m2c_ctx** out)
         c->kz = cfg->tile_z;
     } else {
         const long long txy = (long long)((c->g.nx + c->tx - 1) / c->tx) * ((c->g.ny + c->ty - 1) / c->ty);
-        c->kz = txy * ((c->g.nz + 15) / 16) >= 4096 ? 16 : 8;
+        c->kz = txy * ((c->g.nz + 31) / 32) >= 4096 ? 32 : (txy * ((c->g.nz + 15) / 16) >= 4096 ? 16 : 8);
     }
     if (c->kz > c->g.nz) c->kz = c->g.nz;
     c->tiles[0] = (c->g.nx + c->tx - 1) / c->tx;
@@ -800,12 +801,12 @@ int m2c_riemann_solve(int64_t n, const double* in, const double* eos, int32_t gu
 
 int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
 {
-    static const int cands_sg[][3] = {{16, 15, 8},  {16, 15, 16}, {16, 16, 8}, {16, 16, 16},
-                                      {16, 16, 4},  {32, 8, 8},   {32, 7, 8},  {16, 15, 4}};
+    static const int cands_sg[][3] = {{16, 15, 8}, {16, 15, 16}, {16, 16, 8}, {16, 16, 16}, {16, 16, 4},
+                                      {32, 8, 8},  {32, 7, 8},   {16, 15, 4}, {16, 15, 32}};
     static const int cands_eos[][3] = {{16, 16, 8}, {16, 16, 4}};
     if (!c || steps < 1) return M2C_ERR_ARG;
     const int(*cands)[3] = c->g.eosg ? cands_eos : cands_sg;
-    const int ncand = c->g.eosg ? 2 : 8;
+    const int ncand = c->g.eosg ? 2 : 9;
     if (!c->has_state) return set_err(c, M2C_ERR_STATE, "no state set");
     HIPCHK(c, hipSetDevice(c->device));
     int rc = pull_scalars(c);
