@@ -29,8 +29,9 @@
 //
 // Register budget: the column window keeps primitives of three planes,
 // the z-slope and lower z-flux of the current plane, phi of five planes and
-// the raw state of the prefetched plane; the stage-input state of the cell
-// being updated is re-read (a cache hit) instead of being carried.
+// the raw state of the prefetched plane; the stage-input conservative state
+// of the cell being updated is not carried: the FP64 stiffened-gas kernels
+// rebuild it from the cell's primitives, the other forms re-read it.
 //
 // Precision: TF is the type of reconstruction, HLLC and of the primitives
 // and single-material fluxes staged in LDS and registers (double, or float
