@@ -9,13 +9,15 @@
 // slowest lane, so a set that mixes material pairs is first grouped by pair
 // (a counting sort over the at most 64 pair keys) and solved through that
 // permutation: the lanes of a wavefront then share their materials.  The
-// keys are laid out family pair by family pair (NASG, Mie-Grueneisen, JWL on
-// each side).  A set of one family pair is solved by a kernel compiled for
-// exactly those two families, which carries neither the code nor the
-// registers of the others; a set of several family pairs takes one launch of
-// the kernel that dispatches on the families at run time, so that the groups
-// run side by side (launches per group, one after another on the stream,
-// would each wait for the slowest wavefront of the one before).
+// keys are laid out by unordered family pair (NASG, Mie-Grueneisen, JWL),
+// costliest group first, and a problem whose right side has the lower
+// family is solved mirrored.  A set of one family pair (in either order) is
+// solved by a kernel compiled for exactly those two families, which carries
+// neither the code nor the registers of the others; a set of several family
+// pairs takes one launch of the kernel that dispatches on the families at
+// run time, so that the groups run side by side (launches per group, one
+// after another on the stream, would each wait for the slowest wavefront of
+// the one before).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -203,10 +205,10 @@ struct SolveArgs {
     const int32_t* perm;
 };
 
-template <int FL, int FR>
+template <int FA, int FB>
 void launch_solve(const SolveArgs& a, unsigned grid, const int32_t* range, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_riemann_eos<FL, FR>), dim3(grid), dim3(256), 0, s, a.n, a.in, a.mat, a.tab, a.rtol,
+    hipLaunchKernelGGL((k_riemann_eos<FA, FB>), dim3(grid), dim3(256), 0, s, a.n, a.in, a.mat, a.tab, a.rtol,
                        a.maxit, a.hmax, a.out, a.iters, a.nbad, a.perm, range);
 }
 
