@@ -423,9 +423,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         }
         // halo of the next plane: its registers are free once this plane's
         // halo is staged, and the face work below covers the load latency
-        // (the batched, option and general-EOS kernels, whose register
-        // budget this would exceed, load it after the face work)
-        constexpr bool EARLY_HALO = PF && LM && !OPTS && !EG;
+        // (the batched and option kernels, whose register budget this would
+        // exceed, load it after the face work)
+        constexpr bool EARLY_HALO = PF && LM && !OPTS;
         if (EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         __syncthreads();
 
