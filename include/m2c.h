@@ -415,8 +415,14 @@ int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], cons
  * falls as ds^4 (at most about 2e-10 of the sound speed in u* at 0.01 on the
  * materials of the tests).
  * FP64 throughout.  rtol: Newton stop |dp| <= rtol (p - floor) on the closer
- * side.  Returns M2C_ERR_RIEMANN if any problem had no star state,
- * M2C_ERR_ARG for invalid arguments or EOS parameters. */
+ * side.  The problems are grouped by material pair on the device (a
+ * workspace of about 4n bytes that the call allocates and frees); a problem
+ * whose right side has the lower EOS family is solved in its mirror image,
+ * so a problem and its reflection (sides swapped, velocities negated) give
+ * the same p* bit for bit.  The call synchronises hip_stream before it
+ * returns.  Returns M2C_ERR_RIEMANN if any problem had no star state,
+ * M2C_ERR_ARG for invalid arguments or EOS parameters, M2C_ERR_NOMEM if the
+ * workspace cannot be allocated. */
 int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat, const m2c_eos* eos,
                           double rtol, int32_t maxit, double ds, double* out, int32_t* iters, void* hip_stream);
 /* Pressure and sound speed of n states (rho, e) of materials mat[n] of the
