@@ -222,29 +222,44 @@ def fiver_standalone(m2c, torch, n=1_000_000, reps=20):
 def general_eos_standalone(m2c, torch, n=1 << 20, reps=5):
     """Two-material Riemann solves/s with a general EOS on each side (NASG,
     Mie-Grueneisen, JWL): the mixed set of eight material pairs in one call,
-    and single-pair sets of three kinds (gas / solid, detonation products /
-    gas, solid / solid in tension).  The median of ``reps`` timed calls (each
-    groups the set by material pair, solves, and synchronises)."""
+    its four pairs without a Mie-Grueneisen side, and single-pair sets of
+    three kinds (gas / solid, detonation products / gas, solid / solid in
+    tension), each from the acoustic start and from the learned start
+    (committed network).  The median of ``reps`` timed calls (each groups
+    the set by material pair, solves, and synchronises)."""
     import workloads as W
+
+    import numpy as np
+
+    net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess_eos.npy")))
+
+    def timed(fn):
+        fn()
+        ts, r = [], None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[len(ts) // 2], r
 
     def run(pairs):
         inp, mat, mats, _ = W.general_eos_problem_set(2024, n, pairs=pairs)
         ti = torch.tensor(inp, dtype=torch.float64, device="cuda")
         tm = torch.tensor(mat, dtype=torch.int32, device="cuda")
-        m2c.riemann_solve_eos(ti, tm, mats)
-        ts = []
-        for _ in range(reps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            out, it, rc = m2c.riemann_solve_eos(ti, tm, mats)
-            torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        T = sorted(ts)[len(ts) // 2]
-        ok = it != 0
+        T, (out, it, rc) = timed(lambda: m2c.riemann_solve_eos(ti, tm, mats))
+        TL, (_, itl, _, nfb) = timed(lambda: m2c.riemann_solve_eos_learned(net, ti, tm, mats))
+        ok, okl = it != 0, itl != 0
         return {"solves_per_s": n / T, "ms": T * 1e3, "calls": reps,
-                "newton_iters_per_solve": float(it.abs().double()[ok].mean()), "no_star_state": int((~ok).sum())}
+                "newton_iters_per_solve": float(it.abs().double()[ok].mean()), "no_star_state": int((~ok).sum()),
+                "learned_start": {"solves_per_s": n / TL, "ms": TL * 1e3,
+                                  "newton_iters_per_solve": float(itl.abs().double()[okl].mean()),
+                                  "acoustic_starts": int(nfb), "speedup_vs_acoustic": T / TL}}
 
     res = {"problems": n, "ds": 0.01, "mixed_pairs": run(None)}
+    no_mg = [pr for pr in W.EOS_PAIRS if all(W.EOS_MATERIALS[m][0] != m2c.M2C_EOS_MG for m in pr)]
+    res["pairs_without_mie_grueneisen"] = run(no_mg)
     for pr in (("air", "glass"), ("tnt", "air"), ("copper", "tantalum")):
         res["-".join(pr)] = run([pr])
     return res

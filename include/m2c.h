@@ -425,6 +425,42 @@ int m2c_reinit_field(int32_t nx, int32_t ny, int32_t nz, const double h[3], cons
  * workspace cannot be allocated. */
 int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat, const m2c_eos* eos,
                           double rtol, int32_t maxit, double ds, double* out, int32_t* iters, void* hip_stream);
+/* Learned start for the general-EOS solve (the acceleration of the exact
+ * Riemann solves that section "Spatial discretization of governing
+ * equations" calls for; it matters most here, where each outer Newton step
+ * integrates wave curves).  The network of m2c_mlp (8 -> 64 -> 64 -> 1)
+ * with these features of a problem, taken in the orientation it is solved
+ * in (lower family on the left):
+ *   x0 = ln(rho_L/rho_R)/2, x1 = (u_R - u_L)/U, x2 = ln(a_L/a_R)/2,
+ *   x3 = ln(rho_L c_L^2/a_L), x4 = ln(rho_R c_R^2/a_R),
+ *   x5 = ln((p_ac - p_lo)/P) with p_ac the acoustic start,
+ *   x6, x7 = family - 1 (M2C_EOS_*) of the left and right side,
+ * p_lo the higher of the two pressure floors, a_K = p_K - p_lo,
+ * P = sqrt(a_L a_R), U = sqrt(P / sqrt(rho_L rho_R)); the target is
+ * y = ln((p* - p_lo)/P).  X8 [8][n], target [n] (nullable; NaN where p* is
+ * not above p_lo or the problem is inadmissible, with zero features);
+ * pstar [n] (nullable): the star pressures the targets come from.  Device
+ * pointers; asynchronous on hip_stream. */
+int m2c_mlp_features_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat, const m2c_eos* eos,
+                         const double* pstar, float* X8, float* target, void* hip_stream);
+/* As m2c_riemann_solve_eos with the learned start of network m (NULL: the
+ * acoustic start, the same solves as m2c_riemann_solve_eos).  The network
+ * is consulted for problems with a JWL side and no Mie-Grueneisen side
+ * (where an outer step saved pays for it; with NASG on both sides a step
+ * is cheaper than the network, and with a Mie-Grueneisen side the cost is
+ * the length of the isentrope walks, not the number of outer steps), and
+ * not at all in a set that also holds Mie-Grueneisen problems; problems
+ * whose pressures and velocities agree to 1e-3 (relative to the smaller
+ * p_K - p_lo and sound speed) start from the acoustic guess as well.  A learned start is evaluated (F and F' of the outer iteration,
+ * which serve as its first Newton step when it is kept) and kept unless the
+ * tangent there predicts a smaller |F| at the acoustic start; the iteration
+ * then runs to the same tolerance, so the star state does not depend on the
+ * network beyond rtol.  *n_fallback (nullable): problems with a star state
+ * that started from the acoustic guess.  Return codes as for
+ * m2c_riemann_solve_eos. */
+int m2c_riemann_solve_eos_learned(const m2c_mlp* m, int64_t n, const double* in, const int32_t* mat, int32_t nmat,
+                                  const m2c_eos* eos, double rtol, int32_t maxit, double ds, double* out,
+                                  int32_t* iters, int64_t* n_fallback, void* hip_stream);
 /* Pressure and sound speed of n states (rho, e) of materials mat[n] of the
  * table eos[nmat] (device arrays; p, c = NaN where c^2 <= 0 or the index is
  * out of range). */

@@ -18,5 +18,5 @@ from ._binding import (  # noqa: F401
     Config, Stats, M2CError, lib, lib_path, exported_symbols, config_default, config_for, Sim, Batch,
     eval_hllc, riemann_solve, Mlp, TrainOpts, mlp_features, riemann_solve_learned, NPARAM,
     M2C_EOS_NASG, M2C_EOS_MG, M2C_EOS_JWL, M2C_EOS_MAX, Eos, eos_table, riemann_solve_eos, eos_eval,
-    reinit_field, riemann_solve_learned_async, NOALLOC_MAX_PROBLEMS,
+    reinit_field, riemann_solve_learned_async, NOALLOC_MAX_PROBLEMS, riemann_solve_eos_learned, mlp_features_eos,
 )

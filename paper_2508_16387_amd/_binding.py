@@ -35,6 +35,7 @@ EXPORTS = [
     "m2c_mlp_forward", "m2c_mlp_grad", "m2c_mlp_train", "m2c_riemann_solve_learned", "m2c_set_guess",
     "m2c_riemann_solve_learned_noalloc",
     "m2c_riemann_solve_eos", "m2c_eos_eval", "m2c_reinit", "m2c_reinit_workspace", "m2c_reinit_field",
+    "m2c_mlp_features_eos", "m2c_riemann_solve_eos_learned",
 ]
 _NO_STATUS = ("m2c_config_default", "m2c_destroy", "m2c_last_error", "m2c_strerror", "m2c_batch_destroy",
               "m2c_batch_last_error", "m2c_train_opts_default", "m2c_mlp_destroy")
@@ -164,6 +165,8 @@ def _declare(L):
     L.m2c_set_guess.argtypes = [vp, vp]
     L.m2c_riemann_solve_learned_noalloc.argtypes = [vp, i64, vp, vp, d, i32, vp, vp, vp]
     L.m2c_riemann_solve_eos.argtypes = [i64, vp, vp, i32, vp, d, i32, d, vp, vp, vp]
+    L.m2c_mlp_features_eos.argtypes = [i64, vp, vp, i32, vp, vp, vp, vp, vp]
+    L.m2c_riemann_solve_eos_learned.argtypes = [vp, i64, vp, vp, i32, vp, d, i32, d, vp, vp, C.POINTER(i64), vp]
     L.m2c_eos_eval.argtypes = [i64, vp, vp, vp, i32, vp, vp, vp, vp]
     L.m2c_reinit.argtypes = [vp, i32, d]
     L.m2c_reinit_workspace.argtypes = [i32, i32, i32, C.POINTER(i64)]
@@ -514,6 +517,39 @@ def riemann_solve_eos(inp, mat, materials, rtol=1e-12, maxit=50, ds=0.0, stream=
     if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
         raise M2CError(rc, lib().m2c_strerror(rc).decode())
     return out, iters, rc
+
+
+def riemann_solve_eos_learned(mlp, inp, mat, materials, rtol=1e-12, maxit=50, ds=0.0, stream=None, check=True):
+    """:func:`riemann_solve_eos` with the learned start of network ``mlp``
+    (None: the acoustic start).  Returns (out [4, n], iters [n], rc,
+    n_fallback)."""
+    import torch
+    n = inp.shape[1]
+    out = torch.empty((4, n), dtype=torch.float64, device=inp.device)
+    iters = torch.empty((n,), dtype=torch.int32, device=inp.device)
+    nfb = C.c_int64(0)
+    tab = eos_table(materials)
+    rc = lib().m2c_riemann_solve_eos_learned(None if mlp is None else mlp.h, n, _ptr(inp), _ptr(mat), len(materials),
+                                             tab, rtol, maxit, ds, _ptr(out), _ptr(iters), C.byref(nfb),
+                                             _stream_of(inp, stream))
+    if check and rc not in (M2C_OK, M2C_ERR_RIEMANN):
+        raise M2CError(rc, lib().m2c_strerror(rc).decode())
+    return out, iters, rc, nfb.value
+
+
+def mlp_features_eos(inp, mat, materials, pstar=None, stream=None):
+    """Features X [8, n] (and targets [n] when pstar is given) of the
+    general-EOS learned start for problems inp [6, n] (float64) and mat
+    [2, n] (int32) cuda tensors of materials [(family, [params])]."""
+    import torch
+    n = inp.shape[1]
+    X = torch.empty((8, n), dtype=torch.float32, device=inp.device)
+    t = torch.empty(n, dtype=torch.float32, device=inp.device) if pstar is not None else None
+    rc = lib().m2c_mlp_features_eos(n, _ptr(inp), _ptr(mat), len(materials), eos_table(materials), _ptr(pstar),
+                                    _ptr(X), _ptr(t), _stream_of(inp, stream))
+    if rc != M2C_OK:
+        raise M2CError(rc, "m2c_mlp_features_eos failed")
+    return X, t
 
 
 def eos_eval(rho, e, mat, materials, stream=None):

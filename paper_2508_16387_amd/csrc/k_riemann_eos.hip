@@ -24,11 +24,65 @@
 
 #include "m2c.h"
 #include "m2c_eos.h"
+#include "m2c_mlp_infer.h"
+
+const m2c::MlpDev* m2c_mlp_dev(const m2c_mlp* m);   // m2c_learned.hip
 
 namespace m2c {
 namespace {
 
 using namespace m2c::eos;
+
+// Learned start of the general-EOS outer iteration: the network of the
+// stiffened-gas guess (8 -> 64 -> 64 -> 1) with features of a set-up
+// problem in the orientation it is solved in (lower family on the left):
+//   x0 = ln(rho_L/rho_R)/2, x1 = (u_R - u_L)/U, x2 = ln(a_L/a_R)/2,
+//   x3 = ln(rho_L c_L^2/a_L), x4 = ln(rho_R c_R^2/a_R) (the sides'
+//   effective isentropic exponents), x5 = ln((p_ac - p_lo)/P) (the acoustic
+//   start), x6, x7 = family - 1 of each side,
+// with p_lo the higher floor, a_K = p_K - p_lo, P = sqrt(a_L a_R) and
+// U = sqrt(P / sqrt(rho_L rho_R)); the target is y = ln((p* - p_lo)/P), so
+// the guess p_lo + P exp(y) lies above both floors for any y.  False where
+// a side's pressure does not exceed the other side's floor.
+__device__ __forceinline__ bool eos_features(const Pair& P, int famL, int famR, float x[8], double& plo,
+                                             double& Pn)
+{
+    plo = P.base;
+    const double aL = P.L.p - plo, aR = P.R.p - plo;
+    if (!(aL > 0.0) || !(aR > 0.0)) return false;
+    Pn = sqrt(aL * aR);
+    const double U = sqrt(Pn / sqrt(P.L.rho * P.R.rho));
+    x[0] = (float)(0.5 * log(P.L.rho / P.R.rho));
+    x[1] = (float)(P.du / U);
+    x[2] = (float)(0.5 * log(aL / aR));
+    x[3] = (float)log(P.L.rho * P.L.c * P.L.c / aL);
+    x[4] = (float)log(P.R.rho * P.R.c * P.R.c / aR);
+    x[5] = (float)log((P.pac - plo) / Pn);
+    x[6] = (float)(famL - 1);
+    x[7] = (float)(famR - 1);
+    return true;
+}
+
+// Family pairs whose solves take the learned start: a JWL side and no
+// Mie-Grueneisen side.  Measured: the JWL isentrope's Riemann invariant is a
+// quadrature, so each outer step saved pays for the network (1.24x on
+// detonation products / air); with NASG on both sides a step is cheaper than
+// the network (0.93x), and with a Mie-Grueneisen side the cost is the length
+// of the RK4 walks along the isentrope, which a start beyond p* or a
+// rejected candidate lengthens (0.77x on copper / tantalum).
+__host__ __device__ constexpr bool learned_pair(int fa, int fb)
+{
+    return (fa == M2C_EOS_JWL || fb == M2C_EOS_JWL) && fa != M2C_EOS_MG && fb != M2C_EOS_MG;
+}
+
+// Near equilibrium (pressures within 1e-3 of the smaller a_K, velocities
+// within 1e-3 of the smaller sound speed): the acoustic start is then close
+// to exact and the network is not consulted.
+__device__ __forceinline__ bool eos_near_equilibrium(const Pair& P)
+{
+    const double aL = P.L.p - P.base, aR = P.R.p - P.base, du2 = P.du * P.du;
+    return fabs(P.L.p - P.R.p) <= 1e-3 * fmin(aL, aR) && du2 <= 1e-6 * fmin(P.L.c * P.L.c, P.R.c * P.R.c);
+}
 
 // pair key of problem i: ml * nmat + mr, or nmat^2 for an index outside the table
 __device__ __forceinline__ int pair_key(const int32_t* mat, long long n, long long i, int nmat)
@@ -123,10 +177,11 @@ constexpr int kWavesPerSimd = (FA >= 0 && FB >= 0 && FA != M2C_EOS_MG && FB != M
 // Slots range[0] .. range[1] of the permutation perm (whole set without
 // them: thread t solves problem t).  FA <= FB: every problem of the range
 // has one material of family FA and one of family FB, in either order,
-// inside the table (the grouping guarantees it); one with FB on the left is
-// solved mirrored (x -> -x: the sides swap and the velocities change sign),
-// which leaves p* and negates u*.  FA = FB = -1: any materials, indices
-// checked, families dispatched at run time.
+// inside the table (the grouping guarantees it).  FA = FB = -1: any
+// materials, indices checked, families dispatched at run time.  A problem
+// whose right side has the lower family is solved mirrored (x -> -x: the
+// sides swap and the velocities change sign), which leaves p* and negates
+// u*, so a problem and its image take the same arithmetic.
 template <int FA, int FB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<FA, FB>))) void k_riemann_eos(
     long long n, const double* __restrict__ in, const int32_t* __restrict__ mat, const EosTable tab, double rtol,
@@ -142,8 +197,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerSi
         for (int k = 0; k < 6; ++k) q[k] = in[k * n + i];
         const int ml = mat[i], mr = mat[n + i];
         int its;
-        if constexpr (FA >= 0) {
-            const bool flip = FA != FB && tab.m[ml].fam != FA;
+        const bool valid = FA >= 0 || (ml >= 0 && ml < tab.n && mr >= 0 && mr < tab.n);
+        if (valid) {
+            const bool flip = FA >= 0 ? (FA != FB && tab.m[ml].fam != FA) : tab.m[ml].fam > tab.m[mr].fam;
             const double qm[6] = {flip ? q[3] : q[0], flip ? -q[4] : q[1], flip ? q[5] : q[2],
                                   flip ? q[0] : q[3], flip ? -q[1] : q[4], flip ? q[2] : q[5]};
             its = solve_pair<fam_set(FA), fam_set(FB)>(tab.m[flip ? mr : ml], tab.m[flip ? ml : mr], qm, rtol, maxit,
@@ -155,11 +211,114 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerSi
                 res[3] = r;
             }
         } else {
-            its = solve_one(tab, ml, mr, q, rtol, maxit, hmax, res);
+            its = 0;
+            for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
         }
         if (its == 0) atomicAdd(nbad, 1);
         for (int k = 0; k < 4; ++k) out[k * n + i] = res[k];
         if (iters) iters[i] = its;
+    }
+}
+
+// The same with the learned start (the grouping as for k_riemann_eos).  The
+// network is evaluated on the matrix cores by whole wavefronts, so the
+// range is walked in wavefronts; a wavefront evaluates it only for its
+// 16-lane groups that hold a problem away from equilibrium whose families
+// take it (learned_pair).  nfb counts the problems that started from the
+// acoustic guess.
+template <int FA, int FB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd<FA, FB>))) void k_riemann_eos_learned(
+    long long n, const double* __restrict__ in, const int32_t* __restrict__ mat, const EosTable tab, double rtol,
+    int maxit, double hmax, double* __restrict__ out, int32_t* __restrict__ iters, int32_t* __restrict__ nbad,
+    unsigned long long* __restrict__ nfb, const int32_t* __restrict__ perm, const int32_t* __restrict__ range,
+    const MlpDev net)
+{
+    static_assert(FA <= FB, "family pair in canonical order");
+    const long long lo = range ? (long long)range[0] : 0, hi = range ? (long long)range[1] : n;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    const int lane = threadIdx.x & 63;
+    unsigned long long fb = 0;
+    for (long long t0 = lo + (long long)blockIdx.x * blockDim.x + (threadIdx.x & ~63); t0 < hi; t0 += stride) {
+        const long long t = t0 + lane;
+        const bool live = t < hi;
+        long long i = 0;
+        int ml = 0, mr = 0;
+        bool flip = false, ok = false;
+        Pair P;
+        if (live) {
+            i = perm ? (long long)perm[t] : t;
+            ml = mat[i];
+            mr = mat[n + i];
+            const bool valid = FA >= 0 || (ml >= 0 && ml < tab.n && mr >= 0 && mr < tab.n);
+            if (valid) {
+                double q[6];
+                for (int k = 0; k < 6; ++k) q[k] = in[k * n + i];
+                flip = FA >= 0 ? (FA != FB && tab.m[ml].fam != FA) : tab.m[ml].fam > tab.m[mr].fam;
+                const double qm[6] = {flip ? q[3] : q[0], flip ? -q[4] : q[1], flip ? q[5] : q[2],
+                                      flip ? q[0] : q[3], flip ? -q[1] : q[4], flip ? q[2] : q[5]};
+                ok = pair_init<fam_set(FA), fam_set(FB)>(tab.m[flip ? mr : ml], tab.m[flip ? ml : mr], qm, P);
+            }
+        }
+        float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        double plo = 0.0, Pn = 1.0;
+        bool skip = !ok || eos_near_equilibrium(P);
+        if (!skip) {
+            const int fa = tab.m[flip ? mr : ml].fam, fb = tab.m[flip ? ml : mr].fam;
+            skip = !learned_pair(fa, fb) || !eos_features(P, fa, fb, x, plo, Pn);
+        }
+        const double g = guess64_mem(net, x, plo, Pn, skip);              // whole wavefront
+        if (!live) continue;
+        double res[4] = {__builtin_nan(""), __builtin_nan(""), __builtin_nan(""), __builtin_nan("")};
+        int its = 0;
+        bool used = false;
+        if (ok)
+            its = pair_solve<fam_set(FA), fam_set(FB)>(tab.m[flip ? mr : ml], tab.m[flip ? ml : mr], P, rtol, maxit,
+                                                       hmax, g, res, &used);
+        if (flip) {
+            const double r = res[2];
+            res[1] = -res[1];
+            res[2] = res[3];
+            res[3] = r;
+        }
+        fb += its != 0 && !used;
+        if (its == 0) atomicAdd(nbad, 1);
+        for (int k = 0; k < 4; ++k) out[k * n + i] = res[k];
+        if (iters) iters[i] = its;
+    }
+    for (int o = 32; o > 0; o >>= 1) fb += __shfl_xor(fb, o);
+    if (lane == 0 && fb) atomicAdd(nfb, fb);
+}
+
+// Features X [8][n] and targets t [n] (pstar given) of the learned start,
+// in the orientation the solver takes (lower family on the left); zeros and
+// NaN targets for an inadmissible problem or an index outside the table.
+__global__ __launch_bounds__(256) void k_eos_features(long long n, const double* __restrict__ in,
+                                                      const int32_t* __restrict__ mat, const EosTable tab,
+                                                      const double* __restrict__ pstar, float* __restrict__ X,
+                                                      float* __restrict__ tg)
+{
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        double plo = 0.0, Pn = 1.0;
+        bool ok = false;
+        const int ml = mat[i], mr = mat[n + i];
+        if (ml >= 0 && ml < tab.n && mr >= 0 && mr < tab.n) {
+            double q[6];
+            for (int k = 0; k < 6; ++k) q[k] = in[k * n + i];
+            const bool flip = tab.m[ml].fam > tab.m[mr].fam;
+            const double qm[6] = {flip ? q[3] : q[0], flip ? -q[4] : q[1], flip ? q[5] : q[2],
+                                  flip ? q[0] : q[3], flip ? -q[1] : q[4], flip ? q[2] : q[5]};
+            Pair P;
+            const EosK& a = tab.m[flip ? mr : ml];
+            const EosK& b = tab.m[flip ? ml : mr];
+            ok = pair_init(a, b, qm, P) && eos_features(P, a.fam, b.fam, x, plo, Pn);
+        }
+        for (int k = 0; k < 8; ++k) X[k * n + i] = ok ? x[k] : 0.f;
+        if (tg) {
+            const double ps = pstar ? pstar[i] : __builtin_nan("");
+            tg[i] = ok && ps > plo ? (float)log((ps - plo) / Pn) : __builtin_nanf("");
+        }
     }
 }
 
@@ -203,16 +362,29 @@ struct SolveArgs {
     int32_t* iters;
     int32_t* nbad;
     const int32_t* perm;
+    const MlpDev* net;                 // learned start (nullable)
+    unsigned long long* nfb;           // acoustic starts (with net)
 };
 
+// (the learned kernel only for a family pair that takes the learned start,
+// or for the run-time dispatch)
+// Returns whether the learned kernel was launched.
 template <int FA, int FB>
-void launch_solve(const SolveArgs& a, unsigned grid, const int32_t* range, hipStream_t s)
+bool launch_solve(const SolveArgs& a, unsigned grid, const int32_t* range, hipStream_t s)
 {
+    if constexpr (FA < 0 || learned_pair(FA, FB)) {
+        if (a.net) {
+            hipLaunchKernelGGL((k_riemann_eos_learned<FA, FB>), dim3(grid), dim3(256), 0, s, a.n, a.in, a.mat, a.tab,
+                               a.rtol, a.maxit, a.hmax, a.out, a.iters, a.nbad, a.nfb, a.perm, range, *a.net);
+            return true;
+        }
+    }
     hipLaunchKernelGGL((k_riemann_eos<FA, FB>), dim3(grid), dim3(256), 0, s, a.n, a.in, a.mat, a.tab, a.rtol,
                        a.maxit, a.hmax, a.out, a.iters, a.nbad, a.perm, range);
+    return false;
 }
 
-using SolveLaunch = void (*)(const SolveArgs&, unsigned, const int32_t*, hipStream_t);
+using SolveLaunch = bool (*)(const SolveArgs&, unsigned, const int32_t*, hipStream_t);
 // by family-pair group 3 FA + FB, FA <= FB (families M2C_EOS_NASG, _MG, _JWL
 // = 0, 1, 2; the other groups stay empty)
 constexpr SolveLaunch kSolvePair[9] = {launch_solve<0, 0>, launch_solve<0, 1>, launch_solve<0, 2>,
@@ -225,9 +397,11 @@ static_assert(M2C_EOS_NASG == 0 && M2C_EOS_MG == 1 && M2C_EOS_JWL == 2, "family-
 
 using namespace m2c;
 
-extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat,
-                                     const m2c_eos* eos, double rtol, int32_t maxit, double ds, double* out,
-                                     int32_t* iters, void* hip_stream)
+namespace {
+
+int solve_eos(const MlpDev* net, int64_t n, const double* in, const int32_t* mat, int32_t nmat, const m2c_eos* eos,
+              double rtol, int32_t maxit, double ds, double* out, int32_t* iters, int64_t* n_fallback,
+              void* hip_stream)
 {
     if (n < 0 || (n > 0 && (!in || !mat || !out))) return M2C_ERR_ARG;
     if (!(rtol > 0.0) || maxit < 1) return M2C_ERR_ARG;
@@ -240,18 +414,23 @@ extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t*
     // grouped by material pair, and within that by family pair (32-bit slots)
     const bool group = n < (1LL << 31);
     // workspace (int32): failure count, key counts, key cursors, family-pair
-    // ranges, permutation
-    const long long words = 1 + 2 * NKEY + 2 * NFP + (group ? n : 0);
+    // ranges, acoustic-start count (64-bit), permutation
+    const long long words = 1 + 2 * NKEY + 2 * NFP + 3 + (group ? n : 0);
     int32_t* dbad = nullptr;
     if (hipMalloc((void**)&dbad, words * sizeof(int32_t)) != hipSuccess) return M2C_ERR_NOMEM;
     int32_t* counts = dbad + 1;
     int32_t* cursor = counts + NKEY;
     int32_t* range = cursor + NKEY;
-    int32_t* perm = group ? range + 2 * NFP : nullptr;
+    unsigned long long* nfb = (unsigned long long*)(range + 2 * NFP + 1);   // 8-byte aligned
+    int32_t* perm = group ? range + 2 * NFP + 3 : nullptr;
     int32_t hb = 0;
     int rc = M2C_OK;
-    const SolveArgs sa{(long long)n, in, mat, tab, rtol, (int)maxit, ds, out, iters, dbad, perm};
-    if (hipMemsetAsync(dbad, 0, (1 + NKEY) * sizeof(int32_t), s) != hipSuccess) rc = M2C_ERR_DEVICE;
+    unsigned long long hfb = 0;
+    bool learned = false;              // a learned kernel counted the acoustic starts
+    const SolveArgs sa{(long long)n, in, mat, tab, rtol, (int)maxit, ds, out, iters, dbad, perm, net, nfb};
+    if (hipMemsetAsync(dbad, 0, (1 + NKEY) * sizeof(int32_t), s) != hipSuccess ||
+        hipMemsetAsync(nfb, 0, sizeof(unsigned long long), s) != hipSuccess)
+        rc = M2C_ERR_DEVICE;
     if (rc == M2C_OK && group) {
         KeyGroups kg;
         for (int k = 0; k < NKEY; ++k) {
@@ -278,22 +457,69 @@ extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t*
                 ++nonempty;
             }
         if (rc == M2C_OK && nonempty == 1 && only < NFP - 1 && kSolvePair[only]) {
-            kSolvePair[only](sa, grid_for(hr[2 * only + 1] - hr[2 * only]), range + 2 * only, s);
+            learned = kSolvePair[only](sa, grid_for(hr[2 * only + 1] - hr[2 * only]), range + 2 * only, s);
         } else if (rc == M2C_OK) {
-            launch_solve<-1, -1>(sa, grid_for(n), nullptr, s);
+            // several family pairs in one launch: the learned start only
+            // where it pays for the whole launch, i.e. no Mie-Grueneisen
+            // group (its walks set the time of a mixed launch) and some
+            // group that takes it
+            bool mg = false, takes = false;
+            for (int f = 0; f < NFP - 1; ++f)
+                if (hr[2 * f + 1] > hr[2 * f]) {
+                    mg = mg || f / 3 == M2C_EOS_MG || f % 3 == M2C_EOS_MG;
+                    takes = takes || learned_pair(f / 3, f % 3);
+                }
+            SolveArgs sm = sa;
+            if (mg || !takes) sm.net = nullptr;
+            learned = launch_solve<-1, -1>(sm, grid_for(n), nullptr, s);
         }
         if (rc == M2C_OK && hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
     } else if (rc == M2C_OK) {
-        launch_solve<-1, -1>(sa, grid_for(n), nullptr, s);
+        learned = launch_solve<-1, -1>(sa, grid_for(n), nullptr, s);
         if (hipGetLastError() != hipSuccess) rc = M2C_ERR_DEVICE;
     }
     if (rc == M2C_OK &&
         (hipMemcpyAsync(&hb, dbad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+         hipMemcpyAsync(&hfb, nfb, sizeof(hfb), hipMemcpyDeviceToHost, s) != hipSuccess ||
          hipStreamSynchronize(s) != hipSuccess))
         rc = M2C_ERR_DEVICE;
     (void)hipFree(dbad);
+    // without a learned launch every solved problem started from the
+    // acoustic guess
+    if (n_fallback) *n_fallback = learned ? (int64_t)hfb : (int64_t)n - hb;
     if (rc == M2C_OK && hb > 0) rc = M2C_ERR_RIEMANN;
     return rc;
+}
+
+}  // namespace
+
+extern "C" int m2c_riemann_solve_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat,
+                                     const m2c_eos* eos, double rtol, int32_t maxit, double ds, double* out,
+                                     int32_t* iters, void* hip_stream)
+{
+    return solve_eos(nullptr, n, in, mat, nmat, eos, rtol, maxit, ds, out, iters, nullptr, hip_stream);
+}
+
+extern "C" int m2c_riemann_solve_eos_learned(const m2c_mlp* m, int64_t n, const double* in, const int32_t* mat,
+                                             int32_t nmat, const m2c_eos* eos, double rtol, int32_t maxit,
+                                             double ds, double* out, int32_t* iters, int64_t* n_fallback,
+                                             void* hip_stream)
+{
+    if (n_fallback) *n_fallback = 0;
+    return solve_eos(m2c_mlp_dev(m), n, in, mat, nmat, eos, rtol, maxit, ds, out, iters, n_fallback, hip_stream);
+}
+
+extern "C" int m2c_mlp_features_eos(int64_t n, const double* in, const int32_t* mat, int32_t nmat,
+                                    const m2c_eos* eos, const double* pstar, float* X8, float* target,
+                                    void* hip_stream)
+{
+    if (n < 0 || (n > 0 && (!in || !mat || !X8))) return M2C_ERR_ARG;
+    EosTable tab;
+    if (!prepare(nmat, eos, tab)) return M2C_ERR_ARG;
+    if (n == 0) return M2C_OK;
+    hipLaunchKernelGGL(k_eos_features, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, (long long)n, in,
+                       mat, tab, pstar, X8, target);
+    return hipGetLastError() == hipSuccess ? M2C_OK : M2C_ERR_DEVICE;
 }
 
 extern "C" int m2c_eos_eval(int64_t n, const double* rho, const double* e, const int32_t* mat, int32_t nmat,

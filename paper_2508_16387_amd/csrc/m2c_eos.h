@@ -47,6 +47,10 @@
 #ifndef M2C_HD
 #define M2C_HD __device__
 #endif
+// the wave-curve code is inlined into every kernel that uses it: kernels
+// that share one family's functions would otherwise call them, and a call
+// keeps the solver's state on the stack
+#define M2C_HDI M2C_HD __attribute__((always_inline)) inline
 
 namespace m2c {
 namespace eos {
@@ -147,7 +151,7 @@ M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
 
 // e(v, p)
 template <int S = FAM_ALL>
-M2C_HD double eos_e(const EosK& m, double v, double p)
+M2C_HDI double eos_e(const EosK& m, double v, double p)
 {
     if (fam_of<S>(m) == M2C_EOS_NASG) return (p + m.k[5]) * (v - m.k[2]) * m.k[4] + m.k[3];
     if (fam_of<S>(m) == M2C_EOS_MG) {
@@ -161,7 +165,7 @@ M2C_HD double eos_e(const EosK& m, double v, double p)
 
 // p(v, e)
 template <int S = FAM_ALL>
-M2C_HD double eos_p(const EosK& m, double v, double e)
+M2C_HDI double eos_p(const EosK& m, double v, double e)
 {
     if (fam_of<S>(m) == M2C_EOS_NASG) return (e - m.k[3]) / ((v - m.k[2]) * m.k[4]) - m.k[5];
     if (fam_of<S>(m) == M2C_EOS_MG) {
@@ -175,7 +179,7 @@ M2C_HD double eos_p(const EosK& m, double v, double e)
 
 // c^2(v, p)
 template <int S = FAM_ALL>
-M2C_HD double eos_c2(const EosK& m, double v, double p)
+M2C_HDI double eos_c2(const EosK& m, double v, double p)
 {
     if (fam_of<S>(m) == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v / (v - m.k[2]);
     if (fam_of<S>(m) == M2C_EOS_MG) {
@@ -189,7 +193,7 @@ M2C_HD double eos_c2(const EosK& m, double v, double p)
 
 // c^2(v, p) with the Mie-Grueneisen branch given (other families: eos_c2).
 template <int S = FAM_ALL>
-M2C_HD double eos_c2_on(const EosK& m, double v, double p, int br)
+M2C_HDI double eos_c2_on(const EosK& m, double v, double p, int br)
 {
     if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref_on(m, 1.0 - m.k[0] * v, br);
@@ -200,7 +204,7 @@ M2C_HD double eos_c2_on(const EosK& m, double v, double p, int br)
 
 // de/dv at constant p, and de/dp at constant v.
 template <int S = FAM_ALL>
-M2C_HD void eos_ederiv(const EosK& m, double v, double p, double& ev, double& ep)
+M2C_HDI void eos_ederiv(const EosK& m, double v, double p, double& ev, double& ep)
 {
     if (fam_of<S>(m) == M2C_EOS_NASG) {
         ev = (p + m.k[5]) * m.k[4];
@@ -234,7 +238,7 @@ struct Wave {
 // (y, s, f) to y + h: ds/dy = (p - floor)/(rho c^2), df/dy = c ds/dy.
 // False where c^2 <= 0 (outside the convex part of the EOS).
 template <int S = FAM_ALL>
-M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, double& f)
+M2C_HDI bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, double& f)
 {
     double ks[4], kf[4];
     // every stage on one Mie-Grueneisen branch: a step never spans a branch
@@ -269,7 +273,7 @@ M2C_HD bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, d
 // exactly -- a Newton iteration on the length of the step that ends there --
 // so that no RK4 step spans one and each keeps its order.
 template <int S = FAM_ALL>
-M2C_HD bool walk(const EosK& m, Side& K, double Y, double hmax)
+M2C_HDI bool walk(const EosK& m, Side& K, double Y, double hmax)
 {
     double kink[2] = {INFINITY, INFINITY};
     if (fam_of<S>(m) == M2C_EOS_MG) {
@@ -442,7 +446,7 @@ M2C_HD inline void jwl_ps(const EosK& m, double C, double v, double& ps, double&
 // most 0.1 in ln v; where both exponentials are below e^-40 of their
 // amplitude the integrand is the power law sqrt((1 + omega) C) v^-(1 + omega/2)
 // and the rest is integrated in closed form.  False where -p_s' <= 0.
-M2C_HD bool jwl_quad(const EosK& m, double C, double v0, double v1, double& I)
+M2C_HDI bool jwl_quad(const EosK& m, double C, double v0, double v1, double& I)
 {
     const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
     const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
@@ -480,7 +484,7 @@ M2C_HD bool jwl_quad(const EosK& m, double C, double v0, double v1, double& I)
 
 // f_K(p) for p <= p_K on a JWL side: v* from p_s(v*) = p by safeguarded
 // Newton in ln v, f continued from the last point of this isentrope.
-M2C_HD bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
+M2C_HDI bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
 {
     const double C = K.jC;
     double lo = K.v, hi = INFINITY;                     // p_s(lo) >= p > p_s(hi)
@@ -526,7 +530,7 @@ M2C_HD bool jwl_rarefaction(const EosK& m, Side& K, double p, Wave& w)
 
 // f_K(p) for p <= p_K: the isentrope walked to y = ln(p - floor).
 template <int S = FAM_ALL>
-M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
+M2C_HDI bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
     if (fam_of<S>(m) == M2C_EOS_JWL) {
         if (p == K.p) {
@@ -573,7 +577,7 @@ M2C_HD bool rarefaction(const EosK& m, Side& K, double p, double hmax, Wave& w)
 // f_K(p) for p > p_K: Hugoniot volume by Newton in v, bracketed by
 // (v_min, v_K].
 template <int S = FAM_ALL>
-M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
+M2C_HDI bool shock(const EosK& m, Side& K, double p, Wave& w)
 {
     const double vK = K.v, half = 0.5 * (p + K.p);
     double lo = m.k[KVMIN], hi = vK;
@@ -587,6 +591,15 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
         const double H = eos_e<S>(m, v, p) - K.e - half * (vK - v);
         double ev, ep;
         eos_ederiv<S>(m, v, p, ev, ep);
+        if (!(ev + half > 0.0)) {
+            // H does not increase here: a stretch below the branch the
+            // shock takes (JWL has a second, unphysical root at strong
+            // compression, which an acoustic start far above p_K can pass);
+            // the physical root is the largest one, above v
+            lo = v;
+            v = 0.5 * (lo + hi);
+            continue;
+        }
         if (H > 0.0) hi = v; else lo = v;
         const double step = H / (ev + half);
         // a converged Newton step is taken before the bracket is consulted
@@ -618,7 +631,7 @@ M2C_HD bool shock(const EosK& m, Side& K, double p, Wave& w)
 }
 
 template <int S = FAM_ALL>
-M2C_HD inline bool wave(const EosK& m, Side& K, double p, double hmax, Wave& w)
+M2C_HDI bool wave(const EosK& m, Side& K, double p, double hmax, Wave& w)
 {
     return p > K.p ? shock<S>(m, K, p, w) : rarefaction<S>(m, K, p, hmax, w);
 }
@@ -629,7 +642,7 @@ M2C_HD inline double floor_margin(const Side& K)
 }
 
 template <int S = FAM_ALL>
-M2C_HD bool side_init(const EosK& m, double rho, double p, Side& K)
+M2C_HDI bool side_init(const EosK& m, double rho, double p, Side& K)
 {
     K.fl = m.k[KFLOOR];
     if (!(rho > 0.0) || !isfinite(rho) || !isfinite(p)) return false;
@@ -664,80 +677,135 @@ M2C_HD inline double bisect(double lo, double hi, double base)
     return b > 1e3 * a ? base + sqrt(a * b) : 0.5 * (lo + hi);
 }
 
-// One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials mL, mR;
-// res = (p*, u*, rho*_L, rho*_R) or NaN; returns the Newton steps (negative
-// after a bisection step; 0: no star state or an inadmissible input).
+// One problem set up for the outer iteration: both sides' states and the
+// acoustic start.
+struct Pair {
+    Side L, R;
+    double uL, uR, du;
+    double pfl;                    // lowest admissible trial pressure
+    double base;                   // the higher floor (reference of the geometric bisection)
+    double pac;                    // acoustic start, kept above pfl
+};
+
+// Set-up of q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials mL, mR;
+// false for an inadmissible input.
 template <int SL = FAM_ALL, int SR = FAM_ALL>
-M2C_HD inline int solve_pair(const EosK& mL, const EosK& mR, const double* q, double rtol, int maxit, double hmax,
-                             double* res)
+M2C_HDI bool pair_init(const EosK& mL, const EosK& mR, const double* q, Pair& P)
+{
+    if (!side_init<SL>(mL, q[0], q[2], P.L) || !side_init<SR>(mR, q[3], q[5], P.R)) return false;
+    P.uL = q[1];
+    P.uR = q[4];
+    P.du = P.uR - P.uL;
+    P.pfl = fmax(P.L.fl + floor_margin(P.L), P.R.fl + floor_margin(P.R));
+    P.base = fmax(P.L.fl, P.R.fl);
+    const double zL = P.L.rho * P.L.c, zR = P.R.rho * P.R.c;
+    double p = (zR * P.L.p + zL * P.R.p - zL * zR * P.du) / (zL + zR);
+    if (!(p > P.pfl)) p = P.pfl + 0.5 * (fmin(P.L.p, P.R.p) - P.pfl);
+    P.pac = p;
+    return true;
+}
+
+// Outer iteration of a set-up problem: res = (p*, u*, rho*_L, rho*_R) or
+// NaN; returns the Newton steps (negative after a bisection step; 0: no
+// star state).  guess: a candidate start (NaN: none).  F and F' are
+// evaluated there (they become the first Newton step when it is kept, and
+// F's sign narrows the bracket either way); the candidate is kept unless
+// the tangent there predicts a smaller |F| at the acoustic start.  F is
+// increasing in p, so Newton converges from either start, and the answer
+// does not depend on the candidate beyond the stopping tolerance.  *used
+// (nullable): the candidate was the start.
+template <int SL = FAM_ALL, int SR = FAM_ALL>
+M2C_HDI int pair_solve(const EosK& mL, const EosK& mR, Pair& P, double rtol, int maxit, double hmax,
+                             double guess, double* res, bool* used = nullptr)
 {
     for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
-    int its = 0;
-    Side L, R;
-    bool ok = side_init<SL>(mL, q[0], q[2], L);
-    ok = ok && side_init<SR>(mR, q[3], q[5], R);
-    if (ok) {
-        const double uL = q[1], uR = q[4], du = uR - uL;
-        const double pfl = fmax(L.fl + floor_margin(L), R.fl + floor_margin(R));
-        const double base = fmax(L.fl, R.fl);
-        // acoustic start
-        const double zL = L.rho * L.c, zR = R.rho * R.c;
-        double p = (zR * L.p + zL * R.p - zL * zR * du) / (zL + zR);
-        if (!(p > pfl)) p = pfl + 0.5 * (fmin(L.p, R.p) - pfl);
-        double lo = pfl, hi = INFINITY;
-        bool bis = false, floor_checked = false, conv = false;
-        Wave wl, wr;
-        ok = false;
-        for (its = 1; its <= maxit; ++its) {
-            if (!wave<SL>(mL, L, p, hmax, wl) || !wave<SR>(mR, R, p, hmax, wr)) {
-                // p lies below where an isentrope ends (c^2 reaches zero
-                // before the floor): it bounds the bracket from below
-                lo = p;
-                p = isinf(hi) ? 0.5 * (p + fmax(L.p, R.p)) : bisect(lo, hi, base);
-                bis = true;
-                continue;
+    if (used) *used = false;
+    Side& L = P.L;
+    Side& R = P.R;
+    const double uL = P.uL, uR = P.uR, du = P.du, pfl = P.pfl, base = P.base;
+    double p = P.pac;
+    double lo = pfl, hi = INFINITY;
+    bool bis = false, floor_checked = false, conv = false, first = false;
+    Wave wl, wr;
+    if (guess > pfl && isfinite(guess)) {
+        Wave a, b;
+        if (wave<SL>(mL, L, guess, hmax, a) && wave<SR>(mR, R, guess, hmax, b)) {
+            const double F = a.f + b.f + du, dF = a.df + b.df;
+            if (F < 0.0) lo = guess; else hi = guess;
+            if (fabs(F) <= fabs(F + dF * (p - guess))) {
+                p = guess;
+                wl = a;
+                wr = b;
+                first = true;
+                if (used) *used = true;
             }
-            const double F = wl.f + wr.f + du;
-            if (F < 0.0) lo = p; else hi = p;
-            double pn = p - F / (wl.df + wr.df);
-            const double tol = rtol * fmin(p - L.fl, p - R.fl);
-            if (fabs(pn - p) <= tol && pn > pfl) {
-                p = pn;
-                conv = true;
-                break;
-            }
-            // F at the rounding level of its terms, or a bracket closed to a
-            // few ulps: p is as good as FP64 resolves it (near cavitation
-            // the stopping rule above asks for more)
-            if (fabs(F) <= 8e-16 * (fabs(wl.f) + fabs(wr.f) + fabs(uL) + fabs(uR)) ||
-                (isfinite(hi) && hi - lo <= 4e-16 * fabs(hi))) {
-                conv = true;
-                break;
-            }
-            if (!(pn > lo && pn < hi)) {
-                if (!(pn > lo) && lo == pfl && !floor_checked) {
-                    // the Newton step leaves the admissible range: is
-                    // there a star state above the floor at all?
-                    floor_checked = true;
-                    Wave a, b;
-                    if (!wave<SL>(mL, L, pfl, hmax, a) || !wave<SR>(mR, R, pfl, hmax, b)) break;
-                    if (a.f + b.f + du > 0.0) break;          // cavitation
-                }
-                pn = isinf(hi) ? p + fmax(p - pfl, fabs(p) + 1.0) : bisect(lo, hi, base);
-                bis = true;
-            }
-            p = pn;
         }
-        if (conv && wave<SL>(mL, L, p, hmax, wl) && wave<SR>(mR, R, p, hmax, wr)) {
-            res[0] = p;
-            res[1] = 0.5 * (uL - wl.f + uR + wr.f);
-            res[2] = wl.rho;
-            res[3] = wr.rho;
-            ok = true;
-            if (bis) its = -its;
-        }
+        // (a candidate where a wave curve cannot be evaluated is dropped)
     }
-    return ok ? its : 0;
+    int its;
+    for (its = 1; its <= maxit; ++its) {
+        if (!(first && its == 1) && (!wave<SL>(mL, L, p, hmax, wl) || !wave<SR>(mR, R, p, hmax, wr))) {
+            // p lies below where an isentrope ends (c^2 reaches zero
+            // before the floor): it bounds the bracket from below
+            lo = fmax(lo, p);
+            p = isinf(hi) ? 0.5 * (p + fmax(L.p, R.p)) : bisect(lo, hi, base);
+            bis = true;
+            continue;
+        }
+        const double F = wl.f + wr.f + du;
+        if (F < 0.0) lo = fmax(lo, p); else hi = fmin(hi, p);
+        double pn = p - F / (wl.df + wr.df);
+        const double tol = rtol * fmin(p - L.fl, p - R.fl);
+        if (fabs(pn - p) <= tol && pn > pfl) {
+            p = pn;
+            conv = true;
+            break;
+        }
+        // F at the rounding level of its terms, or a bracket closed to a
+        // few ulps: p is as good as FP64 resolves it (near cavitation
+        // the stopping rule above asks for more)
+        if (fabs(F) <= 8e-16 * (fabs(wl.f) + fabs(wr.f) + fabs(uL) + fabs(uR)) ||
+            (isfinite(hi) && hi - lo <= 4e-16 * fabs(hi))) {
+            conv = true;
+            break;
+        }
+        if (!(pn > lo && pn < hi)) {
+            if (!(pn > lo) && lo == pfl && !floor_checked) {
+                // the Newton step leaves the admissible range: is
+                // there a star state above the floor at all?
+                floor_checked = true;
+                Wave a, b;
+                if (!wave<SL>(mL, L, pfl, hmax, a) || !wave<SR>(mR, R, pfl, hmax, b)) break;
+                if (a.f + b.f + du > 0.0) break;          // cavitation
+            }
+            pn = isinf(hi) ? p + fmax(p - pfl, fabs(p) + 1.0) : bisect(lo, hi, base);
+            bis = true;
+        }
+        p = pn;
+    }
+    if (conv && wave<SL>(mL, L, p, hmax, wl) && wave<SR>(mR, R, p, hmax, wr)) {
+        res[0] = p;
+        res[1] = 0.5 * (uL - wl.f + uR + wr.f);
+        res[2] = wl.rho;
+        res[3] = wr.rho;
+        return bis ? -its : its;
+    }
+    return 0;
+}
+
+// One problem: q = (rho_L, u_L, p_L, rho_R, u_R, p_R) of materials mL, mR
+// from the acoustic start; res and the return value as for pair_solve (0
+// also for an inadmissible input).
+template <int SL = FAM_ALL, int SR = FAM_ALL>
+M2C_HDI int solve_pair(const EosK& mL, const EosK& mR, const double* q, double rtol, int maxit, double hmax,
+                             double* res)
+{
+    Pair P;
+    if (!pair_init<SL, SR>(mL, mR, q, P)) {
+        for (int k = 0; k < 4; ++k) res[k] = __builtin_nan("");
+        return 0;
+    }
+    return pair_solve<SL, SR>(mL, mR, P, rtol, maxit, hmax, __builtin_nan(""), res);
 }
 
 // The same for materials ml, mr of a table (0 for an index out of range).
