@@ -327,11 +327,40 @@ def general_eos_step(m2c, torch, steps=20):
     on 128^3 cells, FP64, TVD-RK2 with MC and HLLC.  Interface faces take the
     general-EOS exact Riemann solve (Hugoniot shocks, closed-form JWL and
     NASG isentropes)."""
+    import numpy as np
+
     import workloads as W
     p = W.eos_charge(0, n=(128, 128, 128), steps=steps)
     rate, T = time_sim(m2c, torch, p, m2c.M2C_PREC_FP64, steps, 2)
-    return {"workload": "tnt_sphere_in_water_nasg_128", "steps": steps, "cell_updates_per_stage_per_s": rate,
-            "ms_per_step": T / steps * 1e3}
+    out = {"workload": "tnt_sphere_in_water_nasg_128", "steps": steps, "cell_updates_per_stage_per_s": rate,
+           "ms_per_step": T / steps * 1e3}
+    # FIVER of the same run from the acoustic and from the learned start
+    # (library events around the kernels of every step)
+    net = m2c.Mlp(np.load(os.path.join(ROOT, "paper_2508_16387_amd", "learned_guess_eos.npy")))
+    for name, guess in (("acoustic", None), ("learned", net)):
+        sim = m2c.Sim(m2c.config_for(p))
+        sim.set_stream(torch.cuda.current_stream())
+        if guess is not None:
+            sim.set_guess(guess)
+        sim.set_state(p.prim)
+        sim.step(2)
+        sim.set_state(p.prim)
+        sim.reset_stats()
+        sim.set_profiling(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        Ts = time.perf_counter() - t0
+        st = sim.stats()
+        out["fiver_" + name] = {"ms_per_step": Ts / steps * 1e3,
+                                "fiver_ms_per_launch": st["ms_fiver"] / max(st["fiver_launches"], 1),
+                                "newton_iters_per_solve": st["newton_iters"] / max(st["riemann_solves"], 1),
+                                "acoustic_starts": st["mlp_fallbacks"] if guess is not None else None}
+        sim.close()
+    out["fiver_speedup_learned_vs_acoustic"] = (out["fiver_acoustic"]["fiver_ms_per_launch"] /
+                                                out["fiver_learned"]["fiver_ms_per_launch"])
+    return out
 
 
 def host_round_trip(m2c, torch, problem, steps):

@@ -365,7 +365,11 @@ int m2c_riemann_solve_learned_noalloc(const m2c_mlp* m, int64_t n, const double*
                                       double rtol, int32_t maxit, double* out, int32_t* iters,
                                       void* hip_stream);
 /* Use a copy of the network for every interface Riemann problem of later
- * steps (NULL: back to the acoustic guess). */
+ * steps (NULL: back to the acoustic guess).  With eos_general, m is a
+ * network of the general-EOS features (m2c_mlp_features_eos), consulted
+ * when the two materials' families take the learned start (a JWL side and
+ * no Mie-Grueneisen side, as for m2c_riemann_solve_eos_learned); other
+ * pairs keep the acoustic start. */
 int m2c_set_guess(m2c_ctx* ctx, const m2c_mlp* m);
 
 /* ---- level-set reinitialization (section "Level set method", eq. reinit) --

@@ -20,6 +20,7 @@
 #include "m2c_device.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
+#include "m2c_mlp_eos.h"
 #include "m2c_mlp_infer.h"
 
 namespace m2c {
@@ -401,7 +402,7 @@ template <bool EG, bool LG = false, int F0 = -1, int F1 = -1>
 __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int blk, int nblk,
                                            const MlpDev* m = nullptr)
 {
-    static_assert(!(EG && LG), "the learned guess is for stiffened gases");
+    static_assert(!(EG && LG) || (F0 >= 0 && F1 >= 0), "the general-EOS learned start needs the families");
     __shared__ unsigned long long sCnt[3][4];
     __shared__ int sErr;
     __shared__ eos::EosK sEos[EG ? 2 : 1];
@@ -440,7 +441,7 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
         bool used = false;
         bool hg = false;
         double gs = 0.0;
-        if constexpr (LG) {
+        if constexpr (LG && !EG) {
             const bool skip = !live || acoustic_suffices(qa[0], ua, qa[4], gA, pcA, qb[0], ub, qb[4], gB, pcB);
             if (__ballot(!skip) != 0ull) {                       // wave-uniform
                 float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -461,7 +462,25 @@ __device__ __forceinline__ void fiver_body(const IfaceArgs& a, int record, int b
             const double in[6] = {flip ? qb[0] : qa[0], flip ? -ub : ua, flip ? qb[4] : qa[4],
                                   flip ? qa[0] : qb[0], flip ? -ua : ub, flip ? qa[4] : qb[4]};
             double o[4];
-            it = eos::solve_pair<eos::fam_set(F0), eos::fam_set(F1)>(sEos[0], sEos[1], in, G.rtol, G.maxit, G.rds, o);
+            constexpr int S0 = eos::fam_set(F0), S1 = eos::fam_set(F1);
+            if constexpr (LG) {
+                // learned start (the families take it, see learned_pair):
+                // the network evaluated by whole wavefronts for the faces
+                // away from equilibrium, then the judged outer iteration
+                eos::Pair P;
+                const bool ok = live && eos::pair_init<S0, S1>(sEos[0], sEos[1], in, P);
+                float x[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                double plo = 0.0, Pn = 1.0;
+                const bool skip = !ok || eos_near_equilibrium(P) || !eos_features(P, F0, F1, x, plo, Pn);
+                double g = __builtin_nan("");
+                if (__ballot(!skip) != 0ull) g = guess64_mem(*m, x, plo, Pn, skip);      // wave-uniform
+                if (!live) continue;
+                it = 0;
+                for (int k = 0; k < 4; ++k) o[k] = __builtin_nan("");
+                if (ok) it = eos::pair_solve<S0, S1>(sEos[0], sEos[1], P, G.rtol, G.maxit, G.rds, g, o, &used);
+            } else {
+                it = eos::solve_pair<S0, S1>(sEos[0], sEos[1], in, G.rtol, G.maxit, G.rds, o);
+            }
             out[0] = o[0];
             out[1] = flip ? -o[1] : o[1];
             out[2] = flip ? o[3] : o[2];
@@ -554,12 +573,25 @@ __global__ __launch_bounds__(256) void k_fiver_eos(const IfaceArgs a, int record
     fiver_body<true, false, F0, F1>(a, record, blockIdx.x, gridDim.x);
 }
 
+// with the learned start, for the family pairs that take it (learned_pair)
 template <int F0, int F1>
-void launch_fiver_eos(const IfaceArgs& a, unsigned nb, int record, hipStream_t s)
+__global__ __launch_bounds__(256) void k_fiver_eos_learned(const IfaceArgs a, int record, const MlpDev m)
 {
+    fiver_body<true, true, F0, F1>(a, record, blockIdx.x, gridDim.x, &m);
+}
+
+template <int F0, int F1>
+void launch_fiver_eos(const IfaceArgs& a, unsigned nb, int record, const MlpDev* mlp, hipStream_t s)
+{
+    if constexpr (learned_pair(F0, F1)) {
+        if (mlp) {
+            hipLaunchKernelGGL((k_fiver_eos_learned<F0, F1>), dim3(nb), dim3(256), 0, s, a, record, *mlp);
+            return;
+        }
+    }
     hipLaunchKernelGGL((k_fiver_eos<F0, F1>), dim3(nb), dim3(256), 0, s, a, record);
 }
-using FiverEosLaunch = void (*)(const IfaceArgs&, unsigned, int, hipStream_t);
+using FiverEosLaunch = void (*)(const IfaceArgs&, unsigned, int, const MlpDev*, hipStream_t);
 // by 3 family(material 0) + family(material 1), families NASG, MG, JWL = 0, 1, 2
 constexpr FiverEosLaunch kFiverEos[9] = {launch_fiver_eos<0, 0>, launch_fiver_eos<0, 1>, launch_fiver_eos<0, 2>,
                                          launch_fiver_eos<1, 0>, launch_fiver_eos<1, 1>, launch_fiver_eos<1, 2>,
@@ -579,7 +611,7 @@ hipError_t launch_fiver(const IfaceArgs& a, bool record, const MlpDev* mlp, hipS
     if (a.g.eosg) {
         const int f0 = a.g.ek[0].fam, f1 = a.g.ek[1].fam;
         if (f0 < 0 || f0 > 2 || f1 < 0 || f1 > 2) return hipErrorInvalidValue;
-        kFiverEos[3 * f0 + f1](a, (unsigned)nb, record ? 1 : 0, s);
+        kFiverEos[3 * f0 + f1](a, (unsigned)nb, record ? 1 : 0, mlp, s);
     } else if (mlp)
         hipLaunchKernelGGL(k_fiver_learned, dim3((unsigned)nb), dim3(256), 0, s, a, record ? 1 : 0, *mlp);
     else

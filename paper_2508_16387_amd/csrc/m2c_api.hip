@@ -897,7 +897,6 @@ int m2c_set_guess(m2c_ctx* c, const m2c_mlp* m)
         c->use_mlp = false;
         return M2C_OK;
     }
-    if (c->g.eosg) return set_err(c, M2C_ERR_ARG, "the learned guess is for stiffened gases only");
     const MlpDev* src = m2c_mlp_dev(m);
     if (!c->mlp.master) {
         HIPCHK(c, hipMalloc((void**)&c->mlp.master, MLP_NPARAM * sizeof(float)));

@@ -174,3 +174,38 @@ def test_untrained_network_keeps_the_star_state(m2c):
     fl, cmax = _floor_and_speed(inp, mat, mats)
     assert (np.abs(ol[0] - oa[0])[ok] / (oa[0][ok] - fl[ok])).max() <= 1e-10
     assert (np.abs(ol[1] - oa[1])[ok] / cmax[ok]).max() <= 1e-9
+
+
+def test_learned_start_in_the_general_eos_step(m2c, net):
+    """The grid step with a general EOS per material and the learned start
+    at interface faces (JWL products in NASG water): the state after the
+    steps matches the oracle at the FP64 bar and the acoustic-start run to
+    the stopping rule, with fewer outer steps per interface solve."""
+    import oracle
+    from tests.parity import TOL_FP64, compare_runs
+    p = W.eos_charge(21, n=(20, 18, 16), steps=8)
+    print(p.name, p.n, "steps", p.steps, flush=True)
+    o = oracle.OracleSim(p)
+    assert o.step(p.steps) == 0
+    runs = {}
+    for name, guess in (("acoustic", None), ("learned", net)):
+        g = m2c.Sim(m2c.config_for(p), p.prim)
+        if guess is not None:
+            g.set_guess(guess)
+        assert g.step(p.steps) == 0
+        st = g.stats()
+        e = compare_runs(g, o, p)
+        print(name, {k: (f"{v:.2e}" if isinstance(v, float) else v) for k, v in e.items()},
+              "outer steps per solve", st["newton_iters"] / st["riemann_solves"], "acoustic starts",
+              st["mlp_fallbacks"], "of", st["riemann_solves"], flush=True)
+        assert e["id_mismatch"] == 0
+        for k in ("rho", "rhou", "rhov", "rhow", "rhoE", "phi"):
+            assert e[k] <= TOL_FP64, (name, k, e[k])
+        runs[name] = (g.get_conserved(), st)
+        g.close()
+    (wa, sa), (wl, sl) = runs["acoustic"], runs["learned"]
+    assert sa["riemann_solves"] == sl["riemann_solves"]
+    assert sl["newton_iters"] < sa["newton_iters"]
+    assert 0 < sl["mlp_fallbacks"] < sl["riemann_solves"]
+    scale = np.maximum(np.abs(wa).max(axis=1, keepdims=True), 1e-30)
+    assert np.max(np.abs(wl - wa) / scale) <= 1e-10
