@@ -115,7 +115,7 @@ bool valid_config(const m2c_config* c, char* why, size_t n)
         if (!(c->riemann_ds == 0.0 || (c->riemann_ds >= 1e-3 && c->riemann_ds <= 0.5)))
             return snprintf(why, n, "riemann_ds must be 0 or in [1e-3, 0.5]"), false;
         if ((c->tile_x || c->tile_y) && !stage_tile_supported_eos(c->tile_x, c->tile_y))
-            return snprintf(why, n, "general EOS: stage tile must be 16x16 or 64x2"), false;
+            return snprintf(why, n, "general EOS: stage tile must be 16x15 or 64x2"), false;
     } else {
         for (int m = 0; m < 2; ++m)
             if (!(c->gamma[m] > 1.0) || !(c->pc[m] >= 0.0) || !std::isfinite(c->pc[m]))
@@ -523,14 +523,14 @@ int m2c_create(const m2c_config* cfg, m2c_ctx** out)
     c->nblk_compact = (int)((N + COMPACT_CELLS_PER_BLOCK - 1) / COMPACT_CELLS_PER_BLOCK);
 
     // stage tiles: (tile_x, tile_y), else 16x15 (its 511 in-plane faces are
-    // exactly two rounds of the block's 256 threads; the general-EOS kernels
-    // come in 16x16), 64x2 for quasi-1D grids.  Planes per block: tile_z,
+    // exactly two rounds of the block's 256 threads), 64x2 for quasi-1D
+    // grids.  Planes per block: tile_z,
     // else the most of 32, 16 that still leaves at least 4096 blocks (16
     // rounds of two blocks per CU: the prologue of a block's march and the
     // re-read halo planes are amortised over more planes; 32 measured 1.5%
     // faster than 16 on 384^3), otherwise 8.
     c->tx = cfg->tile_x ? cfg->tile_x : 16;
-    c->ty = cfg->tile_y ? cfg->tile_y : (c->g.eosg ? 16 : 15);
+    c->ty = cfg->tile_y ? cfg->tile_y : 15;
     if (!cfg->tile_x && c->g.ny == 1) {
         c->tx = 64;
         c->ty = 2;
@@ -803,7 +803,7 @@ int m2c_autotune(m2c_ctx* c, int32_t steps, int32_t tile_out[3], float* ms_out)
 {
     static const int cands_sg[][3] = {{16, 15, 8}, {16, 15, 16}, {16, 16, 8}, {16, 16, 16}, {16, 16, 4},
                                       {32, 8, 8},  {32, 7, 8},   {16, 15, 4}, {16, 15, 32}};
-    static const int cands_eos[][3] = {{16, 16, 8}, {16, 16, 4}};
+    static const int cands_eos[][3] = {{16, 15, 8}, {16, 15, 4}};
     if (!c || steps < 1) return M2C_ERR_ARG;
     const int(*cands)[3] = c->g.eosg ? cands_eos : cands_sg;
     const int ncand = c->g.eosg ? 2 : 9;

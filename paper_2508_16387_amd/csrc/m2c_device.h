@@ -128,18 +128,21 @@ __device__ __forceinline__ T lim_slope(int limiter, int k, T dm, T dp, T alpha)
     return va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
 }
 
-// The limited slope, or 0 where the cell's stencil along the axis reaches
-// the other material (flat).  For the MC limiter the flag joins the
-// limiter's own sign test, so the slope stays one select and never becomes
-// a divergent branch per variable.
+// Half the limited slope (the offset of a face value from the cell value
+// in the linear reconstruction), or 0 where the cell's stencil along the
+// axis reaches the other material (flat).  halpha = alpha / 2.  For the MC
+// limiter the halving is folded into the limiter's constants, which gives
+// the same value as halving the slope (scaling by a power of two commutes
+// with rounding), and the flag joins the limiter's own sign test, so the
+// slope stays one select and never becomes a divergent branch per variable.
 template <typename T>
-__device__ __forceinline__ T lim_slope_flat(int limiter, int k, T dm, T dp, T alpha, bool flat)
+__device__ __forceinline__ T lim_half_slope_flat(int limiter, int k, T dm, T dp, T halpha, bool flat)
 {
     if (limiter == LIM_MC) {
-        const T a = fmin(alpha * fmin(fabs(dm), fabs(dp)), T(0.5) * fabs(dm + dp));
+        const T a = fmin(halpha * fmin(fabs(dm), fabs(dp)), T(0.25) * fabs(dm + dp));
         return ((!flat) & (dm * dp > T(0))) ? copysign(a, dp) : T(0);
     }
-    return flat ? T(0) : va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
+    return flat ? T(0) : T(0.5) * va_slope<T>(dm, dp, k, limiter == LIM_VA_MOD);
 }
 
 // --------------------------------------------------------------- HLLC ------

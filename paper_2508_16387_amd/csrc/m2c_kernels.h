@@ -76,10 +76,10 @@ bool stage_tile_supported(int tx, int ty);
 hipError_t launch_stage(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
 // the same with the configured limiter and flux (any, including MC + HLLC)
 hipError_t launch_stage_opts(int stage, bool mixed, int tx, int ty, const StageArgs& a, hipStream_t s);
-// general-EOS stage kernels (FP64; tiles 16x16 and 64x2)
+// general-EOS stage kernels (FP64; tiles 16x15 and 64x2)
 bool stage_tile_supported_eos(int tx, int ty);
 hipError_t launch_stage_eos(int stage, int tx, int ty, const StageArgs& a, hipStream_t s);
-// the default scheme on the 16x16 tile for fs, the set of the two
+// the default scheme on the 16x15 tile for fs, the set of the two
 // materials' families (eos::fam_set): sets with NASG, and the others
 hipError_t launch_stage_eos_nasg(int stage, int fs, const StageArgs& a, hipStream_t s);
 hipError_t launch_stage_eos_other(int stage, int fs, const StageArgs& a, hipStream_t s);

@@ -17,9 +17,9 @@
 // and marches along z over kz planes (2.5D).  Per plane the tile's
 // primitives plus a 2-cell halo ring are staged in LDS; the x- and y-faces
 // of the tile are evaluated once each as one flat work list over the
-// block's threads, by one code path whose only axis dependence is an LDS
-// stride and a component permutation (no divergence between x and y faces
-// inside a wavefront), and parked in LDS; the z-face above each column is
+// block's threads, laid out so that each wavefront holds faces of one axis
+// (no divergence between x and y faces, and LDS strides and component
+// order fixed at compile time per axis), and parked in LDS; the z-face above each column is
 // computed by the column's own thread from a 3-plane register window and
 // carried to the next plane.  Each face flux is therefore evaluated once.
 // Faces whose two cells hold different materials are not evaluated here:
@@ -39,6 +39,8 @@
 // interface faces (read straight from their FP64 buffer), the residual
 // accumulation and the update are FP64 in both forms.
 #pragma once
+#include <type_traits>
+
 #include "m2c_device.h"
 #include "m2c_internal.h"
 #include "m2c_kernels.h"
@@ -169,7 +171,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     if (!yact) miry = false;
     const uint32_t sxy = (uint32_t)nx * ny;
     const uint32_t col = si + (uint32_t)nx * sj;
-    const TF alpha = (TF)G.alpha;
+    const TF halpha = TF(0.5) * (TF)G.alpha;
     const int lim = OPTS ? G.limiter : (int)LIM_MC, limk = G.limk;
     const int flux = OPTS ? G.flux : (int)FLUX_HLLC;
 
@@ -192,13 +194,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         q[3] = TF((mz && zact) ? -ww : ww);
         q[4] = TF(p);
     };
-    // z-slope of a cell from its column neighbours (zero next to another
-    // material along z).
+    // half the z-slope of a cell from its column neighbours (zero next to
+    // another material along z).
     auto zslope = [&](const TF qm[5], const TF q0[5], const TF qp[5], uint8_t xm, uint8_t x0, uint8_t xp,
                       TF s[5]) {
         const bool flat = (xm != x0) || (xp != x0);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) s[v] = lim_slope_flat<TF>(lim, limk, q0[v] - qm[v], qp[v] - q0[v], alpha, flat);
+        for (int v = 0; v < 5; ++v) s[v] = lim_half_slope_flat<TF>(lim, limk, q0[v] - qm[v], qp[v] - q0[v], halpha, flat);
     };
     // z-face between planes k (lower) and k+1.  A single-material face gets
     // its HLLC flux in F and slot -1; an interface face returns the queue
@@ -209,16 +211,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             TF Fr[5];
             // face frame: normal w, tangential u, v
             if constexpr (EG) {
-                geos_flux<FS>(sEos[xl], flux, ql[0] + 0.5 * sl[0], ql[3] + 0.5 * sl[3], ql[1] + 0.5 * sl[1],
-                          ql[2] + 0.5 * sl[2], ql[4] + 0.5 * sl[4], qu[0] - 0.5 * su[0], qu[3] - 0.5 * su[3],
-                          qu[1] - 0.5 * su[1], qu[2] - 0.5 * su[2], qu[4] - 0.5 * su[4], Fr);
+                geos_flux<FS>(sEos[xl], flux, ql[0] + sl[0], ql[3] + sl[3], ql[1] + sl[1], ql[2] + sl[2],
+                          ql[4] + sl[4], qu[0] - su[0], qu[3] - su[3], qu[1] - su[1], qu[2] - su[2], qu[4] - su[4],
+                          Fr);
             } else {
                 const TF g = TF(mat(xl, MAT_GAMMA)), pc = TF(mat(xl, MAT_PC)), gpc = TF(mat(xl, MAT_GPC)),
                          igm1 = TF(mat(xl, MAT_IGM1));
-                num_flux<TF>(flux, ql[0] + TF(0.5) * sl[0], ql[3] + TF(0.5) * sl[3], ql[1] + TF(0.5) * sl[1],
-                             ql[2] + TF(0.5) * sl[2], ql[4] + TF(0.5) * sl[4], qu[0] - TF(0.5) * su[0],
-                             qu[3] - TF(0.5) * su[3], qu[1] - TF(0.5) * su[1], qu[2] - TF(0.5) * su[2],
-                             qu[4] - TF(0.5) * su[4], g, pc, gpc, igm1, Fr);
+                num_flux<TF>(flux, ql[0] + sl[0], ql[3] + sl[3], ql[1] + sl[1], ql[2] + sl[2], ql[4] + sl[4],
+                             qu[0] - su[0], qu[3] - su[3], qu[1] - su[1], qu[2] - su[2], qu[4] - su[4], g, pc, gpc,
+                             igm1, Fr);
             }
             F[0] = Fr[0];
             F[3] = Fr[1];
@@ -241,7 +242,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     TF Q0[5], Q1[5], Q2[5];           // primitives at k, k+1, k+2
     double PH[5];                     // phi at k-2 .. k+2
     uint8_t X0, X1, X2;               // ids at k .. k+2
-    TF S0[5];                         // z-slope of plane k
+    TF S0[5];                         // half z-slope of plane k
     TF Fzlo[5];                       // single-material flux through the lower z-face of plane k
     int qzlo = -1;                    // or the queue slot of that face's FIVER fluxes
     {
@@ -350,26 +351,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     };
     if (PF) halo_load(kz0);
 
-    // In-plane face list: face t < NXF is the x-face left of tile column
-    // t % (TX+1) in row t / (TX+1); the others are y-faces below row
-    // (t - NXF) / TX.  Per round: LDS offset of the lower cell << 2 | x-face
-    // << 1 | face inside the grid.
-    constexpr int FR = (NF + NT - 1) / NT;
+    // In-plane face list: slot t < NXF is the x-face left of tile column
+    // t % (TX+1) in row t / (TX+1); slot t in [YB, YB + NYF) is the y-face
+    // below row (t - YB) / TX.  YB is NXF rounded up to whole wavefronts, so
+    // that each wavefront holds faces of one axis and runs that axis's code
+    // path, whose LDS strides and component order are compile-time
+    // constants.  Per round: LDS offset of the lower cell << 1 | face inside
+    // the grid.
+    constexpr int YB = (NXF + 63) / 64 * 64, NFL = YB + NYF;
+    constexpr int FR = (NFL + NT - 1) / NT;
     static_assert(FR <= 3, "at most three rounds of in-plane faces");
     int fdesc[FR];
 #pragma unroll
     for (int rr = 0; rr < FR; ++rr) {
         const int t = tid + rr * NT;
         fdesc[rr] = 0;
-        if (t < NF) {
-            const bool isx = t < NXF;
-            const int tt = isx ? t : t - NXF;
+        const bool isx = t < NXF, isy = t >= YB && t < NFL;
+        if (isx || isy) {
+            const int tt = isx ? t : t - YB;
             const int W_ = isx ? TX + 1 : TX;
             const int fa = tt % W_, fb = tt / W_;
             const int oA = isx ? (fb + 2) * LX + (fa + 1) : (fb + 1) * LX + (fa + 2);
             const int gx = i0 + fa, gy = j0 + fb;
             const bool valid = isx ? (xact && gx <= nx && gy < ny) : (yact && gx < nx && gy <= ny);
-            fdesc[rr] = (oA << 2) | (isx ? 2 : 0) | (valid ? 1 : 0);
+            fdesc[rr] = (oA << 1) | (valid ? 1 : 0);
         }
     }
 
@@ -429,32 +434,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         if (EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         __syncthreads();
 
-        // (3) x- and y-faces of the tile as one work list, one code path (the
-        // list decomposition is the same for every plane, see fdesc)
-#pragma unroll 1
-        for (int rr = 0; rr < FR; ++rr) {
-            const int t = tid + rr * NT;
-            const int fd = rr == 0 ? fdesc[0] : (rr == 1 ? fdesc[1 % FR] : fdesc[2 % FR]);
-            const int oA = fd >> 2;
-            if (!(fd & 1)) continue;
-            const bool isx = fd & 2;
-            const int step = isx ? 1 : LX;
+        // (3) x- and y-faces of the tile as one work list (the list
+        // decomposition is the same for every plane, see fdesc).  One face:
+        // axis ISX, list slot t, LDS offset oA of its lower cell; its fluxes
+        // go to face index f of sF / sS (x-faces first, then y-faces).
+        auto face = [&](auto axis_tag, const int t, const int oA) {
+            constexpr bool ISX = decltype(axis_tag)::value;
+            constexpr int step = ISX ? 1 : LX;
+            constexpr int nrm = ISX ? 1 : 2, ta = ISX ? 2 : 3, tb = ISX ? 3 : 1;
+            const int tt = ISX ? t : t - YB;
+            const int f = ISX ? t : NXF + tt;
             const int oB = oA + step;
-            const int nrm = isx ? 1 : 2, ta = isx ? 2 : 3, tb = isx ? 3 : 1;
             const uint8_t xa = sX[oA], xb = sX[oB];
             if (xa == xb) {
                 const bool flatA = sX[oA - step] != xa || sX[oB] != xa;
                 const bool flatB = sX[oA] != xb || sX[oB + step] != xb;
                 TF qa[5], qb[5];
-                const int comp[5] = {0, nrm, ta, tb, 4};
+                constexpr int comp[5] = {0, nrm, ta, tb, 4};
 #pragma unroll
                 for (int v = 0; v < 5; ++v) {
                     const TF* s = sQ + comp[v] * PL;
                     const TF m1 = s[oA - step], a0 = s[oA], b0 = s[oB], p1 = s[oB + step];
-                    const TF sa = lim_slope_flat<TF>(lim, limk, a0 - m1, b0 - a0, alpha, flatA);
-                    const TF sb = lim_slope_flat<TF>(lim, limk, b0 - a0, p1 - b0, alpha, flatB);
-                    qa[v] = a0 + TF(0.5) * sa;
-                    qb[v] = b0 - TF(0.5) * sb;
+                    qa[v] = a0 + lim_half_slope_flat<TF>(lim, limk, a0 - m1, b0 - a0, halpha, flatA);
+                    qb[v] = b0 - lim_half_slope_flat<TF>(lim, limk, b0 - a0, p1 - b0, halpha, flatB);
                 }
                 TF Fr[5];
                 if constexpr (EG)
@@ -463,30 +465,39 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     num_flux<TF>(flux, qa[0], qa[1], qa[2], qa[3], qa[4], qb[0], qb[1], qb[2], qb[3], qb[4],
                                  TF(mat(xa, MAT_GAMMA)), TF(mat(xa, MAT_PC)), TF(mat(xa, MAT_GPC)), TF(mat(xa, MAT_IGM1)),
                                  Fr);
-                sF[t] = Fr[0];
-                sF[nrm * NF + t] = Fr[1];
-                sF[ta * NF + t] = Fr[2];
-                sF[tb * NF + t] = Fr[3];
-                sF[4 * NF + t] = Fr[4];
-                sS[t] = -1;
+                sF[f] = Fr[0];
+                sF[nrm * NF + f] = Fr[1];
+                sF[ta * NF + f] = Fr[2];
+                sF[tb * NF + f] = Fr[3];
+                sF[4 * NF + f] = Fr[4];
+                sS[f] = -1;
             } else {
                 bool m;
-                const int tt = isx ? t : t - NXF;
-                const int W_ = isx ? TX + 1 : TX;
+                constexpr int W_ = ISX ? TX + 1 : TX;
                 const int gx = i0 + tt % W_, gy = j0 + tt / W_;   // x: face left of cell gx; y: below gy
                 uint32_t lower;
-                if (isx) {
+                if constexpr (ISX) {
                     const int lx = bc_index(gx - 1, nx, G.bc[0], G.bc[1], m);
                     lower = lx + (uint32_t)nx * gy;
                 } else {
                     const int ly = bc_index(gy - 1, ny, G.bc[2], G.bc[3], m);
                     lower = gx + (uint32_t)nx * ly;
                 }
-                const uint32_t fid = 3 * (lower + sxy * k) + (isx ? 0 : 1);
+                const uint32_t fid = 3 * (lower + sxy * k) + (ISX ? 0 : 1);
                 const int q = a.fslot[fid];
                 if (q < 0) report_error(&sc->err, &sc->err_cell, ST_NONPHYSICAL, fid / 3);
-                sS[t] = q < 0 ? 0 : q;
+                sS[f] = q < 0 ? 0 : q;
             }
+        };
+#pragma unroll 1
+        for (int rr = 0; rr < FR; ++rr) {
+            const int t = tid + rr * NT;
+            const int fd = rr == 0 ? fdesc[0] : (rr == 1 ? fdesc[1 % FR] : fdesc[2 % FR]);
+            // the wavefront's first slot decides its axis (uniform across it)
+            const int wt = __builtin_amdgcn_readfirstlane((tid & ~63) + rr * NT);
+            if (!(fd & 1)) continue;
+            if (wt < YB) face(std::integral_constant<bool, true>(), t, fd >> 1);
+            else face(std::integral_constant<bool, false>(), t, fd >> 1);
         }
 
         // (4) z-face above plane k for this column

@@ -105,11 +105,11 @@ def test_mixed_stage_kernels_keep_three_waves_without_spills(stage_resources):
 
 
 def test_general_eos_stage_kernels_fit_two_waves_without_spills(stage_eos_resources):
-    """The general-EOS stage kernels on the 16x16 tile (the default scheme
+    """The general-EOS stage kernels on the 16x15 tile (the default scheme
     for each of the six sets of one or two families, and the run-time
     options): no scratch and two waves per SIMD for every stage kind (holding
     W^n across the plane iteration pushed kinds 2 and 3 to one wave)."""
-    ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi16E" in n}
+    ks = {n: r for n, r in stage_eos_resources.items() if "k_stage" in n and "Li16ELi15E" in n}
     assert len(ks) == 4 * (6 + 1), sorted(ks)   # 4 stage kinds x (6 family sets + run-time options)
     for n, r in ks.items():
         assert r["scratch"] == 0, (n, r)

@@ -133,7 +133,7 @@ def test_eos_every_family_pair_3d_matches_oracle(m2c, name):
     p = W.eos_charge(9, n=(10, 9, 8), steps=3, inner=inner, outer=outer, p_inner=p_in, rho_inner=rho_in,
                      rho_outer=rho_out, p_outer=p_out)
     g, o = _run(m2c, p, 3)
-    assert g.tile()[:2] == (16, 16)
+    assert g.tile()[:2] == (16, 15)
     assert o.stats()["iface_faces_last"] > 50
 
 
@@ -156,7 +156,7 @@ def test_eos_autotune_restores_state(m2c):
     g = m2c.Sim(m2c.config_for(p), p.prim)
     tile, ms = g.autotune(2)
     print("tile", tile, "ms", ms, flush=True)
-    assert tile[:2] == (16, 16)
+    assert tile[:2] == (16, 15)
     o = oracle.OracleSim(p)
     assert g.step(4) == 0 and o.step(4) == 0
     e = compare_runs(g, o, p)

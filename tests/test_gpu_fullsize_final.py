@@ -232,7 +232,7 @@ def test_eos_charge_multi_tile(m2c, case):
     _say(case, p.n, "steps", p.steps)
     o = oracle.OracleSim(p)
     g = m2c.Sim(m2c.config_for(p), p.prim)
-    assert g.tile()[:2] == (16, 16)
+    assert g.tile()[:2] == (16, 15)
     assert o.step(p.steps) == 0
     assert g.step(p.steps) == 0
     e = compare_runs(g, o, p)
