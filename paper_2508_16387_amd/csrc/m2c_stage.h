@@ -336,8 +336,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             hmir |= ((my && yact) ? 2u : 0u) << (2 * q);
         }
     }
-    double hw[HPT][6];
-    uint8_t hx[HPT];
+    double hw[HPT][6] = {};
+    uint8_t hx[HPT] = {};
     auto halo_load = [&](int k) {
 #pragma unroll
         for (int q = 0; q < HPT; ++q) {
@@ -349,7 +349,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             }
         }
     };
+    // Consume the prefetched raw halo (the empty asm): a use after this
+    // point never waits on the vector-memory counter, which counts stores as
+    // well as loads in issue order, so placing this before a plane's stores
+    // keeps the staging of the next plane from waiting for them.
+    auto halo_consume = [&]() {
+#pragma unroll
+        for (int q = 0; q < HPT; ++q) {
+            uint32_t x = hx[q];
+            asm volatile("" : "+v"(hw[q][0]), "+v"(hw[q][1]), "+v"(hw[q][2]), "+v"(hw[q][3]), "+v"(hw[q][4]),
+                         "+v"(hw[q][5]), "+v"(x));
+            hx[q] = (uint8_t)x;
+        }
+    };
+    // Single-grid default kernels (FP64): the halo of the next plane is
+    // loaded right after this plane's halo is staged and consumed after the
+    // face work, before this plane's stores; the batched and option kernels,
+    // whose register budget this would exceed, load it after the face work.
+    constexpr bool EARLY_HALO = PF && LM && !OPTS;
     if (PF) halo_load(kz0);
+    if (EARLY_HALO) halo_consume();
 
     // In-plane face list: slot t < NXF is the x-face left of tile column
     // t % (TX+1) in row t / (TX+1); slot t in [YB, YB + NYF) is the y-face
@@ -383,11 +402,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         TF* const sQ = sQ2[buf];
         double* const sPhi = sPhi2[buf];
         uint8_t* const sX = sX2[buf];
-        // lead load of plane k+3 (consumed at the end of the iteration)
+        // lead load of plane k+3 (turned into primitives before this
+        // plane's stores, see below)
         double Wn[6];
-        uint8_t Xn = 0;
-        bool mzn = false;
-        if (zact) load_raw(k + 3, Wn, Xn, mzn);
+        uint8_t Xn;
+        bool mzn;
+        if (zact) {
+            load_raw(k + 3, Wn, Xn, mzn);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 6; ++v) Wn[v] = 1.0;
+            Xn = 0;
+            mzn = false;
+        }
         // stage 2: the step-start state of the cell, fetched early
         constexpr bool W0E = BLEND && sizeof(TF) == sizeof(double) && !EG && !OPTS;
         double w0[6];
@@ -428,9 +455,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         }
         // halo of the next plane: its registers are free once this plane's
         // halo is staged, and the face work below covers the load latency
-        // (the batched and option kernels, whose register budget this would
-        // exceed, load it after the face work)
-        constexpr bool EARLY_HALO = PF && LM && !OPTS;
         if (EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         __syncthreads();
 
@@ -509,6 +533,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         }
         __syncthreads();
         if (PF && !EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
+        // the lead-loaded plane is consumed here, before this plane's stores,
+        // on every path: the vector-memory counter counts stores as well as
+        // loads, in issue order, so a use of the lead load after the stores
+        // (or a path on which the compiler cannot see it consumed) would wait
+        // for the stores to complete.  Without a z-axis the values are unused.
+        TF Qn[5];
+        to_prim(Wn, Xn, mzn, Qn);
+        double phn = Wn[5];
+        uint32_t xnv = Xn;
+        asm volatile("" : "+v"(phn), "+v"(xnv));
+        if (EARLY_HALO && k + 1 < kz1) halo_consume();
 
         // (5) residual and stage update of cell (gi, gj, k)
         if (inside) {
@@ -650,8 +685,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 
         // (6) advance the column window
         if (zact) {
-            TF Qn[5];
-            to_prim(Wn, Xn, mzn, Qn);
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 Q0[v] = Q1[v];
@@ -665,10 +698,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             PH[1] = PH[2];
             PH[2] = PH[3];
             PH[3] = PH[4];
-            PH[4] = Wn[5];
+            PH[4] = phn;
             X0 = X1;
             X1 = X2;
-            X2 = Xn;
+            X2 = (uint8_t)xnv;
         }
         // no barrier here: the next plane is staged in the other buffer, and
         // its first barrier orders this plane's reads before any reuse
