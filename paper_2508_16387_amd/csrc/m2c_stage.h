@@ -69,15 +69,15 @@ constexpr int stage_threads(int tx, int ty) { return (tx * ty + 63) / 64 * 64; }
 
 // One tile (TX x TY columns, a.kz planes) of one stage.  Called once per
 // block by the single-grid kernel and once per work item by the persistent
-// batched kernel; the whole block takes part.  LM: material parameters from
-// an LDS table (see below).  OPTS: limiter, flux and level-set band as
+// batched kernel; the whole block takes part.  SG: the single-grid kernel
+// (material table in LDS for FP64, halo prefetched one plane ahead).  OPTS: limiter, flux and level-set band as
 // configured (Van Albada, local Lax-Friedrichs, narrow band); otherwise MC,
 // HLLC and the whole grid, fixed at compile time so that the default kernels
 // carry neither the code nor the registers of the other options.  EG: a
 // general EOS per material; FS: the set of the two materials' families (bit
 // mask, eos::fam_set), so that the kernel carries only their code
 // (eos::FAM_ALL: dispatched on the materials' tags at run time).
-template <int STAGE, int TX, int TY, typename TF, bool LM, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
+template <int STAGE, int TX, int TY, typename TF, bool SG, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
 __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
 {
     // Stage kinds: 1 first stage of RK2 / RK3 (W_out = W_in + dt R); 2 last
@@ -101,12 +101,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     __shared__ int sS[NF];                 // queue slot of an interface face, else -1
     __shared__ double sRed[NT / 64];
     __shared__ int sErr;
-    // LM: material parameters indexed by material id, so that a per-lane
+    // LMAT: material parameters indexed by material id, so that a per-lane
     // id costs one LDS read per parameter instead of a select between two
     // scalar register pairs.  Measured faster for the single-grid FP64
     // kernel; the mixed form and the batched kernel (whose register budget
     // it would exceed) keep the selects.
-    constexpr bool LMAT = LM && !EG;
+    constexpr bool LMAT = SG && !EG && sizeof(TF) == sizeof(double);
     __shared__ double sMat[2][MAT_FIELDS];
     // EG: general EOS of the two materials (FP64 form only)
     static_assert(!EG || sizeof(TF) == sizeof(double), "general EOS runs in FP64");
@@ -310,10 +310,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             lj = r < 2 ? r : TY + r;
         }
     };
-    // FP64 form: the halo of the next plane is prefetched into registers;
-    // the mixed form keeps its register budget for four waves per SIMD and
-    // loads the halo when it stages the plane.
-    constexpr bool PF = sizeof(TF) == sizeof(double);
+    // The halo of the next plane is prefetched into registers (FP64, and
+    // the single-grid mixed form); the batched mixed form keeps its register
+    // budget for three waves per SIMD and loads the halo when it stages the
+    // plane.
+    constexpr bool PF = SG || sizeof(TF) == sizeof(double);
     // plane-independent part of the halo elements of this thread: LDS
     // offset (-1: none), source column in the xy-plane, wall-image flags
     int hofs[HPT];
@@ -366,7 +367,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // loaded right after this plane's halo is staged and consumed after the
     // face work, before this plane's stores; the batched and option kernels,
     // whose register budget this would exceed, load it after the face work.
-    constexpr bool EARLY_HALO = PF && LM && !OPTS;
+    constexpr bool EARLY_HALO = PF && SG && !OPTS;
     if (PF) halo_load(kz0);
     if (EARLY_HALO) halo_consume();
 
@@ -565,15 +566,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                     lo[v] = (double)flo[v * stride];
                     hi[v] = (double)fhi[v * stride];
                 }
+                // (the empty asm takes the wait for these loads inside the
+                // branch, so wavefronts without an interface face do not wait
+                // on the vector-memory counter here)
                 if (qlo >= 0) {
                     const double* f = a.fluxF + 10 * (long long)qlo + 5;
 #pragma unroll
                     for (int v = 0; v < 5; ++v) lo[v] = f[v];
+                    asm volatile("" : "+v"(lo[0]), "+v"(lo[1]), "+v"(lo[2]), "+v"(lo[3]), "+v"(lo[4]));
                 }
                 if (qhi >= 0) {
                     const double* f = a.fluxF + 10 * (long long)qhi;
 #pragma unroll
                     for (int v = 0; v < 5; ++v) hi[v] = f[v];
+                    asm volatile("" : "+v"(hi[0]), "+v"(hi[1]), "+v"(hi[2]), "+v"(hi[3]), "+v"(hi[4]));
                 }
 #pragma unroll
                 for (int v = 0; v < 5; ++v) acc[v] += (hi[v] - lo[v]) * rh;
@@ -736,7 +742,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk)
 template <int STAGE, int TX, int TY, typename TF, bool OPTS, bool EG = false, int FS = eos::FAM_ALL>
 __global__ M2C_STAGE_BOUNDS(TX, TY, TF) void k_stage(const StageArgs a)
 {
-    stage_tile<STAGE, TX, TY, TF, sizeof(TF) == sizeof(double), OPTS, EG, FS>(a, xcd_tile(blockIdx.x, gridDim.x));
+    stage_tile<STAGE, TX, TY, TF, true, OPTS, EG, FS>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Launch of the single-grid kernel of one stage kind over the whole grid.
