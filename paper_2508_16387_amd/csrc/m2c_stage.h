@@ -368,6 +368,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // face work, before this plane's stores; the batched and option kernels,
     // whose register budget this would exceed, load it after the face work.
     constexpr bool EARLY_HALO = PF && SG && !OPTS;
+    // stage-input state of the cell fetched at the top of the plane (forms
+    // that do not rebuild it from the primitives)
+    constexpr bool WIE = SG && !OPTS && (EG || sizeof(TF) != sizeof(double));
+    double wie[5] = {};
+    // blended stages: the step-start state of the cell, fetched likewise
+    constexpr bool W0E = BLEND && SG && !OPTS;
+    double w0[6] = {};
     if (PF) halo_load(kz0);
     if (EARLY_HALO) halo_consume();
 
@@ -417,12 +424,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             mzn = false;
         }
         // stage 2: the step-start state of the cell, fetched early
-        constexpr bool W0E = BLEND && sizeof(TF) == sizeof(double) && !EG && !OPTS;
-        double w0[6];
         if (W0E && inside) {
             const uint32_t c0 = col + sxy * k;
 #pragma unroll
             for (int v = 0; v < 6; ++v) w0[v] = ldf(a.W0 + v * N, c0);
+        }
+        // forms that re-read the stage-input state of the cell (mixed,
+        // general EOS): the single-grid default kernels fetch it here, so
+        // that the face work covers the load
+        if (WIE && inside) {
+            const uint32_t c0 = col + sxy * k;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) wie[v] = ldf(Win + v * N, c0);
         }
 
         // (1) own plane-k values into the LDS tile
@@ -545,6 +558,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         uint32_t xnv = Xn;
         asm volatile("" : "+v"(phn), "+v"(xnv));
         if (EARLY_HALO && k + 1 < kz1) halo_consume();
+        if (WIE) asm volatile("" : "+v"(wie[0]), "+v"(wie[1]), "+v"(wie[2]), "+v"(wie[3]), "+v"(wie[4]));
+        if (W0E)
+            asm volatile("" : "+v"(w0[0]), "+v"(w0[1]), "+v"(w0[2]), "+v"(w0[3]), "+v"(w0[4]), "+v"(w0[5]));
 
         // (5) residual and stage update of cell (gi, gj, k)
         if (inside) {
@@ -620,6 +636,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 wi[2] = r * Q0[2];
                 wi[3] = r * Q0[3];
                 wi[4] = eos_energy<double>(r, Q0[1], Q0[2], Q0[3], Q0[4], mat(X0, MAT_GPC), mat(X0, MAT_IGM1));
+            } else if constexpr (WIE) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) wi[v] = wie[v];
             } else {
 #pragma unroll
                 for (int v = 0; v < 5; ++v) wi[v] = ldf(Win + v * N, c);
