@@ -311,10 +311,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         }
     };
     // The halo of the next plane is prefetched into registers (FP64, and
-    // the single-grid mixed form); the batched mixed form keeps its register
-    // budget for three waves per SIMD and loads the halo when it stages the
-    // plane.
-    constexpr bool PF = SG || sizeof(TF) == sizeof(double);
+    // the single-grid mixed form on tiles with one halo cell per thread);
+    // the batched mixed form keeps its register budget for three waves per
+    // SIMD and loads the halo when it stages the plane.
+    constexpr bool PF = sizeof(TF) == sizeof(double) || (SG && HPT == 1);
     // plane-independent part of the halo elements of this thread: LDS
     // offset (-1: none), source column in the xy-plane, wall-image flags
     int hofs[HPT];
@@ -363,17 +363,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             hx[q] = (uint8_t)x;
         }
     };
-    // Single-grid default kernels (FP64): the halo of the next plane is
+    // Tiles with one halo cell per thread: the halo of the next plane is
     // loaded right after this plane's halo is staged and consumed after the
-    // face work, before this plane's stores; the batched and option kernels,
-    // whose register budget this would exceed, load it after the face work.
-    constexpr bool EARLY_HALO = PF && SG && !OPTS;
+    // face work, before this plane's stores; the 64x2 tile (three per
+    // thread), whose register budget this would exceed, loads it after the
+    // face work.
+    constexpr bool EARLY_HALO = PF && HPT == 1;
     // stage-input state of the cell fetched at the top of the plane (forms
     // that do not rebuild it from the primitives)
-    constexpr bool WIE = SG && !OPTS && (EG || sizeof(TF) != sizeof(double));
+    constexpr bool WIE = HPT == 1 && (EG || sizeof(TF) != sizeof(double));
     double wie[5] = {};
     // blended stages: the step-start state of the cell, fetched likewise
-    constexpr bool W0E = BLEND && SG && !OPTS;
+    constexpr bool W0E = BLEND && ((HPT == 1 && (SG || sizeof(TF) == sizeof(double))) ||
+                                   (sizeof(TF) == sizeof(double) && !EG && !OPTS));
     double w0[6] = {};
     if (PF) halo_load(kz0);
     if (EARLY_HALO) halo_consume();
