@@ -529,15 +529,21 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
                 sS[f] = q < 0 ? 0 : q;
             }
         };
+        if constexpr (YB == NT && FR == 2 && sizeof(TF) == sizeof(double) && !EG) {
+            // the first round holds every x-face and the second every y-face
+            if (fdesc[0] & 1) face(std::integral_constant<bool, true>(), tid, fdesc[0] >> 1);
+            if (fdesc[FR - 1] & 1) face(std::integral_constant<bool, false>(), tid + NT, fdesc[FR - 1] >> 1);
+        } else {
 #pragma unroll 1
-        for (int rr = 0; rr < FR; ++rr) {
-            const int t = tid + rr * NT;
-            const int fd = rr == 0 ? fdesc[0] : (rr == 1 ? fdesc[1 % FR] : fdesc[2 % FR]);
-            // the wavefront's first slot decides its axis (uniform across it)
-            const int wt = __builtin_amdgcn_readfirstlane((tid & ~63) + rr * NT);
-            if (!(fd & 1)) continue;
-            if (wt < YB) face(std::integral_constant<bool, true>(), t, fd >> 1);
-            else face(std::integral_constant<bool, false>(), t, fd >> 1);
+            for (int rr = 0; rr < FR; ++rr) {
+                const int t = tid + rr * NT;
+                const int fd = rr == 0 ? fdesc[0] : (rr == 1 ? fdesc[1 % FR] : fdesc[2 % FR]);
+                // the wavefront's first slot decides its axis (uniform across it)
+                const int wt = __builtin_amdgcn_readfirstlane((tid & ~63) + rr * NT);
+                if (!(fd & 1)) continue;
+                if (wt < YB) face(std::integral_constant<bool, true>(), t, fd >> 1);
+                else face(std::integral_constant<bool, false>(), t, fd >> 1);
+            }
         }
 
         // (4) z-face above plane k for this column
