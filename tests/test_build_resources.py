@@ -52,7 +52,7 @@ def all_resources(tmp_path_factory):
     d = tmp_path_factory.mktemp("res")
     procs = {}
     for src in SOURCES:
-        procs[src] = subprocess.Popen([HIPCC, *B.FLAGS, "-c", os.path.join(B.CSRC, src), "-o", str(d / (src + ".o")),
+        procs[src] = subprocess.Popen([HIPCC, *B.flags_for(src), "-c", os.path.join(B.CSRC, src), "-o", str(d / (src + ".o")),
                                        "-Rpass-analysis=kernel-resource-usage"],
                                       stdout=subprocess.DEVNULL, stderr=subprocess.PIPE, text=True)
     out = {}
