@@ -29,7 +29,8 @@ FLAGS = [
 # scheduled for instruction-level parallelism: at their two (FP64) or three
 # (mixed) waves per SIMD the extra registers cost no occupancy, and the
 # 384^3 stage launch measured 2.68 -> 2.64 ms.  The general-EOS kernels keep
-# the default scheduler (with it, some dropped to one wave per SIMD).
+# the default scheduler: with it some dropped to one wave per SIMD, and held
+# to two waves they measured slower (128^3 charge 230 -> 241 us).
 EXTRA_FLAGS = {
     "k_stage.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
     "k_stage_opts.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
