@@ -240,28 +240,44 @@ __device__ __forceinline__ void llf(T rL, T uL, T aL, T bL, T pL, T rR, T uR, T 
 // ------------------------------------------------------- general EOS -----
 // A material with a general EOS (section "Equations of state": NASG,
 // Mie-Grueneisen, JWL; FP64 only).  Conservative -> primitive: returns p.
-// The NASG forms are written out here with the refined reciprocal (the
-// common case of liquids and gases, and the one whose IEEE divisions would
-// dominate); the other families take the general functions.
+// The NASG and JWL forms are written out here with the refined reciprocal
+// and the density the caller already has (r = 1/vi), so that neither takes
+// an IEEE division (the liquids, gases and detonation products of the
+// common cases); Mie-Grueneisen takes the general functions.
 // S: the set of families the material may have (bit mask, eos::fam_set);
 // a kernel compiled for the families of its two materials carries only
 // their code, eos::FAM_ALL dispatches on the tag at run time.
 template <int S = eos::FAM_ALL>
-__device__ __forceinline__ double geos_p(const eos::EosK& m, double vi, double e)
+__device__ __forceinline__ double geos_p(const eos::EosK& m, double r, double vi, double e)
 {
     if (eos::fam_of<S>(m) == M2C_EOS_NASG) return (e - m.k[3]) * rcp_nr((vi - m.k[2]) * m.k[4]) - m.k[5];
+    if (eos::fam_of<S>(m) == M2C_EOS_JWL) {
+        double T, dT;
+        eos::jwl_terms_rho(m, vi, r, T, dT);
+        return m.k[0] * e * r + T;
+    }
     return eos::eos_p<S>(m, vi, e);
 }
 template <int S = eos::FAM_ALL>
-__device__ __forceinline__ double geos_e(const eos::EosK& m, double vi, double p)
+__device__ __forceinline__ double geos_e(const eos::EosK& m, double r, double vi, double p)
 {
     if (eos::fam_of<S>(m) == M2C_EOS_NASG) return (p + m.k[5]) * (vi - m.k[2]) * m.k[4] + m.k[3];
+    if (eos::fam_of<S>(m) == M2C_EOS_JWL) {
+        double T, dT;
+        eos::jwl_terms_rho(m, vi, r, T, dT);
+        return (p - T) * vi * m.k[7];
+    }
     return eos::eos_e<S>(m, vi, p);
 }
 template <int S = eos::FAM_ALL>
-__device__ __forceinline__ double geos_c2v(const eos::EosK& m, double vi, double p)
+__device__ __forceinline__ double geos_c2v(const eos::EosK& m, double r, double vi, double p)
 {
     if (eos::fam_of<S>(m) == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * vi * vi * rcp_nr(vi - m.k[2]);
+    if (eos::fam_of<S>(m) == M2C_EOS_JWL) {
+        double T, dT;
+        eos::jwl_terms_rho(m, vi, r, T, dT);
+        return ((1.0 + m.k[0]) * p - T) * vi + dT;
+    }
     return eos::eos_c2<S>(m, vi, p);
 }
 
@@ -274,20 +290,20 @@ __device__ __forceinline__ double geos_prim(const eos::EosK& m, double r, double
     v = my * ri;
     w = mz * ri;
     const double ke = 0.5 * (mx * u + my * v + mz * w);
-    return geos_p<S>(m, ri, (E - ke) * ri);
+    return geos_p<S>(m, r, ri, (E - ke) * ri);
 }
 
 // Total energy per unit volume of a primitive state.
 __device__ __forceinline__ double geos_energy(const eos::EosK& m, double r, double u, double v, double w, double p)
 {
-    return r * geos_e(m, rcp_nr(r), p) + 0.5 * r * (u * u + v * v + w * w);
+    return r * geos_e(m, r, rcp_nr(r), p) + 0.5 * r * (u * u + v * v + w * w);
 }
 
 // c^2 of a state (<= 0 or NaN where the EOS is not hyperbolic).
 template <int S = eos::FAM_ALL>
 __device__ __forceinline__ double geos_c2(const eos::EosK& m, double r, double p)
 {
-    return geos_c2v<S>(m, rcp_nr(r), p);
+    return geos_c2v<S>(m, r, rcp_nr(r), p);
 }
 
 // Admissible primitive state: finite, rho > 0, p above the floor, c^2 > 0.
@@ -303,9 +319,9 @@ __device__ __forceinline__ void geos_flux(const eos::EosK& m, int flux, double r
                                           double F[5])
 {
     const double riL = rcp_nr(rL), riR = rcp_nr(rR);
-    const double cL = sqrt_nr(geos_c2v<S>(m, riL, pL)), cR = sqrt_nr(geos_c2v<S>(m, riR, pR));
-    const double EL = rL * geos_e<S>(m, riL, pL) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
-    const double ER = rR * geos_e<S>(m, riR, pR) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
+    const double cL = sqrt_nr(geos_c2v<S>(m, rL, riL, pL)), cR = sqrt_nr(geos_c2v<S>(m, rR, riR, pR));
+    const double EL = rL * geos_e<S>(m, rL, riL, pL) + 0.5 * rL * (uL * uL + aL * aL + bL * bL);
+    const double ER = rR * geos_e<S>(m, rR, riR, pR) + 0.5 * rR * (uR * uR + aR * aR + bR * bR);
     if (flux == FLUX_LLF) llf_ce<double>(rL, uL, aL, bL, pL, cL, EL, rR, uR, aR, bR, pR, cR, ER, F);
     else hllc_ce<double>(rL, uL, aL, bL, pL, riL, cL, EL, rR, uR, aR, bR, pR, riR, cR, ER, F);
 }

@@ -138,15 +138,19 @@ M2C_HD inline Ref mg_ref(const EosK& m, double eta)
 }
 
 // JWL exponential terms T(rho) = sum_i A_i (1 - omega rho/(R_i rho_0))
-// exp(-R_i rho_0 v) and dT/drho.
-M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
+// exp(-R_i rho_0 v) and dT/drho, with rho = 1/v given.
+M2C_HD inline void jwl_terms_rho(const EosK& m, double v, double rho, double& T, double& dT)
 {
-    const double rho = 1.0 / v;
     const double x1 = exp(-m.k[3] * v), x2 = exp(-m.k[4] * v);
     const double a1 = 1.0 - m.k[5] * rho, a2 = 1.0 - m.k[6] * rho;
     const double v2 = v * v;
     T = m.k[1] * a1 * x1 + m.k[2] * a2 * x2;
     dT = m.k[1] * x1 * (a1 * m.k[3] * v2 - m.k[5]) + m.k[2] * x2 * (a2 * m.k[4] * v2 - m.k[6]);
+}
+
+M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
+{
+    jwl_terms_rho(m, v, 1.0 / v, T, dT);
 }
 
 // e(v, p)
