@@ -358,6 +358,7 @@ __device__ __forceinline__ void num_flux(int flux, T rL, T uL, T aL, T bL, T pL,
 // g(p) = f_L + f_R + u_R - u_L on p > p_lo = -min(pc_L, pc_R).
 struct RSide {
     double r, u, p, pc, pbar, c, A, B, mu, z, k2c, rc;
+    double ipbar, irc, sqA;       // 1/pbar, 1/(rho c), sqrt(A)
 };
 
 __device__ __forceinline__ void rside_init(RSide& s, double r, double u, double p, double g, double pc)
@@ -371,23 +372,39 @@ __device__ __forceinline__ void rside_init(RSide& s, double r, double u, double 
     s.z = (g - 1.0) / (2.0 * g);
     s.k2c = 2.0 * s.c / (g - 1.0);
     s.rc = r * s.c;
+    s.ipbar = 1.0 / s.pbar;
+    s.irc = 1.0 / s.rc;
+    s.sqA = sqrt(s.A);
+}
+
+// Reciprocal square root from the hardware estimate refined by two
+// Newton-Raphson steps (about one ulp for positive normal arguments).
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
 }
 
 // f_K(p) and f_K'(p).  Shock: (p - p_K) sqrt(A/(pbar + B)); rarefaction:
 // 2c/(gamma-1) ((pbar/pbar_K)^z - 1) with z = (gamma-1)/(2 gamma); the
-// derivative of the latter is (pbar/pbar_K)^(z-1) / (rho c).
+// derivative of the latter is (pbar/pbar_K)^(z-1) / (rho c).  Written with
+// the side's reciprocals, the refined reciprocal and reciprocal square root,
+// and the power as exp2(z log2 x): no IEEE division in the iteration.
 __device__ __forceinline__ double rside_f(const RSide& s, double p, double& df)
 {
     const double pb = p + s.pc;
     if (p > s.p) {
         const double den = pb + s.B;
-        const double q = sqrt(s.A / den);
-        df = q * (1.0 - (p - s.p) / (2.0 * den));
+        const double rs = rsqrt_nr(den);
+        const double q = s.sqA * rs;
+        df = q * (1.0 - (p - s.p) * 0.5 * rs * rs);
         return (p - s.p) * q;
     }
-    const double x = pb / s.pbar;
-    const double t = pow(x, s.z);
-    df = t / (x * s.rc);
+    const double x = pb * s.ipbar;
+    const double t = exp2(s.z * log2(x));
+    df = t * rcp_nr(x) * s.irc;
     return s.k2c * (t - 1.0);
 }
 
@@ -461,7 +478,7 @@ __device__ __forceinline__ int riemann_solve(double rL, double uL, double pL, do
             gv = rside_f(L, p, dLf) + rside_f(R, p, dRf) + du;
             dv = dLf + dRf;
         }
-        double pn = p - gv / dv;
+        double pn = p - gv * rcp_nr(dv);
         if (pn <= plo) pn = plo + 0.5 * (p - plo);
         ++it;
         conv = fabs(pn - p) <= rtol * (pn - plo);
