@@ -58,7 +58,7 @@ namespace eos {
 // Prepared constants of one material (host-computed from m2c_eos).
 //   NASG: k0 gamma, k1 p_c, k2 b, k3 e_c, k4 1/(gamma - 1), k5 gamma p_c
 //   MG:   k0 rho_0, k1 Gamma_0, k2 s, k3 e_0, k4 eta_min, k5 K_0 = rho_0 c_0^2,
-//         k6 rho_0 Gamma_0, k7 e_R(eta_min), k8 1/(rho_0 Gamma_0)
+//         k6 rho_0 Gamma_0, k7 e_R(eta_min), k8 1/(rho_0 Gamma_0), k9 1/rho_0
 //   JWL:  k0 omega, k1 A_1, k2 A_2, k3 R_1 rho_0, k4 R_2 rho_0,
 //         k5 omega/(R_1 rho_0), k6 omega/(R_2 rho_0), k7 1/omega
 //   all:  k10 smallest specific volume (b, (1 - 1/s)/rho_0 or 0), k11 floor
@@ -95,6 +95,19 @@ M2C_HD inline int fam_of(const EosK& m)
     else return m.fam;
 }
 
+// Reciprocal from the hardware estimate refined by two Newton-Raphson
+// steps: about one ulp for the positive normal arguments of the formulas
+// below, at a fraction of the IEEE division sequence (the iterations of the
+// solver evaluate the EOS many times per problem).
+M2C_HD inline double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 // Mie-Grueneisen reference curves and their eta-derivatives.
 struct Ref {
     double pR, eR, dpR, deR;
@@ -109,25 +122,25 @@ M2C_HD inline int mg_branch(const EosK& m, double eta)
 // Reference curves on a given branch (extended smoothly past its ends).
 M2C_HD inline Ref mg_ref_on(const EosK& m, double eta, int br)
 {
-    const double r0 = m.k[0], s = m.k[2], e0 = m.k[3], em = m.k[4], K0 = m.k[5];
+    const double ir0 = m.k[9], s = m.k[2], e0 = m.k[3], em = m.k[4], K0 = m.k[5];
     Ref r;
     if (br == 0) {
-        const double a = 1.0 / (1.0 - s * eta);
+        const double a = rcp(1.0 - s * eta);
         r.pR = K0 * eta * a * a;
         r.dpR = K0 * (1.0 + s * eta) * a * a * a;
-        r.eR = 0.5 * r.pR * eta / r0 + e0;
-        r.deR = 0.5 * (r.dpR * eta + r.pR) / r0;
+        r.eR = 0.5 * r.pR * eta * ir0 + e0;
+        r.deR = 0.5 * (r.dpR * eta + r.pR) * ir0;
     } else if (br == 1) {
         r.pR = K0 * eta;
         r.dpR = K0;
-        r.eR = 0.5 * K0 * eta * eta / r0 + e0;
-        r.deR = K0 * eta / r0;
+        r.eR = 0.5 * K0 * eta * eta * ir0 + e0;
+        r.deR = K0 * eta * ir0;
     } else {
         const double pmin = m.k[KFLOOR];
         r.pR = pmin;
         r.dpR = 0.0;
-        r.eR = m.k[7] + pmin / r0 * (eta - em);
-        r.deR = pmin / r0;
+        r.eR = m.k[7] + pmin * ir0 * (eta - em);
+        r.deR = pmin * ir0;
     }
     return r;
 }
@@ -150,7 +163,7 @@ M2C_HD inline void jwl_terms_rho(const EosK& m, double v, double rho, double& T,
 
 M2C_HD inline void jwl_terms(const EosK& m, double v, double& T, double& dT)
 {
-    jwl_terms_rho(m, v, 1.0 / v, T, dT);
+    jwl_terms_rho(m, v, rcp(v), T, dT);
 }
 
 // e(v, p)
@@ -171,21 +184,21 @@ M2C_HDI double eos_e(const EosK& m, double v, double p)
 template <int S = FAM_ALL>
 M2C_HDI double eos_p(const EosK& m, double v, double e)
 {
-    if (fam_of<S>(m) == M2C_EOS_NASG) return (e - m.k[3]) / ((v - m.k[2]) * m.k[4]) - m.k[5];
+    if (fam_of<S>(m) == M2C_EOS_NASG) return (e - m.k[3]) * rcp((v - m.k[2]) * m.k[4]) - m.k[5];
     if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         return r.pR + m.k[6] * (e - r.eR);
     }
     double T, dT;
     jwl_terms(m, v, T, dT);
-    return m.k[0] * e / v + T;
+    return m.k[0] * e * rcp(v) + T;
 }
 
 // c^2(v, p)
 template <int S = FAM_ALL>
 M2C_HDI double eos_c2(const EosK& m, double v, double p)
 {
-    if (fam_of<S>(m) == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v / (v - m.k[2]);
+    if (fam_of<S>(m) == M2C_EOS_NASG) return m.k[0] * (p + m.k[1]) * v * v * rcp(v - m.k[2]);
     if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
         return m.k[0] * v * v * (r.dpR - m.k[6] * r.deR + m.k[1] * p);
@@ -215,12 +228,12 @@ M2C_HDI void eos_ederiv(const EosK& m, double v, double p, double& ev, double& e
         ep = (v - m.k[2]) * m.k[4];
     } else if (fam_of<S>(m) == M2C_EOS_MG) {
         const Ref r = mg_ref(m, 1.0 - m.k[0] * v);
-        ev = r.dpR / m.k[1] - m.k[0] * r.deR;
+        ev = r.dpR * (m.k[0] * m.k[8]) - m.k[0] * r.deR;
         ep = m.k[8];
     } else {
         double T, dT;
         jwl_terms(m, v, T, dT);
-        ev = (p - T + dT / v) * m.k[7];
+        ev = (p - T + dT * rcp(v)) * m.k[7];
         ep = v * m.k[7];
     }
 }
@@ -252,18 +265,18 @@ M2C_HDI bool rk4_y(const EosK& m, const Side& K, double y, double h, double& s, 
     int br = 0;
     if (fam_of<S>(m) == M2C_EOS_MG) {
         const double rho0 = K.rho * exp(s), q0 = exp(y);
-        const double c20 = eos_c2<S>(m, 1.0 / rho0, K.fl + q0);
+        const double c20 = eos_c2<S>(m, rcp(rho0), K.fl + q0);
         if (!(c20 > 0.0)) return false;
-        const double probe = s + 0.25 * h * q0 / (rho0 * c20);
-        br = mg_branch(m, 1.0 - m.k[0] / (K.rho * exp(probe)));
+        const double probe = s + 0.25 * h * q0 * rcp(rho0 * c20);
+        br = mg_branch(m, 1.0 - m.k[0] * rcp(K.rho * exp(probe)));
     }
     for (int j = 0; j < 4; ++j) {
         const double a = j == 0 ? 0.0 : (j == 3 ? h : 0.5 * h);
         const double ss = j == 0 ? s : s + a * ks[j - 1];
         const double q = exp(y + a), rho = K.rho * exp(ss);
-        const double c2 = eos_c2_on<S>(m, 1.0 / rho, K.fl + q, br);
+        const double c2 = eos_c2_on<S>(m, rcp(rho), K.fl + q, br);
         if (!(c2 > 0.0) || !isfinite(c2)) return false;
-        ks[j] = q / (rho * c2);
+        ks[j] = q * rcp(rho * c2);
         kf[j] = ks[j] * sqrt(c2);
     }
     s += h * (ks[0] + 2.0 * ks[1] + 2.0 * ks[2] + ks[3]) * (1.0 / 6.0);
@@ -605,7 +618,7 @@ M2C_HDI bool shock(const EosK& m, Side& K, double p, Wave& w)
             continue;
         }
         if (H > 0.0) hi = v; else lo = v;
-        const double step = H / (ev + half);
+        const double step = H * rcp(ev + half);
         // a converged Newton step is taken before the bracket is consulted
         // (a step below rounding would otherwise fail the bracket test and
         // restart a bisection)
@@ -758,7 +771,7 @@ M2C_HDI int pair_solve(const EosK& mL, const EosK& mR, Pair& P, double rtol, int
         }
         const double F = wl.f + wr.f + du;
         if (F < 0.0) lo = fmax(lo, p); else hi = fmin(hi, p);
-        double pn = p - F / (wl.df + wr.df);
+        double pn = p - F * rcp(wl.df + wr.df);
         const double tol = rtol * fmin(p - L.fl, p - R.fl);
         if (fabs(pn - p) <= tol && pn > pfl) {
             p = pn;
@@ -861,6 +874,7 @@ inline bool prepare(int32_t nmat, const m2c_eos* eos, EosTable& t)
                 k[6] = a[0] * a[2];
                 k[7] = 0.5 * K0 * a[5] * a[5] / a[0] + a[4];
                 k[8] = 1.0 / (a[0] * a[2]);
+                k[9] = 1.0 / a[0];
                 k[KVMIN] = a[3] > 1.0 ? (1.0 - 1.0 / a[3]) / a[0] : 0.0;
                 k[KFLOOR] = K0 * a[5];
                 break;
