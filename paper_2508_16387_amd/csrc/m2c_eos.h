@@ -98,14 +98,19 @@ M2C_HD inline int fam_of(const EosK& m)
 // Reciprocal from the hardware estimate refined by two Newton-Raphson
 // steps: about one ulp for the positive normal arguments of the formulas
 // below, at a fraction of the IEEE division sequence (the iterations of the
-// solver evaluate the EOS many times per problem).
+// solver evaluate the EOS many times per problem).  A host compilation of
+// this header (CPU checks of the numerics) divides.
 M2C_HD inline double rcp(double x)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
     double r = __builtin_amdgcn_rcp(x);
     double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
     e = fma(-x, r, 1.0);
     return fma(r, e, r);
+#else
+    return 1.0 / x;
+#endif
 }
 
 // Mie-Grueneisen reference curves and their eta-derivatives.
