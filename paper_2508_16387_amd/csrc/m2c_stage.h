@@ -369,6 +369,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
     // thread), whose register budget this would exceed, loads it after the
     // face work.
     constexpr bool EARLY_HALO = PF && HPT == 1;
+    // wave priorities by phase of the plane (see the face work below)
+    constexpr bool PRIO = sizeof(TF) == sizeof(double) && !OPTS;
     // stage-input state of the cell fetched at the top of the plane (forms
     // that do not rebuild it from the primitives)
     constexpr bool WIE = HPT == 1 && (EG || sizeof(TF) != sizeof(double));
@@ -473,6 +475,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
         // halo is staged, and the face work below covers the load latency
         if (EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         __syncthreads();
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 
         // (3) x- and y-faces of the tile as one work list (the list
         // decomposition is the same for every plane, see fdesc).  One face:
@@ -546,6 +549,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             }
         }
 
+        // Wave priority (FP64 default-scheme kernels): the end of the face
+        // work (the z-face) at 2, the update and the staging of the next
+        // plane at 3, the in-plane face rounds at 0.  A block whose waves are
+        // finishing a plane is preferred over the other block on the CU,
+        // which is in the middle of its face rounds, so the barriers release
+        // sooner and the two blocks take turns (384^3 stage launch 2.64 ->
+        // 2.46 ms).  The mixed form (three blocks per CU) and the option
+        // kernels measured no gain or a loss at 128^3 and keep one priority.
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
         // (4) z-face above plane k for this column
         TF S1[5], Fzhi[5];
         int qzhi = -1;
@@ -554,6 +566,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs& a, const int tile)
             if (inside) qzhi = zface(k, Q0, S0, X0, Q1, S1, X1, Fzhi);
         }
         __syncthreads();
+        if constexpr (PRIO) __builtin_amdgcn_s_setprio(3);
         if (PF && !EARLY_HALO && k + 1 < kz1) halo_load(k + 1);
         // the lead-loaded plane is consumed here, before this plane's stores,
         // on every path: the vector-memory counter counts stores as well as
